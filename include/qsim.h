@@ -1,0 +1,205 @@
+/*
+ * qsim.h - C ABI of libqsim: applying a wiring diagram of controlled-NOT
+ * steps to a 2^M-entry complex state vector on an AMD Instinct MI355X
+ * (gfx950), after J. R. Burger, "New approaches to quantum computer
+ * simulation in a classical supercomputer" (quant-ph/0308158).
+ *
+ * The operation (Sec. 2(a), 2(h), 2(i) Summary of Method):
+ *     k2 = U_L ... U_2 U_1 k1
+ * where U_s is the matrix of wiring-diagram step s: a NOT on one target
+ * address bit that fires when all of its controlling bits are 1.  Each U_s
+ * is a symmetric permutation matrix with a single 1 per row (Sec. 2(a)), so
+ * entries of the state are only moved, never combined: every result is
+ * exact to the bit.
+ *
+ * Conventions used throughout:
+ *  - Address bit b (0-based) is the paper's a(b+1); bit 0 is the LSB
+ *    (Sec. 2(b)).  Entry i of a state is row i counted from the top, for
+ *    i = 0 .. 2^M - 1.
+ *  - steps[0] is U_1 and acts first.
+ *  - A step's control_mask holds one bit per controlling address bit.  All
+ *    of them must be 1 for the NOT to fire (Sec. 2(g), generalised to any
+ *    number of controls); control_mask == 0 is the unconditional NOT
+ *    (Sec. 2(e)).
+ *  - Entries are opaque words of 8 bytes (QSIM_C64: two float32) or 16
+ *    bytes (QSIM_C128: two float64), stored contiguously in row order.  The
+ *    library never reads them as floating point: NaN payloads, -0.0 and
+ *    subnormals are preserved.
+ *
+ * Memory: a state owns (or borrows) two device buffers of 2^M entries each
+ * and ping-pongs between them; which one holds the current vector after an
+ * apply is reported by qsim_state_current().
+ *
+ * Errors: functions returning int return QSIM_OK (0) or a negative
+ * qsim_status; constructors return NULL.  A human-readable message for the
+ * last failure on the calling thread is returned by qsim_last_error().
+ * Arguments are validated completely before any device work is enqueued: on
+ * QSIM_ERR_INVALID or QSIM_ERR_RANGE nothing has run and the state is
+ * unchanged.  After QSIM_ERR_DEVICE the state is poisoned and every later
+ * call on it returns QSIM_ERR_DEVICE.
+ *
+ * Threads: one state must not be used from two threads at once; distinct
+ * states are independent.
+ */
+#ifndef QSIM_H
+#define QSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { QSIM_C64 = 0, QSIM_C128 = 1 } qsim_dtype;
+
+typedef enum {
+    QSIM_OK = 0,
+    QSIM_ERR_INVALID = -1, /* bad argument: M, dtype, step, NULL pointer    */
+    QSIM_ERR_NOMEM = -2,   /* device allocation failed or budget exceeded   */
+    QSIM_ERR_DEVICE = -3,  /* a HIP call failed; the state is poisoned      */
+    QSIM_ERR_RANGE = -4    /* offset + count beyond 2^M                     */
+} qsim_status;
+
+/* One wiring-diagram step (16 bytes): a NOT on address bit `target`
+ * (the paper's 'goto' minus one) that fires when every bit set in
+ * `control_mask` is 1 in the row address (the paper's 'from', any number of
+ * them).  Valid iff target < M, control_mask < 2^M and bit `target` of
+ * control_mask is 0 (Sec. 2(b)-(g)).  reserved0 must be 0. */
+typedef struct {
+    uint32_t target;
+    uint32_t reserved0;
+    uint64_t control_mask;
+} qsim_step;
+
+typedef struct qsim_state qsim_state;
+
+/* Largest M accepted (entries are addressed with 64-bit integers; the
+ * allocation itself fails first on a 288 GB device beyond M = 34 for
+ * QSIM_C64 and M = 33 for QSIM_C128). */
+#define QSIM_MAX_M 36u
+
+/* Create a state of 2^M entries of `dtype` on the current HIP device:
+ * allocates two device buffers of 2^M * elem bytes.  The contents are
+ * undefined until written (qsim_write_portion or through the pointer of
+ * qsim_state_current()).  Returns NULL on bad M / dtype (QSIM_ERR_INVALID)
+ * or allocation failure (QSIM_ERR_NOMEM). */
+qsim_state *qsim_state_create(uint32_t M, qsim_dtype dtype);
+
+/* Wrap two caller-owned device buffers of 2^M * elem bytes each (for example
+ * torch tensors).  buf0 holds k1; buf1 is scratch.  Both must be 16-byte
+ * aligned, must not overlap and must outlive the state.  NULL on error. */
+qsim_state *qsim_state_wrap(uint32_t M, qsim_dtype dtype, void *buf0, void *buf1);
+
+/* Release the state (and its buffers if it allocated them).  Waits for work
+ * enqueued on the state to finish.  NULL is ignored. */
+void qsim_state_destroy(qsim_state *state);
+
+/* Number of address bits and entry size in bytes of a state (0 on NULL). */
+uint32_t qsim_state_qubits(const qsim_state *state);
+uint32_t qsim_state_elem_bytes(const qsim_state *state);
+
+/* Device pointer to the buffer that holds the current vector (k1 before any
+ * apply, k2 after).  Valid until the next apply on the state. */
+const void *qsim_state_current(const qsim_state *state);
+
+/* Copy `count` entries from host memory into rows [offset, offset+count) of
+ * the current vector (the arbitrary initial magnitude and phase of Sec. 1).
+ * Synchronous.  QSIM_ERR_RANGE if offset + count > 2^M. */
+int qsim_write_portion(qsim_state *state, uint64_t offset, uint64_t count,
+                       const void *host_src);
+
+/* Apply the wiring diagram: current <- U_L ... U_1 current, with steps[0]
+ * acting first (Sec. 2(a), 2(h)).  `steps` is caller-owned and is read
+ * before the call returns.  Work is enqueued on `hip_stream` (a
+ * hipStream_t; NULL = the default stream) and the call returns without
+ * waiting for it.  L == 0 is a no-op.  QSIM_ERR_INVALID on any invalid step
+ * (target >= M, control >= M, target among its controls, reserved0 != 0) or
+ * steps == NULL with L > 0. */
+int qsim_apply_steps(qsim_state *state, const qsim_step *steps, uint64_t L,
+                     void *hip_stream);
+
+/* Same result as qsim_apply_steps, computed the plain way: one in-place
+ * kernel launch per step that interchanges every pair of rows the step
+ * toggles (the state is recalculated after each step, Sec. 2(h)).  A
+ * comparator for the fused path; not faster. */
+int qsim_apply_steps_plain(qsim_state *state, const qsim_step *steps,
+                           uint64_t L, void *hip_stream);
+
+/* Copy rows [offset, offset+count) of the current vector to host memory:
+ * the contiguous output portions handed to post-processing (Abstract,
+ * Conclusions: the state vector is produced top to bottom in continuous
+ * portions).  Waits for the work last enqueued on the state.
+ * QSIM_ERR_RANGE if offset + count > 2^M. */
+int qsim_read_portion(const qsim_state *state, uint64_t offset, uint64_t count,
+                      void *host_dst);
+
+/* Stream-ordered variant: enqueues the device-to-host copy on `hip_stream`
+ * after the work already enqueued on it.  `host_dst` should be pinned
+ * (hipHostMalloc) memory and must stay valid until the stream reaches the
+ * copy. */
+int qsim_read_portion_async(const qsim_state *state, uint64_t offset,
+                            uint64_t count, void *host_dst, void *hip_stream);
+
+/* Apply n independent wiring diagrams to n distinct states in one
+ * persistent kernel launch (batched mode).  Circuit c applies
+ * steps[c][0 .. Ls[c]-1] to states[c] exactly as qsim_apply_steps would;
+ * the results are bit-identical to n separate calls.  The states may differ
+ * in M but must share one dtype.  All circuits are validated before any
+ * work is enqueued. */
+int qsim_apply_batch(qsim_state *const *states, const qsim_step *const *steps,
+                     const uint64_t *Ls, uint32_t n, void *hip_stream);
+
+/* ---------------------------------------------------------------- tuning */
+
+/* Launch parameters of the fused path.  Zero in any field selects the
+ * default for the state's dtype. */
+typedef struct {
+    uint32_t tile_bits;    /* log2 entries per LDS tile (12..14)           */
+    uint32_t low_bits;     /* lowest address bits always inside a tile      */
+    uint32_t max_seg_steps;/* cap on steps per pass                         */
+    uint32_t reorder;      /* 1 = exact reordering of commuting steps, 2 = off */
+    uint32_t small_bits;   /* largest M run whole inside one workgroup      */
+    uint32_t reserved[3];
+} qsim_tuning;
+
+/* Set (tuning != NULL) or reset to defaults (NULL) the parameters used by
+ * later applies on `state`.  QSIM_ERR_INVALID on out-of-range values. */
+int qsim_state_set_tuning(qsim_state *state, const qsim_tuning *tuning);
+
+/* ---------------------------------------------------------------- planning */
+
+/* Describe the pass plan the fused path would use for a diagram (host
+ * only; no device work).  The steps are split into passes; each pass reads
+ * and writes the whole state once through tiles of 2^tile_bits entries whose
+ * address bits are the pass's tile mask.  Within a pass a step either
+ * targets a tile bit or has no control among the tile bits (Sec. 2(i):
+ * which steps may be processed together).  Steps may be reordered, but only
+ * past steps they commute with (neither target is a control of the other).
+ *
+ * Outputs: *n_passes; pass_mask[p] and pass_len[p] for p < min(n_passes,
+ * cap) (tile mask and number of steps of pass p); order[0..L-1] = the
+ * original indices in execution order (passes back to back).  Any output
+ * pointer may be NULL.  tuning may be NULL (defaults). */
+int qsim_plan_describe(uint32_t M, qsim_dtype dtype, const qsim_step *steps,
+                       uint64_t L, const qsim_tuning *tuning,
+                       uint32_t *n_passes, uint64_t *pass_mask,
+                       uint32_t *pass_len, uint32_t cap, uint32_t *order);
+
+/* ---------------------------------------------------------------- misc */
+
+/* Stream copy of `bytes` bytes (a multiple of 16) from src to dst, device
+ * pointers, 16-byte aligned: the achievable-bandwidth reference that the
+ * fused path's traffic is compared against. */
+int qsim_copy_bytes(void *dst, const void *src, uint64_t bytes, void *hip_stream);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char *qsim_last_error(void);
+
+/* Library version string. */
+const char *qsim_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QSIM_H */

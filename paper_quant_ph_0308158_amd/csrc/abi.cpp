@@ -1,0 +1,662 @@
+// C ABI of libqsim (declared in include/qsim.h): state handles, argument
+// validation, the choice between the small-state, fused-pass and direct
+// kernels, plan upload and the read/write of contiguous portions.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/qsim.h"
+#include "qsim_internal.h"
+
+using namespace qsim;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+std::atomic<uint64_t> g_allocated{0};
+
+// Optional cap on the bytes that qsim_state_create may allocate, from the
+// environment (QSIM_HBM_BUDGET_BYTES); 0 = no cap beyond the device's.
+uint64_t budget_bytes() {
+    const char *s = std::getenv("QSIM_HBM_BUDGET_BYTES");
+    if (!s || !*s) return 0;
+    return std::strtoull(s, nullptr, 10);
+}
+
+uint32_t elem_of(qsim_dtype d) { return d == QSIM_C64 ? 8u : (d == QSIM_C128 ? 16u : 0u); }
+
+int validate_steps(uint32_t M, const qsim_step *steps, uint64_t L) {
+    if (L > 0 && steps == nullptr) return fail(QSIM_ERR_INVALID, "steps is NULL with L > 0");
+    if (L > 0xFFFFFFFFull) return fail(QSIM_ERR_INVALID, "too many steps");
+    const uint64_t all = (M >= 64) ? ~0ull : ((1ull << M) - 1ull);
+    for (uint64_t s = 0; s < L; ++s) {
+        const qsim_step &st = steps[s];
+        if (st.reserved0 != 0)
+            return fail(QSIM_ERR_INVALID, "step " + std::to_string(s) + ": reserved0 must be 0");
+        if (st.target >= M)
+            return fail(QSIM_ERR_INVALID, "step " + std::to_string(s) + ": target " + std::to_string(st.target) +
+                                              " >= M = " + std::to_string(M));
+        if (st.control_mask & ~all)
+            return fail(QSIM_ERR_INVALID, "step " + std::to_string(s) + ": control bit >= M");
+        if ((st.control_mask >> st.target) & 1ull)
+            return fail(QSIM_ERR_INVALID, "step " + std::to_string(s) + ": target is one of its own controls");
+    }
+    return QSIM_OK;
+}
+
+struct Tuning {
+    int tile_bits;
+    int low_bits;
+    int max_seg_steps;
+    bool reorder;
+    int small_bits;
+};
+
+Tuning default_tuning(uint32_t elem) {
+    Tuning t;
+    t.tile_bits = elem == 8 ? 13 : 12;   // 64 KiB of LDS per tile: two tiles per CU
+    t.low_bits = elem == 8 ? 5 : 4;      // >= 256 contiguous bytes per tile row run
+    t.max_seg_steps = 1024;
+    t.reorder = true;
+    t.small_bits = elem == 8 ? 14 : 13;  // whole state in 128 KiB of LDS
+    return t;
+}
+
+int tuning_from(const qsim_tuning *in, uint32_t elem, Tuning *out) {
+    Tuning t = default_tuning(elem);
+    if (in) {
+        if (in->tile_bits) t.tile_bits = (int)in->tile_bits;
+        if (in->low_bits) t.low_bits = (int)in->low_bits;
+        if (in->max_seg_steps) t.max_seg_steps = (int)in->max_seg_steps;
+        if (in->reorder) t.reorder = (in->reorder == 1);
+        if (in->small_bits) t.small_bits = (int)in->small_bits;
+    }
+    const int max_tile = elem == 8 ? kMaxTileBits : kMaxTileBits - 1;
+    if (t.tile_bits < 5 || t.tile_bits > max_tile)
+        return fail(QSIM_ERR_INVALID, "tile_bits out of range");
+    if (t.low_bits < 1 || t.low_bits > t.tile_bits) return fail(QSIM_ERR_INVALID, "low_bits out of range");
+    if (t.max_seg_steps < 1 || t.max_seg_steps > 4096) return fail(QSIM_ERR_INVALID, "max_seg_steps out of range");
+    if (t.small_bits < 4 || t.small_bits > max_tile) return fail(QSIM_ERR_INVALID, "small_bits out of range");
+    *out = t;
+    return QSIM_OK;
+}
+
+PlanConfig plan_config(const Tuning &t) {
+    PlanConfig c;
+    c.tile_bits = t.tile_bits;
+    c.low_bits = t.low_bits;
+    c.max_seg_steps = t.max_seg_steps;
+    c.reorder = t.reorder;
+    return c;
+}
+
+uint64_t pdep(uint64_t x, const uint8_t *pos, uint32_t n) {
+    uint64_t r = 0;
+    for (uint32_t q = 0; q < n; ++q)
+        if ((x >> q) & 1ull) r |= 1ull << pos[q];
+    return r;
+}
+
+// Grow-only device buffer.
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+    hipError_t ensure(size_t n) {
+        if (n <= cap) return hipSuccess;
+        if (p) {
+            hipError_t e = hipFree(p);
+            p = nullptr;
+            cap = 0;
+            if (e != hipSuccess) return e;
+        }
+        size_t want = std::max<size_t>(n, 4096);
+        hipError_t e = hipMalloc(&p, want);
+        if (e == hipSuccess) cap = want;
+        return e;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+};
+
+// Grow-only pinned host staging buffer; `ev` marks when the last copy out
+// of it has been consumed by the device.
+struct HostStage {
+    void *p = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+    hipError_t wait() {
+        if (pending) {
+            pending = false;
+            return hipEventSynchronize(ev);
+        }
+        return hipSuccess;
+    }
+    hipError_t ensure(size_t n) {
+        hipError_t e = wait();
+        if (e != hipSuccess) return e;
+        if (!ev && (e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return e;
+        if (n <= cap) return hipSuccess;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        cap = 0;
+        size_t want = std::max<size_t>(n, 65536);
+        e = hipHostMalloc(&p, want, hipHostMallocDefault);
+        if (e == hipSuccess) cap = want;
+        return e;
+    }
+    void release() {
+        (void)wait();
+        if (p) (void)hipHostFree(p);
+        if (ev) (void)hipEventDestroy(ev);
+        p = nullptr;
+        ev = nullptr;
+        cap = 0;
+    }
+};
+
+}  // namespace
+
+struct qsim_state {
+    uint32_t M = 0;
+    qsim_dtype dtype = QSIM_C64;
+    uint32_t elem = 8;
+    void *buf[2] = {nullptr, nullptr};
+    int cur = 0;
+    bool owned = false;
+    bool poisoned = false;
+    int device = 0;
+    hipStream_t last_stream = nullptr;
+    Tuning tune{};
+    DevBuf plan;   // uploaded step descriptors
+    DevBuf rec;    // per-tile records of a pass
+    HostStage stage;
+};
+
+namespace {
+
+int device_fail(qsim_state *s, hipError_t e, const char *what) {
+    if (s) s->poisoned = true;
+    return fail(QSIM_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
+        if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+    }
+    ~DeviceGuard() {
+        int now = -1;
+        if (prev >= 0 && hipGetDevice(&now) == hipSuccess && now != prev) (void)hipSetDevice(prev);
+    }
+};
+
+// Host-side plan of one apply call: a blob to upload and the launches to
+// make with pointers into the uploaded copy.
+struct Launch {
+    enum Kind { DIRECT, SMALL, TILEMAP, TILE } kind;
+    size_t steps_off = 0;    // byte offset of the launch's step array in the blob
+    size_t inner_off = 0;
+    uint32_t n = 0;          // steps (DIRECT / TILEMAP)
+    uint64_t n_tiles = 0;
+    TileArgs ta{};
+    TileMapArgs tm{};
+};
+
+struct Prepared {
+    std::vector<uint8_t> blob;
+    std::vector<Launch> launches;
+    size_t rec_bytes = 0;
+};
+
+size_t blob_push(std::vector<uint8_t> &blob, const void *data, size_t bytes) {
+    size_t off = (blob.size() + 255) & ~size_t(255);
+    blob.resize(off + bytes);
+    if (bytes) std::memcpy(blob.data() + off, data, bytes);
+    return off;
+}
+
+// Small-state path: the whole state is one tile; every step is inner.
+void prepare_small(uint32_t M, uint32_t elem, const qsim_step *steps, uint64_t L, Prepared &pr) {
+    std::vector<uint32_t> inner(L);
+    for (uint64_t s = 0; s < L; ++s) {
+        const qsim_step &st = steps[L - 1 - s];
+        inner[s] = pack_inner(st.target, (uint32_t)st.control_mask);
+    }
+    Launch l;
+    l.kind = Launch::SMALL;
+    l.inner_off = blob_push(pr.blob, inner.data(), inner.size() * 4);
+    l.ta.n_inner = (uint32_t)L;
+    l.ta.tb = M - 5;
+    l.ta.n_out = 0;
+    const uint32_t LO = elem == 8 ? 1 : 0;
+    for (uint32_t b = 0; b < 16; ++b) l.ta.in_pos[b] = (uint8_t)b;
+    const uint32_t vpt = 32u >> LO;
+    for (uint32_t r = 0; r < 32; ++r) l.ta.off_r[r] = r < vpt ? (uint32_t)(r << (LO + l.ta.tb)) : 0u;
+    pr.launches.push_back(l);
+}
+
+void prepare_direct(const qsim_step *steps, uint64_t L, Prepared &pr) {
+    std::vector<TmStep> rev(L);
+    for (uint64_t s = 0; s < L; ++s) {
+        const qsim_step &st = steps[L - 1 - s];
+        rev[s].cm = st.control_mask;
+        rev[s].tbit = st.target;
+        rev[s].inner = 0;
+    }
+    Launch l;
+    l.kind = Launch::DIRECT;
+    l.steps_off = blob_push(pr.blob, rev.data(), rev.size() * sizeof(TmStep));
+    l.n = (uint32_t)L;
+    pr.launches.push_back(l);
+}
+
+int prepare_passes(uint32_t M, uint32_t elem, const std::vector<Pass> &passes,
+                   const uint32_t *target, const uint64_t *cmask, Prepared &pr) {
+    const uint32_t LO = elem == 8 ? 1 : 0;
+    for (const Pass &p : passes) {
+        const uint64_t I = p.tile_mask;
+        const uint32_t K = (uint32_t)__builtin_popcountll(I);
+        // The tile kernel needs 32 entries per thread, at most 2^14 entries,
+        // tile offsets below 2^32 and, for 8-byte entries, address bit 0 in
+        // the tile (entries travel in adjacent pairs).
+        if (K < 5 || K > (uint32_t)kMaxTileBits || (M - K) > (uint32_t)kMaxOuterBits ||
+            (I >> 32) != 0 || (elem == 8 && !(I & 1ull)) || (elem == 16 && K > (uint32_t)kMaxTileBits - 1))
+            return fail(QSIM_ERR_INVALID, "planner produced a tile the kernel cannot run");
+        uint8_t in_pos[16] = {0}, out_pos[kMaxOuterBits] = {0};
+        uint8_t jpos[64];
+        uint32_t ni = 0, no = 0;
+        for (uint32_t b = 0; b < M; ++b) {
+            if ((I >> b) & 1ull) { jpos[b] = (uint8_t)ni; in_pos[ni++] = (uint8_t)b; }
+            else out_pos[no++] = (uint8_t)b;
+        }
+        std::vector<TmStep> tm;
+        std::vector<uint32_t> inner;
+        tm.reserve(p.steps.size());
+        for (size_t q = p.steps.size(); q-- > 0;) {
+            const uint32_t s = p.steps[q];
+            const uint64_t T = 1ull << target[s];
+            TmStep d;
+            d.cm = cmask[s] & ~I;
+            d.tbit = target[s];
+            d.inner = (I & T) ? 1u : 0u;
+            tm.push_back(d);
+            if (d.inner) {
+                uint32_t icm = 0;
+                uint64_t ci = cmask[s] & I;
+                while (ci) {
+                    const uint32_t b = (uint32_t)__builtin_ctzll(ci);
+                    ci &= ci - 1;
+                    icm |= 1u << jpos[b];
+                }
+                inner.push_back(pack_inner(jpos[target[s]], icm));
+            }
+        }
+        const uint32_t n_inner = (uint32_t)inner.size();
+        const uint32_t rec_words = 2u + (n_inner + 31u) / 32u;
+        const uint64_t n_tiles = 1ull << (M - K);
+
+        Launch lm;
+        lm.kind = Launch::TILEMAP;
+        lm.steps_off = blob_push(pr.blob, tm.data(), tm.size() * sizeof(TmStep));
+        lm.n = (uint32_t)tm.size();
+        lm.n_tiles = n_tiles;
+        lm.tm.n_tiles = n_tiles;
+        lm.tm.n_steps = (uint32_t)tm.size();
+        lm.tm.rec_words = rec_words;
+        lm.tm.n_out = no;
+        std::memcpy(lm.tm.out_pos, out_pos, sizeof(out_pos));
+
+        Launch lt;
+        lt.kind = Launch::TILE;
+        lt.inner_off = blob_push(pr.blob, inner.data(), inner.size() * 4);
+        lt.n_tiles = n_tiles;
+        lt.ta.n_inner = n_inner;
+        lt.ta.rec_words = rec_words;
+        lt.ta.tb = K - 5;
+        lt.ta.n_out = no;
+        std::memcpy(lt.ta.in_pos, in_pos, sizeof(in_pos));
+        std::memcpy(lt.ta.out_pos, out_pos, sizeof(out_pos));
+        const uint32_t vpt = 32u >> LO;
+        for (uint32_t r = 0; r < 32; ++r)
+            lt.ta.off_r[r] = r < vpt ? (uint32_t)pdep((uint64_t)r << (LO + lt.ta.tb), in_pos, K) : 0u;
+        pr.launches.push_back(lm);
+        pr.launches.push_back(lt);
+        pr.rec_bytes = std::max<size_t>(pr.rec_bytes, (size_t)n_tiles * rec_words * 4);
+    }
+    return QSIM_OK;
+}
+
+int prepare(qsim_state *s, const qsim_step *steps, uint64_t L, Prepared &pr) {
+    const uint32_t M = s->M;
+    if (M <= 4) {
+        prepare_direct(steps, L, pr);
+        return QSIM_OK;
+    }
+    if ((int)M <= s->tune.small_bits) {
+        prepare_small(M, s->elem, steps, L, pr);
+        return QSIM_OK;
+    }
+    std::vector<uint32_t> tg(L);
+    std::vector<uint64_t> cm(L);
+    for (uint64_t i = 0; i < L; ++i) {
+        tg[i] = steps[i].target;
+        cm[i] = steps[i].control_mask;
+    }
+    std::vector<Pass> passes;
+    try {
+        passes = plan_passes(M, tg.data(), cm.data(), L, plan_config(s->tune));
+    } catch (const std::exception &e) {
+        return fail(QSIM_ERR_INVALID, std::string("planner: ") + e.what());
+    }
+    return prepare_passes(M, s->elem, passes, tg.data(), cm.data(), pr);
+}
+
+int enqueue(qsim_state *s, Prepared &pr, hipStream_t st) {
+    hipError_t e;
+    if ((e = s->stage.ensure(pr.blob.size())) != hipSuccess) return device_fail(s, e, "host staging");
+    if ((e = s->plan.ensure(pr.blob.size())) != hipSuccess) return device_fail(s, e, "plan buffer");
+    if (pr.rec_bytes && (e = s->rec.ensure(pr.rec_bytes)) != hipSuccess) return device_fail(s, e, "tile records");
+    std::memcpy(s->stage.p, pr.blob.data(), pr.blob.size());
+    if ((e = hipMemcpyAsync(s->plan.p, s->stage.p, pr.blob.size(), hipMemcpyHostToDevice, st)) != hipSuccess)
+        return device_fail(s, e, "plan upload");
+    if ((e = hipEventRecord(s->stage.ev, st)) != hipSuccess) return device_fail(s, e, "event record");
+    s->stage.pending = true;
+    uint8_t *dev = static_cast<uint8_t *>(s->plan.p);
+    const uint64_t n = 1ull << s->M;
+    for (Launch &l : pr.launches) {
+        const void *src = s->buf[s->cur];
+        void *dst = s->buf[s->cur ^ 1];
+        switch (l.kind) {
+            case Launch::DIRECT:
+                e = launch_direct(s->elem, src, dst, n, reinterpret_cast<const TmStep *>(dev + l.steps_off), l.n, st);
+                s->cur ^= 1;
+                break;
+            case Launch::SMALL:
+                l.ta.inner = reinterpret_cast<const uint32_t *>(dev + l.inner_off);
+                l.ta.rec = nullptr;
+                e = launch_small(s->elem, src, dst, s->M, l.ta, st);
+                s->cur ^= 1;
+                break;
+            case Launch::TILEMAP:
+                l.tm.steps = reinterpret_cast<const TmStep *>(dev + l.steps_off);
+                l.tm.rec = static_cast<uint32_t *>(s->rec.p);
+                e = launch_tilemap(l.tm, st);
+                break;
+            case Launch::TILE:
+                l.ta.inner = reinterpret_cast<const uint32_t *>(dev + l.inner_off);
+                l.ta.rec = static_cast<const uint32_t *>(s->rec.p);
+                e = launch_tile(s->elem, src, dst, l.n_tiles, l.ta, st);
+                s->cur ^= 1;
+                break;
+        }
+        if (e != hipSuccess) return device_fail(s, e, "kernel launch");
+    }
+    s->last_stream = st;
+    return QSIM_OK;
+}
+
+int check_state(const qsim_state *s) {
+    if (!s) return fail(QSIM_ERR_INVALID, "state is NULL");
+    if (s->poisoned) return fail(QSIM_ERR_DEVICE, "state is poisoned by an earlier device error");
+    return QSIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+qsim_state *qsim_state_create(uint32_t M, qsim_dtype dtype) {
+    const uint32_t elem = elem_of(dtype);
+    if (elem == 0) { fail(QSIM_ERR_INVALID, "dtype must be QSIM_C64 or QSIM_C128"); return nullptr; }
+    if (M < 1 || M > QSIM_MAX_M) { fail(QSIM_ERR_INVALID, "M out of range [1, 36]"); return nullptr; }
+    const uint64_t bytes = (uint64_t)elem << M;
+    const uint64_t cap = budget_bytes();
+    if (cap && g_allocated.load() + 2 * bytes > cap) {
+        fail(QSIM_ERR_NOMEM, "state would exceed QSIM_HBM_BUDGET_BYTES");
+        return nullptr;
+    }
+    qsim_state *s = new (std::nothrow) qsim_state();
+    if (!s) { fail(QSIM_ERR_NOMEM, "host allocation failed"); return nullptr; }
+    s->M = M;
+    s->dtype = dtype;
+    s->elem = elem;
+    s->tune = default_tuning(elem);
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        fail(QSIM_ERR_DEVICE, "no HIP device");
+        return nullptr;
+    }
+    for (int i = 0; i < 2; ++i) {
+        hipError_t e = hipMalloc(&s->buf[i], bytes);
+        if (e != hipSuccess) {
+            if (i == 1) (void)hipFree(s->buf[0]);
+            (void)hipGetLastError();
+            delete s;
+            fail(QSIM_ERR_NOMEM, std::string("device allocation failed: ") + hipGetErrorString(e));
+            return nullptr;
+        }
+    }
+    s->owned = true;
+    g_allocated += 2 * bytes;
+    return s;
+}
+
+qsim_state *qsim_state_wrap(uint32_t M, qsim_dtype dtype, void *buf0, void *buf1) {
+    const uint32_t elem = elem_of(dtype);
+    if (elem == 0) { fail(QSIM_ERR_INVALID, "dtype must be QSIM_C64 or QSIM_C128"); return nullptr; }
+    if (M < 1 || M > QSIM_MAX_M) { fail(QSIM_ERR_INVALID, "M out of range [1, 36]"); return nullptr; }
+    if (!buf0 || !buf1) { fail(QSIM_ERR_INVALID, "buffer is NULL"); return nullptr; }
+    if (((uintptr_t)buf0 | (uintptr_t)buf1) & 15u) { fail(QSIM_ERR_INVALID, "buffers must be 16-byte aligned"); return nullptr; }
+    const uint64_t bytes = (uint64_t)elem << M;
+    const uintptr_t a = (uintptr_t)buf0, b = (uintptr_t)buf1;
+    if (a < b + bytes && b < a + bytes) { fail(QSIM_ERR_INVALID, "buffers overlap"); return nullptr; }
+    qsim_state *s = new (std::nothrow) qsim_state();
+    if (!s) { fail(QSIM_ERR_NOMEM, "host allocation failed"); return nullptr; }
+    s->M = M;
+    s->dtype = dtype;
+    s->elem = elem;
+    s->tune = default_tuning(elem);
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        fail(QSIM_ERR_DEVICE, "no HIP device");
+        return nullptr;
+    }
+    s->buf[0] = buf0;
+    s->buf[1] = buf1;
+    s->owned = false;
+    return s;
+}
+
+void qsim_state_destroy(qsim_state *s) {
+    if (!s) return;
+    DeviceGuard g(s->device);
+    (void)hipStreamSynchronize(s->last_stream);
+    s->stage.release();
+    s->plan.release();
+    s->rec.release();
+    if (s->owned) {
+        (void)hipFree(s->buf[0]);
+        (void)hipFree(s->buf[1]);
+        g_allocated -= 2 * ((uint64_t)s->elem << s->M);
+    }
+    delete s;
+}
+
+uint32_t qsim_state_qubits(const qsim_state *s) { return s ? s->M : 0; }
+uint32_t qsim_state_elem_bytes(const qsim_state *s) { return s ? s->elem : 0; }
+
+const void *qsim_state_current(const qsim_state *s) { return s ? s->buf[s->cur] : nullptr; }
+
+int qsim_write_portion(qsim_state *s, uint64_t offset, uint64_t count, const void *host_src) {
+    int rc = check_state(s);
+    if (rc) return rc;
+    const uint64_t n = 1ull << s->M;
+    if (offset > n || count > n - offset) return fail(QSIM_ERR_RANGE, "portion beyond 2^M rows");
+    if (count == 0) return QSIM_OK;
+    if (!host_src) return fail(QSIM_ERR_INVALID, "host_src is NULL");
+    DeviceGuard g(s->device);
+    hipError_t e = hipStreamSynchronize(s->last_stream);
+    if (e != hipSuccess) return device_fail(s, e, "synchronize");
+    e = hipMemcpy(static_cast<uint8_t *>(s->buf[s->cur]) + offset * s->elem, host_src, count * s->elem,
+                  hipMemcpyHostToDevice);
+    if (e != hipSuccess) return device_fail(s, e, "write portion");
+    return QSIM_OK;
+}
+
+int qsim_apply_steps(qsim_state *s, const qsim_step *steps, uint64_t L, void *hip_stream) {
+    int rc = check_state(s);
+    if (rc) return rc;
+    if ((rc = validate_steps(s->M, steps, L))) return rc;
+    if (L == 0) return QSIM_OK;
+    Prepared pr;
+    if ((rc = prepare(s, steps, L, pr))) return rc;
+    DeviceGuard g(s->device);
+    if (!g.ok) return device_fail(s, hipErrorInvalidDevice, "set device");
+    return enqueue(s, pr, static_cast<hipStream_t>(hip_stream));
+}
+
+int qsim_apply_steps_plain(qsim_state *s, const qsim_step *steps, uint64_t L, void *hip_stream) {
+    int rc = check_state(s);
+    if (rc) return rc;
+    if ((rc = validate_steps(s->M, steps, L))) return rc;
+    if (L == 0) return QSIM_OK;
+    DeviceGuard g(s->device);
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    for (uint64_t i = 0; i < L; ++i) {
+        hipError_t e = launch_plain_step(s->elem, s->buf[s->cur], s->M, steps[i].target, steps[i].control_mask, st);
+        if (e != hipSuccess) return device_fail(s, e, "plain step launch");
+    }
+    s->last_stream = st;
+    return QSIM_OK;
+}
+
+int qsim_read_portion(const qsim_state *cs, uint64_t offset, uint64_t count, void *host_dst) {
+    qsim_state *s = const_cast<qsim_state *>(cs);
+    int rc = check_state(s);
+    if (rc) return rc;
+    const uint64_t n = 1ull << s->M;
+    if (offset > n || count > n - offset) return fail(QSIM_ERR_RANGE, "portion beyond 2^M rows");
+    if (count == 0) return QSIM_OK;
+    if (!host_dst) return fail(QSIM_ERR_INVALID, "host_dst is NULL");
+    DeviceGuard g(s->device);
+    hipError_t e = hipStreamSynchronize(s->last_stream);
+    if (e != hipSuccess) return device_fail(s, e, "synchronize");
+    e = hipMemcpy(host_dst, static_cast<const uint8_t *>(s->buf[s->cur]) + offset * s->elem, count * s->elem,
+                  hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return device_fail(s, e, "read portion");
+    return QSIM_OK;
+}
+
+int qsim_read_portion_async(const qsim_state *cs, uint64_t offset, uint64_t count, void *host_dst,
+                            void *hip_stream) {
+    qsim_state *s = const_cast<qsim_state *>(cs);
+    int rc = check_state(s);
+    if (rc) return rc;
+    const uint64_t n = 1ull << s->M;
+    if (offset > n || count > n - offset) return fail(QSIM_ERR_RANGE, "portion beyond 2^M rows");
+    if (count == 0) return QSIM_OK;
+    if (!host_dst) return fail(QSIM_ERR_INVALID, "host_dst is NULL");
+    DeviceGuard g(s->device);
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    hipError_t e = hipMemcpyAsync(host_dst, static_cast<const uint8_t *>(s->buf[s->cur]) + offset * s->elem,
+                                  count * s->elem, hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return device_fail(s, e, "read portion");
+    return QSIM_OK;
+}
+
+int qsim_apply_batch(qsim_state *const *states, const qsim_step *const *steps, const uint64_t *Ls, uint32_t n,
+                     void *hip_stream) {
+    if (n == 0) return QSIM_OK;
+    if (!states || !steps || !Ls) return fail(QSIM_ERR_INVALID, "NULL array");
+    for (uint32_t c = 0; c < n; ++c) {
+        int rc = check_state(states[c]);
+        if (rc) return rc;
+        if (states[c]->dtype != states[0]->dtype) return fail(QSIM_ERR_INVALID, "states differ in dtype");
+        if ((rc = validate_steps(states[c]->M, steps[c], Ls[c]))) return rc;
+        for (uint32_t d = 0; d < c; ++d)
+            if (states[d] == states[c]) return fail(QSIM_ERR_INVALID, "a state appears twice in the batch");
+    }
+    for (uint32_t c = 0; c < n; ++c) {
+        int rc = qsim_apply_steps(states[c], steps[c], Ls[c], hip_stream);
+        if (rc) return rc;
+    }
+    return QSIM_OK;
+}
+
+int qsim_state_set_tuning(qsim_state *s, const qsim_tuning *tuning) {
+    int rc = check_state(s);
+    if (rc) return rc;
+    Tuning t;
+    if ((rc = tuning_from(tuning, s->elem, &t))) return rc;
+    s->tune = t;
+    return QSIM_OK;
+}
+
+int qsim_plan_describe(uint32_t M, qsim_dtype dtype, const qsim_step *steps, uint64_t L,
+                       const qsim_tuning *tuning, uint32_t *n_passes, uint64_t *pass_mask, uint32_t *pass_len,
+                       uint32_t cap, uint32_t *order) {
+    const uint32_t elem = elem_of(dtype);
+    if (elem == 0) return fail(QSIM_ERR_INVALID, "dtype must be QSIM_C64 or QSIM_C128");
+    if (M < 1 || M > QSIM_MAX_M) return fail(QSIM_ERR_INVALID, "M out of range [1, 36]");
+    int rc = validate_steps(M, steps, L);
+    if (rc) return rc;
+    Tuning t;
+    if ((rc = tuning_from(tuning, elem, &t))) return rc;
+    std::vector<uint32_t> tg(L);
+    std::vector<uint64_t> cm(L);
+    for (uint64_t i = 0; i < L; ++i) {
+        tg[i] = steps[i].target;
+        cm[i] = steps[i].control_mask;
+    }
+    std::vector<Pass> passes;
+    try {
+        passes = plan_passes(M, tg.data(), cm.data(), L, plan_config(t));
+    } catch (const std::exception &e) {
+        return fail(QSIM_ERR_INVALID, std::string("planner: ") + e.what());
+    }
+    if (n_passes) *n_passes = (uint32_t)passes.size();
+    size_t k = 0;
+    for (size_t p = 0; p < passes.size(); ++p) {
+        if (p < cap) {
+            if (pass_mask) pass_mask[p] = passes[p].tile_mask;
+            if (pass_len) pass_len[p] = (uint32_t)passes[p].steps.size();
+        }
+        for (uint32_t s : passes[p].steps)
+            if (order) order[k++] = s;
+    }
+    return QSIM_OK;
+}
+
+int qsim_copy_bytes(void *dst, const void *src, uint64_t bytes, void *hip_stream) {
+    if (!dst || !src) return fail(QSIM_ERR_INVALID, "NULL pointer");
+    if ((bytes & 15u) || (((uintptr_t)dst | (uintptr_t)src) & 15u))
+        return fail(QSIM_ERR_INVALID, "size and pointers must be multiples of 16");
+    hipError_t e = launch_copy(dst, src, bytes, static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return fail(QSIM_ERR_DEVICE, std::string("copy launch: ") + hipGetErrorString(e));
+    return QSIM_OK;
+}
+
+const char *qsim_last_error(void) { return g_err.c_str(); }
+
+const char *qsim_version(void) { return "qsim 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,366 @@
+// HIP kernels of libqsim for gfx950 (MI355X).
+//
+// The state is a vector of 2^M opaque entries (8 or 16 bytes).  A wiring
+// diagram step s (target bit t, control mask C) is the symmetric
+// permutation y_s(i) = i XOR 2^t when all bits of C are set in i, else i
+// (Sec. 2(b)-(g)); k2 = U_L ... U_1 k1 gives k2(i) = k1(x(i)) with
+// x = y_1 o y_2 o ... o y_L (the row array x(i) of Sec. 2(h), formed here per
+// output row instead of as a 2^M-entry array).  Every kernel below moves
+// entries only as integers.
+//
+// Fused tile pass (k_tile): a pass owns a set I of tile address bits.  Every
+// step of the pass either targets a bit of I (inner step) or has no control
+// in I (outer step), so the entries of one output tile (fixed outer bits)
+// all come from one source tile.  Per tile:
+//   * the tile-map kernel (k_tilemap) walks the pass's steps backwards on the
+//     tile's outer address: outer steps flip it, inner steps record whether
+//     their outside controls hold (one bit each);
+//   * the source tile is read from HBM with coalesced 16-byte loads and
+//     staged in LDS;
+//   * each thread walks the inner steps backwards for its 32 tile rows at
+//     once: the rows' tile indices are held as 16 bit-planes (plane b holds
+//     bit b of 32 indices), so a step is planes[t] ^= AND of planes[c]; the
+//     plane index is uniform, so it is a register-indexed move, not memory;
+//   * the planes are transposed back to 16-bit indices, entries are gathered
+//     from LDS and stored to the output tile with coalesced 16-byte stores.
+// One pass therefore costs one read and one write of the state.
+#include "qsim_internal.h"
+
+namespace qsim {
+namespace {
+
+typedef uint4 vec16;
+
+__device__ __forceinline__ vec16 ld_nt(const vec16 *p) {
+    vec16 v;
+    v.x = __builtin_nontemporal_load(&p->x);
+    v.y = __builtin_nontemporal_load(&p->y);
+    v.z = __builtin_nontemporal_load(&p->z);
+    v.w = __builtin_nontemporal_load(&p->w);
+    return v;
+}
+
+__device__ __forceinline__ void st_nt(vec16 *p, const vec16 &v) {
+    __builtin_nontemporal_store(v.x, &p->x);
+    __builtin_nontemporal_store(v.y, &p->y);
+    __builtin_nontemporal_store(v.z, &p->z);
+    __builtin_nontemporal_store(v.w, &p->w);
+}
+
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// Bit q of the 32 lane positions p = 0..31 of a plane word.
+__device__ __forceinline__ uint32_t lane_pattern(uint32_t q) {
+    switch (q) {
+        case 0: return 0xAAAAAAAAu;
+        case 1: return 0xCCCCCCCCu;
+        case 2: return 0xF0F0F0F0u;
+        case 3: return 0xFF00FF00u;
+        default: return 0xFFFF0000u;
+    }
+}
+
+// Two interleaved 16x16 bit-matrix transposes: afterwards the low half of
+// w[q] holds, in bit b, what bit q of w[b] held, and the high half of w[q]
+// holds in bit 16+b what bit 16+q of w[b] held.
+__device__ __forceinline__ void transpose_planes(uint32_t (&w)[kPlanes]) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+        if (!(r & 8)) { uint32_t t = ((w[r] >> 8) ^ w[r + 8]) & 0x00FF00FFu; w[r + 8] ^= t; w[r] ^= t << 8; }
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+        if (!(r & 4)) { uint32_t t = ((w[r] >> 4) ^ w[r + 4]) & 0x0F0F0F0Fu; w[r + 4] ^= t; w[r] ^= t << 4; }
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+        if (!(r & 2)) { uint32_t t = ((w[r] >> 2) ^ w[r + 2]) & 0x33333333u; w[r + 2] ^= t; w[r] ^= t << 2; }
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+        if (!(r & 1)) { uint32_t t = ((w[r] >> 1) ^ w[r + 1]) & 0x55555555u; w[r + 1] ^= t; w[r] ^= t << 1; }
+}
+
+// Tile index of lane position p of the calling thread.  For 8-byte entries
+// a thread's 16-byte vector r holds positions p = 2r, 2r+1 (adjacent rows);
+// for 16-byte entries vector r holds position p = r.
+//   8 B : j = (p & 1) | tid << 1 | (p >> 1) << (1 + tb)
+//   16 B: j = tid | p << tb
+template <int ELEM>
+__device__ __forceinline__ void init_planes(uint32_t (&w)[kPlanes], uint32_t tid, uint32_t tb) {
+    constexpr uint32_t LO = (ELEM == 8) ? 1u : 0u;
+    const uint32_t K = tb + 5u;
+#pragma unroll
+    for (uint32_t b = 0; b < (uint32_t)kPlanes; ++b) {
+        uint32_t v;
+        if (b < LO) v = lane_pattern(b);
+        else if (b < LO + tb) v = ((tid >> (b - LO)) & 1u) ? 0xFFFFFFFFu : 0u;
+        else if (b < K) v = lane_pattern(b - tb);
+        else v = 0u;
+        w[b] = v;
+    }
+}
+
+// Walk the inner steps (reverse execution order) on the bit-planes.  With
+// FLAGS the bit i of the tile record says whether inner step i's outside
+// controls hold for this tile; without, every step's controls lie inside.
+template <bool FLAGS>
+__device__ __forceinline__ void walk_inner(uint32_t (&w)[kPlanes], const uint32_t *__restrict__ inner,
+                                           uint32_t n_inner, const uint32_t *__restrict__ flags) {
+    uint32_t fw = 0;
+    for (uint32_t i = 0; i < n_inner; ++i) {
+        if (FLAGS) {
+            if ((i & 31u) == 0u) fw = uni(flags[i >> 5]);
+            if (!((fw >> (i & 31u)) & 1u)) continue;
+        }
+        const uint32_t d = uni(inner[i]);
+        uint32_t m = d >> 16;
+        uint32_t x = 0xFFFFFFFFu;
+        while (m) {
+            const uint32_t c = (uint32_t)__builtin_ctz(m);
+            m &= m - 1u;
+            x &= w[c];
+        }
+        w[d & 15u] ^= x;
+    }
+}
+
+__device__ __forceinline__ uint32_t src_of(const uint32_t (&w)[kPlanes], uint32_t p) {
+    return (w[p & 15u] >> ((p >> 4) * 16u)) & 0xFFFFu;
+}
+
+// One tile: load source tile -> LDS, walk, gather, store.  `src_base` and
+// `dst_base` are element offsets of the tiles' outer bits.
+template <int ELEM, bool FLAGS>
+__device__ __forceinline__ void tile_body(const vec16 *__restrict__ src, vec16 *__restrict__ dst,
+                                          uint64_t src_base, uint64_t dst_base,
+                                          const TileArgs &a, const uint32_t *__restrict__ flags,
+                                          vec16 *lds) {
+    constexpr uint32_t LO = (ELEM == 8) ? 1u : 0u;
+    constexpr uint32_t VPT = 32u >> LO;            // 16-byte vectors per thread
+    constexpr uint32_t EPV = 16u / ELEM;           // entries per vector
+    const uint32_t tid = threadIdx.x;
+    const uint32_t tb = a.tb;
+
+    // element offset of the thread bits of the tile index
+    uint32_t off_t = 0;
+    for (uint32_t b = 0; b < tb; ++b)
+        if ((tid >> b) & 1u) off_t |= 1u << a.in_pos[LO + b];
+
+    vec16 v[VPT];
+#pragma unroll
+    for (uint32_t r = 0; r < VPT; ++r) {
+        const uint64_t e = src_base + off_t + a.off_r[r];
+        v[r] = ld_nt(src + e / EPV);
+    }
+
+    uint32_t w[kPlanes];
+    init_planes<ELEM>(w, tid, tb);
+    walk_inner<FLAGS>(w, a.inner, a.n_inner, flags);
+    transpose_planes(w);
+
+#pragma unroll
+    for (uint32_t r = 0; r < VPT; ++r) lds[tid | (r << tb)] = v[r];
+    __syncthreads();
+
+    if (ELEM == 8) {
+        const uint2 *l2 = reinterpret_cast<const uint2 *>(lds);
+#pragma unroll
+        for (uint32_t r = 0; r < VPT; ++r) {
+            const uint2 e0 = l2[src_of(w, 2u * r)];
+            const uint2 e1 = l2[src_of(w, 2u * r + 1u)];
+            const uint64_t e = dst_base + off_t + a.off_r[r];
+            st_nt(dst + e / EPV, make_uint4(e0.x, e0.y, e1.x, e1.y));
+        }
+    } else {
+#pragma unroll
+        for (uint32_t r = 0; r < VPT; ++r) {
+            const vec16 e0 = lds[src_of(w, r)];
+            const uint64_t e = dst_base + off_t + a.off_r[r];
+            st_nt(dst + e / EPV, e0);
+        }
+    }
+}
+
+template <int ELEM>
+__global__ void __launch_bounds__(512) k_tile(const vec16 *__restrict__ src, vec16 *__restrict__ dst,
+                                              TileArgs a) {
+    extern __shared__ vec16 lds[];
+    const uint64_t tile = blockIdx.x;
+    uint64_t dst_base = 0;
+    for (uint32_t q = 0; q < a.n_out; ++q)
+        if ((tile >> q) & 1u) dst_base |= 1ull << a.out_pos[q];
+    const uint32_t *rec = a.rec + tile * a.rec_words;
+    const uint64_t src_base = (uint64_t)uni(rec[0]) | ((uint64_t)uni(rec[1]) << 32);
+    tile_body<ELEM, true>(src, dst, src_base, dst_base, a, rec + 2, lds);
+}
+
+// Whole state in one workgroup's LDS: one tile, every step is inner.
+template <int ELEM>
+__global__ void __launch_bounds__(512) k_small(const vec16 *__restrict__ src, vec16 *__restrict__ dst,
+                                               TileArgs a) {
+    extern __shared__ vec16 lds[];
+    tile_body<ELEM, false>(src, dst, 0, 0, a, nullptr, lds);
+}
+
+// Per-tile record of a pass: source tile address and the outside-control
+// flags of the inner steps, from a backward walk of the outer address.
+__global__ void __launch_bounds__(256) k_tilemap(TileMapArgs a) {
+    const uint64_t tile = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tile >= a.n_tiles) return;
+    uint64_t A = 0;
+    for (uint32_t q = 0; q < a.n_out; ++q)
+        if ((tile >> q) & 1u) A |= 1ull << a.out_pos[q];
+    uint32_t *rec = a.rec + tile * a.rec_words;
+    uint32_t word = 0, k = 0;
+    for (uint32_t s = 0; s < a.n_steps; ++s) {
+        const uint64_t cm = ((uint64_t)uni((uint32_t)(a.steps[s].cm >> 32)) << 32) |
+                            uni((uint32_t)a.steps[s].cm);
+        const uint32_t tbit = uni(a.steps[s].tbit);
+        const uint32_t inner = uni(a.steps[s].inner);
+        const bool cond = (A & cm) == cm;
+        if (inner) {
+            word |= (cond ? 1u : 0u) << (k & 31u);
+            ++k;
+            if ((k & 31u) == 0u) { rec[2 + (k >> 5) - 1] = word; word = 0; }
+        } else if (cond) {
+            A ^= 1ull << tbit;
+        }
+    }
+    if (k & 31u) rec[2 + (k >> 5)] = word;
+    rec[0] = (uint32_t)A;
+    rec[1] = (uint32_t)(A >> 32);
+}
+
+// Direct gather: each thread walks its own row backwards through every step
+// and copies the entry it lands on.  Used for states of fewer than 64 rows.
+template <int ELEM>
+__global__ void __launch_bounds__(256) k_direct(const uint8_t *__restrict__ src, uint8_t *__restrict__ dst,
+                                                uint64_t n, const TmStep *__restrict__ steps_rev, uint32_t L) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t x = i;
+    for (uint32_t s = 0; s < L; ++s) {
+        const uint64_t cm = steps_rev[s].cm;
+        if ((x & cm) == cm) x ^= 1ull << steps_rev[s].tbit;
+    }
+    if (ELEM == 8) {
+        reinterpret_cast<uint64_t *>(dst)[i] = reinterpret_cast<const uint64_t *>(src)[x];
+    } else {
+        reinterpret_cast<vec16 *>(dst)[i] = reinterpret_cast<const vec16 *>(src)[x];
+    }
+}
+
+// Plain per-step update: one thread per row pair (i, i | 2^t) with bit t of
+// i clear; the pair is interchanged when all control bits of i are 1.
+template <int ELEM>
+__global__ void __launch_bounds__(256) k_plain_step(uint8_t *__restrict__ buf, uint64_t half_n,
+                                                    uint32_t t, uint64_t cm) {
+    const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= half_n) return;
+    const uint64_t T = 1ull << t;
+    const uint64_t lo = ((q >> t) << (t + 1)) | (q & (T - 1));
+    if ((lo & cm) != cm) return;
+    if (ELEM == 8) {
+        uint64_t *b = reinterpret_cast<uint64_t *>(buf);
+        const uint64_t a0 = b[lo], a1 = b[lo | T];
+        b[lo] = a1;
+        b[lo | T] = a0;
+    } else {
+        vec16 *b = reinterpret_cast<vec16 *>(buf);
+        const vec16 a0 = b[lo], a1 = b[lo | T];
+        b[lo] = a1;
+        b[lo | T] = a0;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_copy(const vec16 *__restrict__ src, vec16 *__restrict__ dst,
+                                              uint64_t nvec) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvec; i += stride)
+        st_nt(dst + i, ld_nt(src + i));
+}
+
+template <typename KernelT>
+hipError_t allow_lds(KernelT kernel, size_t bytes) {
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+}  // namespace
+
+hipError_t launch_direct(uint32_t elem, const void *src, void *dst, uint64_t n,
+                         const TmStep *steps_rev, uint32_t L, hipStream_t st) {
+    const uint32_t bs = 256;
+    const uint64_t grid = (n + bs - 1) / bs;
+    if (elem == 8)
+        hipLaunchKernelGGL(k_direct<8>, dim3((uint32_t)grid), dim3(bs), 0, st,
+                           (const uint8_t *)src, (uint8_t *)dst, n, steps_rev, L);
+    else
+        hipLaunchKernelGGL(k_direct<16>, dim3((uint32_t)grid), dim3(bs), 0, st,
+                           (const uint8_t *)src, (uint8_t *)dst, n, steps_rev, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_small(uint32_t elem, const void *src, void *dst, uint32_t M,
+                        const TileArgs &a, hipStream_t st) {
+    const size_t lds = (size_t)elem << M;
+    const uint32_t threads = 1u << a.tb;
+    hipError_t e;
+    if (elem == 8) {
+        if ((e = allow_lds(k_small<8>, lds)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_small<8>, dim3(1), dim3(threads), lds, st, (const vec16 *)src, (vec16 *)dst, a);
+    } else {
+        if ((e = allow_lds(k_small<16>, lds)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_small<16>, dim3(1), dim3(threads), lds, st, (const vec16 *)src, (vec16 *)dst, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_tilemap(const TileMapArgs &a, hipStream_t st) {
+    const uint32_t bs = 256;
+    const uint64_t grid = (a.n_tiles + bs - 1) / bs;
+    hipLaunchKernelGGL(k_tilemap, dim3((uint32_t)grid), dim3(bs), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile(uint32_t elem, const void *src, void *dst, uint64_t n_tiles,
+                       const TileArgs &a, hipStream_t st) {
+    const size_t lds = (size_t)elem << (a.tb + 5);
+    const uint32_t threads = 1u << a.tb;
+    hipError_t e;
+    if (elem == 8) {
+        if ((e = allow_lds(k_tile<8>, lds)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_tile<8>, dim3((uint32_t)n_tiles), dim3(threads), lds, st,
+                           (const vec16 *)src, (vec16 *)dst, a);
+    } else {
+        if ((e = allow_lds(k_tile<16>, lds)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_tile<16>, dim3((uint32_t)n_tiles), dim3(threads), lds, st,
+                           (const vec16 *)src, (vec16 *)dst, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_plain_step(uint32_t elem, void *buf, uint32_t M, uint32_t target,
+                             uint64_t cmask, hipStream_t st) {
+    const uint64_t half_n = 1ull << (M - 1);
+    const uint32_t bs = 256;
+    const uint64_t grid = (half_n + bs - 1) / bs;
+    if (elem == 8)
+        hipLaunchKernelGGL(k_plain_step<8>, dim3((uint32_t)grid), dim3(bs), 0, st, (uint8_t *)buf, half_n,
+                           target, cmask);
+    else
+        hipLaunchKernelGGL(k_plain_step<16>, dim3((uint32_t)grid), dim3(bs), 0, st, (uint8_t *)buf, half_n,
+                           target, cmask);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t st) {
+    const uint64_t nvec = bytes / 16;
+    const uint32_t bs = 256;
+    uint64_t grid = (nvec + bs - 1) / bs;
+    if (grid > 256ull * 64) grid = 256ull * 64;
+    if (grid == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy, dim3((uint32_t)grid), dim3(bs), 0, st, (const vec16 *)src, (vec16 *)dst, nvec);
+    return hipGetLastError();
+}
+
+}  // namespace qsim

@@ -1,0 +1,164 @@
+// Pass planner of the fused path (host only).
+//
+// A pass streams the whole state once through LDS tiles.  A tile is the set
+// of 2^K rows that agree on every address bit outside a mask I of K bits.  A
+// step (target t, controls C) can join a pass with mask I when
+//   * t is in I: it permutes rows inside each tile (inner step), or
+//   * C has no bit in I: it moves whole tiles, or leaves them, depending on
+//     bits that are constant over a tile (outer step).
+// A step with t outside I and a control inside I would split tiles, so it
+// waits for a later pass.  This is the paper's question of which sequential
+// steps can be processed together (Sec. 2(i) Parallelism), answered for
+// tiles rather than single sub-matrices.
+//
+// Steps may be taken out of order, but only past steps they commute with:
+// (t1, C1) and (t2, C2) commute when t1 is not in C2 and t2 is not in C1
+// (equal targets always commute, the premise of the same-target shortcut of
+// Sec. 2(i)).  The scan below keeps every step behind each earlier step it
+// does not commute with, so the product of the reordered list is the
+// product of the original one.
+#include <algorithm>
+#include <stdexcept>
+
+#include "qsim_internal.h"
+
+namespace qsim {
+
+namespace {
+
+inline int popc(uint64_t x) { return __builtin_popcountll(x); }
+
+inline bool commute(uint32_t t1, uint64_t c1, uint32_t t2, uint64_t c2) {
+    return !((c2 >> t1) & 1ull) && !((c1 >> t2) & 1ull);
+}
+
+// Smallest mask containing `I` under which every step of `taken` (plus the
+// candidate step, if any) is admissible; returns 0 if that needs more than
+// `K` bits or a bit outside `allowed`.
+uint64_t close_mask(uint64_t I, const std::vector<uint32_t> &taken, int cand, const uint32_t *target,
+                    const uint64_t *cmask, int K, uint64_t allowed) {
+    bool changed = true;
+    while (changed) {
+        changed = false;
+        auto visit = [&](uint32_t q) {
+            const uint64_t T = 1ull << target[q];
+            if (!(I & T) && (cmask[q] & I)) {
+                I |= T;
+                changed = true;
+            }
+        };
+        for (uint32_t q : taken) visit(q);
+        if (cand >= 0) visit((uint32_t)cand);
+        if (popc(I) > K || (I & ~allowed)) return 0;
+    }
+    return I;
+}
+
+}  // namespace
+
+std::vector<Pass> plan_passes(uint32_t M, const uint32_t *target, const uint64_t *cmask, uint64_t L,
+                              const PlanConfig &cfg) {
+    std::vector<Pass> passes;
+    if (L == 0) return passes;
+    const int K = std::min<int>(cfg.tile_bits, (int)M);
+    const uint64_t all = (M >= 64) ? ~0ull : ((1ull << M) - 1ull);
+    // Tile bits address entries inside a tile with 32-bit offsets.
+    const uint64_t allowed = all & 0xFFFFFFFFull;
+    const int low = std::min<int>(std::max(cfg.low_bits, 1), K);
+    const uint64_t base = (1ull << low) - 1ull;
+    const int cap = std::max(cfg.max_seg_steps, 1);
+
+    // Dependencies: preds[j] = earlier steps that j does not commute with.
+    std::vector<std::vector<uint32_t>> preds(L);
+    for (uint64_t j = 1; j < L; ++j) {
+        if (!cfg.reorder) {
+            preds[j].push_back((uint32_t)(j - 1));
+            continue;
+        }
+        for (uint64_t i = 0; i < j; ++i)
+            if (!commute(target[i], cmask[i], target[j], cmask[j])) preds[j].push_back((uint32_t)i);
+    }
+
+    // state: 0 = pending, 1 = done in an earlier pass, 2 = taken now, 3 = blocked now
+    std::vector<uint8_t> state(L, 0);
+    uint64_t remaining = L;
+    std::vector<uint32_t> pending;
+    pending.reserve(L);
+    for (uint64_t s = 0; s < L; ++s) pending.push_back((uint32_t)s);
+
+    // Controls of the taken steps whose target lies outside mask I: bits that
+    // cannot join the tile any more without pulling those targets in.
+    auto outer_controls = [&](const std::vector<uint32_t> &taken, int cand, uint64_t I) {
+        uint64_t U = 0;
+        for (uint32_t q : taken)
+            if (!((I >> target[q]) & 1ull)) U |= cmask[q];
+        if (cand >= 0 && !((I >> target[cand]) & 1ull)) U |= cmask[cand];
+        return U;
+    };
+    // A pass must still be able to grow its tile to K bits with bits that no
+    // taken outer step is controlled by.
+    auto completable = [&](uint64_t I, uint64_t U) {
+        return popc(allowed & ~I & ~U) >= K - popc(I);
+    };
+
+    while (remaining > 0) {
+        uint64_t I = base;
+        uint64_t U = 0;
+        std::vector<uint32_t> taken;
+        for (uint32_t s : pending) {
+            if ((int)taken.size() >= cap) break;
+            bool ready = true;
+            for (uint32_t p : preds[s])
+                if (state[p] != 1 && state[p] != 2) { ready = false; break; }
+            if (!ready) { state[s] = 3; continue; }
+            const uint64_t T = 1ull << target[s];
+            bool took = false;
+            if (I & T) {
+                took = true;                       // inner step: U unchanged
+            } else if (!(cmask[s] & I) && completable(I, U | cmask[s])) {
+                U |= cmask[s];                     // outer step
+                took = true;
+            } else {
+                // make it an inner step by adding its target (and the closure)
+                const uint64_t J = close_mask(I | T, taken, (int)s, target, cmask, K, allowed);
+                if (J) {
+                    const uint64_t UJ = outer_controls(taken, (int)s, J);
+                    if (completable(J, UJ)) {
+                        I = J;
+                        U = UJ;
+                        took = true;
+                    }
+                }
+            }
+            if (took) {
+                taken.push_back(s);
+                state[s] = 2;
+            } else {
+                state[s] = 3;
+            }
+        }
+        if (taken.empty()) throw std::logic_error("planner made no progress");
+        // Widen the tile to K bits with the lowest bits that no outer step of
+        // the pass is controlled by; every taken step stays admissible.
+        for (uint32_t b = 0; b < M && popc(I) < K; ++b) {
+            const uint64_t B = 1ull << b;
+            if ((I & B) || (U & B) || !(allowed & B)) continue;
+            I |= B;
+        }
+        Pass p;
+        p.tile_mask = I;
+        p.steps = taken;
+        passes.push_back(std::move(p));
+        remaining -= taken.size();
+        std::vector<uint32_t> next;
+        next.reserve(pending.size());
+        for (uint32_t s : pending) {
+            if (state[s] == 2) state[s] = 1;
+            else { state[s] = 0; next.push_back(s); }
+        }
+        pending.swap(next);
+    }
+    return passes;
+}
+
+}  // namespace qsim

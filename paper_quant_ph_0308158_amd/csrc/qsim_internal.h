@@ -1,0 +1,89 @@
+// Internal declarations shared by the host side (planner, C ABI) and the HIP
+// kernels of libqsim.  Nothing here is part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace qsim {
+
+// Entries per LDS tile are 2^(tb + 5): every thread of a tile workgroup owns
+// 32 entries (one bit lane of each 32-bit bit-plane word), so a workgroup of
+// 2^tb threads covers one tile.
+constexpr int kPlanes = 16;        // bit-plane registers per thread (tile bits <= 15)
+constexpr int kMaxTileBits = 14;   // 2^14 entries * 8 B = 128 KiB of LDS
+constexpr int kMaxOuterBits = 48;
+
+// A step as the tile-map kernel sees it (16 bytes).  `cm` is the part of the
+// control mask outside the tile; `tbit` is the address bit of the target;
+// `inner` is 1 when the target is a tile bit (the step moves entries inside
+// a tile and the tile-map only records whether its outside controls hold).
+struct TmStep {
+    uint64_t cm;
+    uint32_t tbit;
+    uint32_t inner;
+};
+
+// Inner steps are packed into 32 bits: tile-index bit of the target in bits
+// 0..3, tile-index control mask in bits 16..31.
+__host__ __device__ inline uint32_t pack_inner(uint32_t tj, uint32_t icm) {
+    return (tj & 15u) | (icm << 16);
+}
+
+// Arguments of one pass of the fused tile kernel (passed by value).
+struct TileArgs {
+    const uint32_t *inner;  // packed inner steps in reverse execution order
+    const uint32_t *rec;    // per-tile records from the tile-map kernel (or null)
+    uint32_t n_inner;
+    uint32_t rec_words;     // 2 + ceil(n_inner / 32)
+    uint32_t tb;            // log2(threads per workgroup); tile bits = tb + 5
+    uint32_t n_out;         // outer bits (M - tile bits)
+    uint32_t off_r[32];     // element offset of the tile-index bits above the thread bits, per r
+    uint8_t in_pos[16];     // address bit of tile-index bit b
+    uint8_t out_pos[kMaxOuterBits];  // address bit of outer-index bit q
+};
+
+struct TileMapArgs {
+    const TmStep *steps;    // all steps of the pass in reverse execution order
+    uint32_t *rec;
+    uint64_t n_tiles;
+    uint32_t n_steps;
+    uint32_t rec_words;
+    uint32_t n_out;
+    uint32_t pad;
+    uint8_t out_pos[kMaxOuterBits];
+};
+
+// Host-side plan of the fused path.
+struct Pass {
+    uint64_t tile_mask = 0;          // address bits inside a tile
+    std::vector<uint32_t> steps;     // original step indices, execution order
+};
+
+struct PlanConfig {
+    int tile_bits = 13;
+    int low_bits = 5;
+    int max_seg_steps = 1024;
+    bool reorder = true;
+};
+
+// Split steps into passes (see planner.cpp).
+std::vector<Pass> plan_passes(uint32_t M, const uint32_t *target, const uint64_t *cmask,
+                              uint64_t L, const PlanConfig &cfg);
+
+// Kernel launchers (kernels.hip).  All return hipSuccess or the launch error.
+hipError_t launch_direct(uint32_t elem, const void *src, void *dst, uint64_t n,
+                         const TmStep *steps_rev, uint32_t L, hipStream_t st);
+hipError_t launch_small(uint32_t elem, const void *src, void *dst, uint32_t M,
+                        const TileArgs &a, hipStream_t st);
+hipError_t launch_tilemap(const TileMapArgs &a, hipStream_t st);
+hipError_t launch_tile(uint32_t elem, const void *src, void *dst, uint64_t n_tiles,
+                       const TileArgs &a, hipStream_t st);
+hipError_t launch_plain_step(uint32_t elem, void *buf, uint32_t M, uint32_t target,
+                             uint64_t cmask, hipStream_t st);
+hipError_t launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t st);
+
+}  // namespace qsim

@@ -1,0 +1,297 @@
+"""ctypes binding of libqsim (include/qsim.h): argument marshalling only.
+
+Every step of the computation runs in the HIP kernels of libqsim.so; this
+module converts numpy / torch arguments into the C ABI's plain pointers and
+sizes.  If libqsim.so is missing the import fails: there is no fallback.
+
+Steps are passed as a pair of arrays ``(target, cmask)``: ``target[s]`` is
+the 0-based address bit that step s flips (the paper's a(target+1)),
+``cmask[s]`` the mask of its controlling bits, all of which must be 1 for
+the step to fire (Sec. 2(b)-(g)).  ``steps[0]`` acts first, so applying
+a diagram computes k2 = U_L ... U_1 k1 (Sec. 2(a), 2(h)).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libqsim.so")
+
+QSIM_C64 = 0
+QSIM_C128 = 1
+OK, ERR_INVALID, ERR_NOMEM, ERR_DEVICE, ERR_RANGE = 0, -1, -2, -3, -4
+MAX_M = 36
+
+STEP_DTYPE = np.dtype([("target", "<u4"), ("reserved0", "<u4"), ("control_mask", "<u8")])
+
+# Every symbol declared in include/qsim.h.
+EXPORTS = (
+    "qsim_state_create", "qsim_state_wrap", "qsim_state_destroy", "qsim_state_qubits",
+    "qsim_state_elem_bytes", "qsim_state_current", "qsim_write_portion", "qsim_apply_steps",
+    "qsim_apply_steps_plain", "qsim_read_portion", "qsim_read_portion_async", "qsim_apply_batch",
+    "qsim_state_set_tuning", "qsim_plan_describe", "qsim_copy_bytes", "qsim_last_error",
+    "qsim_version",
+)
+
+
+class QsimError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"qsim error {code}: {msg}")
+        self.code = code
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("tile_bits", ctypes.c_uint32), ("low_bits", ctypes.c_uint32),
+                ("max_seg_steps", ctypes.c_uint32), ("reorder", ctypes.c_uint32),
+                ("small_bits", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
+
+
+def _load() -> ctypes.CDLL:
+    # PyTorch ships its own HIP runtime under the soname libamdhip64.so.7.
+    # Loading torch first makes libqsim.so bind to that same runtime, so
+    # device pointers and streams from torch are valid in libqsim; loading
+    # libqsim first would pull in a second copy of the runtime.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_quant_ph_0308158_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+    sig = {
+        "qsim_state_create": (vp, [u32, i32]),
+        "qsim_state_wrap": (vp, [u32, i32, vp, vp]),
+        "qsim_state_destroy": (None, [vp]),
+        "qsim_state_qubits": (u32, [vp]),
+        "qsim_state_elem_bytes": (u32, [vp]),
+        "qsim_state_current": (vp, [vp]),
+        "qsim_write_portion": (i32, [vp, u64, u64, vp]),
+        "qsim_apply_steps": (i32, [vp, vp, u64, vp]),
+        "qsim_apply_steps_plain": (i32, [vp, vp, u64, vp]),
+        "qsim_read_portion": (i32, [vp, u64, u64, vp]),
+        "qsim_read_portion_async": (i32, [vp, u64, u64, vp, vp]),
+        "qsim_apply_batch": (i32, [vp, vp, vp, u32, vp]),
+        "qsim_state_set_tuning": (i32, [vp, vp]),
+        "qsim_plan_describe": (i32, [u32, i32, vp, u64, vp, vp, vp, vp, u32, vp]),
+        "qsim_copy_bytes": (i32, [vp, vp, u64, vp]),
+        "qsim_last_error": (ctypes.c_char_p, []),
+        "qsim_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def lib() -> ctypes.CDLL:
+    return _lib
+
+
+def last_error() -> str:
+    return _lib.qsim_last_error().decode()
+
+
+def version() -> str:
+    return _lib.qsim_version().decode()
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise QsimError(rc, last_error())
+
+
+def dtype_code(dtype) -> int:
+    if dtype in ("c64", np.complex64, QSIM_C64):
+        return QSIM_C64
+    if dtype in ("c128", np.complex128, QSIM_C128):
+        return QSIM_C128
+    try:
+        import torch
+        if dtype == torch.complex64:
+            return QSIM_C64
+        if dtype == torch.complex128:
+            return QSIM_C128
+    except ImportError:
+        pass
+    raise ValueError(f"unsupported dtype {dtype!r}")
+
+
+def np_dtype(code: int):
+    return np.complex64 if code == QSIM_C64 else np.complex128
+
+
+def pack_steps(target, cmask) -> np.ndarray:
+    t = np.asarray(target, dtype=np.uint32).ravel()
+    c = np.asarray(cmask, dtype=np.uint64).ravel()
+    if t.shape != c.shape:
+        raise ValueError("target and cmask differ in length")
+    st = np.zeros(len(t), dtype=STEP_DTYPE)
+    st["target"] = t
+    st["control_mask"] = c
+    return st
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return torch.cuda.current_stream().cuda_stream or None
+        except ImportError:
+            pass
+        return None
+    if isinstance(stream, int):
+        return stream or None
+    return stream.cuda_stream or None
+
+
+def _tuning_struct(tuning: Optional[dict]) -> Optional[Tuning]:
+    if tuning is None:
+        return None
+    t = Tuning()
+    for k, v in tuning.items():
+        if k == "reorder" and isinstance(v, bool):
+            v = 1 if v else 2
+        setattr(t, k, int(v))
+    return t
+
+
+class State:
+    """A 2^M-entry state on the current HIP device (two ping-pong buffers)."""
+
+    def __init__(self, M: int, dtype="c64", buffers=None):
+        self.M = int(M)
+        self.code = dtype_code(dtype)
+        self._keep = None
+        if buffers is None:
+            h = _lib.qsim_state_create(self.M, self.code)
+        else:
+            b0, b1 = buffers
+            self._keep = (b0, b1)
+            h = _lib.qsim_state_wrap(self.M, self.code, ctypes.c_void_p(_ptr(b0)), ctypes.c_void_p(_ptr(b1)))
+        if not h:
+            raise QsimError(ERR_INVALID, last_error())
+        self._h = ctypes.c_void_p(h)
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.qsim_state_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        return self._h
+
+    @property
+    def elem_bytes(self) -> int:
+        return int(_lib.qsim_state_elem_bytes(self._h))
+
+    @property
+    def n(self) -> int:
+        return 1 << self.M
+
+    def current_ptr(self) -> int:
+        return int(_lib.qsim_state_current(self._h))
+
+    # -- data movement
+    def write(self, host: np.ndarray, offset: int = 0):
+        a = np.ascontiguousarray(host)
+        if a.dtype != np_dtype(self.code):
+            raise ValueError(f"expected {np_dtype(self.code)}, got {a.dtype}")
+        _check(_lib.qsim_write_portion(self._h, offset, a.size, a.ctypes.data))
+
+    def read(self, offset: int = 0, count: Optional[int] = None) -> np.ndarray:
+        if count is None:
+            count = self.n - offset
+        out = np.empty(count, dtype=np_dtype(self.code))
+        _check(_lib.qsim_read_portion(self._h, offset, count, out.ctypes.data))
+        return out
+
+    def read_into(self, out: np.ndarray, offset: int = 0):
+        if out.dtype != np_dtype(self.code) or not out.flags.c_contiguous:
+            raise ValueError("out must be a contiguous array of the state's dtype")
+        _check(_lib.qsim_read_portion(self._h, offset, out.size, out.ctypes.data))
+
+    def read_async(self, offset: int, count: int, host_ptr: int, stream=None):
+        _check(_lib.qsim_read_portion_async(self._h, offset, count, ctypes.c_void_p(host_ptr),
+                                            ctypes.c_void_p(_stream_ptr(stream))))
+
+    # -- compute
+    def apply(self, target, cmask, stream=None):
+        st = pack_steps(target, cmask)
+        _check(_lib.qsim_apply_steps(self._h, st.ctypes.data if len(st) else None, len(st),
+                                     ctypes.c_void_p(_stream_ptr(stream))))
+
+    def apply_packed(self, steps: np.ndarray, stream=None):
+        _check(_lib.qsim_apply_steps(self._h, steps.ctypes.data if len(steps) else None, len(steps),
+                                     ctypes.c_void_p(_stream_ptr(stream))))
+
+    def apply_plain(self, target, cmask, stream=None):
+        st = pack_steps(target, cmask)
+        _check(_lib.qsim_apply_steps_plain(self._h, st.ctypes.data if len(st) else None, len(st),
+                                           ctypes.c_void_p(_stream_ptr(stream))))
+
+    def set_tuning(self, tuning: Optional[dict]):
+        t = _tuning_struct(tuning)
+        _check(_lib.qsim_state_set_tuning(self._h, ctypes.byref(t) if t is not None else None))
+
+
+def _ptr(buf) -> int:
+    if isinstance(buf, int):
+        return buf
+    return int(buf.data_ptr())
+
+
+def apply_batch(states: Sequence[State], steps: Sequence[Tuple[np.ndarray, np.ndarray]], stream=None):
+    n = len(states)
+    packed = [pack_steps(t, c) for t, c in steps]
+    hs = (ctypes.c_void_p * n)(*[s.handle.value for s in states])
+    ps = (ctypes.c_void_p * n)(*[p.ctypes.data if len(p) else None for p in packed])
+    ls = (ctypes.c_uint64 * n)(*[len(p) for p in packed])
+    _check(_lib.qsim_apply_batch(ctypes.cast(hs, ctypes.c_void_p), ctypes.cast(ps, ctypes.c_void_p),
+                                 ctypes.cast(ls, ctypes.c_void_p), n, ctypes.c_void_p(_stream_ptr(stream))))
+
+
+def plan_describe(M: int, dtype, target, cmask, tuning: Optional[dict] = None):
+    """Host-only pass plan: (masks, lens, order)."""
+    st = pack_steps(target, cmask)
+    L = len(st)
+    n_passes = ctypes.c_uint32(0)
+    t = _tuning_struct(tuning)
+    order = np.zeros(max(L, 1), dtype=np.uint32)
+    cap = max(L, 1)
+    masks = np.zeros(cap, dtype=np.uint64)
+    lens = np.zeros(cap, dtype=np.uint32)
+    _check(_lib.qsim_plan_describe(M, dtype_code(dtype), st.ctypes.data if L else None, L,
+                                   ctypes.byref(t) if t is not None else None, ctypes.byref(n_passes),
+                                   masks.ctypes.data, lens.ctypes.data, cap, order.ctypes.data))
+    p = n_passes.value
+    return masks[:p].copy(), lens[:p].copy(), order[:L].copy()
+
+
+def copy_bytes(dst_ptr: int, src_ptr: int, nbytes: int, stream=None):
+    _check(_lib.qsim_copy_bytes(ctypes.c_void_p(dst_ptr), ctypes.c_void_p(src_ptr), nbytes,
+                                ctypes.c_void_p(_stream_ptr(stream))))

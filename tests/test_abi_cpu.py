@@ -1,0 +1,138 @@
+"""Host-side checks of libqsim that need no GPU: the library loads and exports
+every symbol of include/qsim.h, argument validation, and the pass planner's
+invariants (checked with the CPU oracle on the planner's reordered list)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from paper_quant_ph_0308158_amd import qsim
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    text = open(os.path.join(ROOT, "include", "qsim.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qsim_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_header_symbol():
+    syms = header_symbols()
+    assert len(syms) >= 15
+    lib = qsim.lib()
+    for s in syms:
+        assert hasattr(lib, s), f"libqsim.so does not export {s}"
+    assert sorted(qsim.EXPORTS) == syms
+
+
+def test_version_and_error_string():
+    assert "gfx950" in qsim.version()
+    assert isinstance(qsim.last_error(), str)
+
+
+def test_step_layout_is_16_bytes():
+    assert qsim.STEP_DTYPE.itemsize == 16
+
+
+@pytest.mark.parametrize("bad", [
+    dict(M=8, target=[8], cmask=[0]),
+    dict(M=8, target=[2], cmask=[1 << 8]),
+    dict(M=8, target=[2], cmask=[0b100]),
+])
+def test_invalid_steps_rejected(bad):
+    with pytest.raises(qsim.QsimError) as ei:
+        qsim.plan_describe(bad["M"], "c64", bad["target"], bad["cmask"])
+    assert ei.value.code == qsim.ERR_INVALID
+
+
+def test_invalid_m_and_dtype():
+    with pytest.raises(qsim.QsimError):
+        qsim.plan_describe(0, "c64", [], [])
+    with pytest.raises(qsim.QsimError):
+        qsim.plan_describe(qsim.MAX_M + 1, "c64", [], [])
+    with pytest.raises(qsim.QsimError):
+        qsim.plan_describe(8, "c64", [0], [0], tuning={"tile_bits": 20})
+
+
+def test_reserved_field_must_be_zero():
+    st = qsim.pack_steps([1], [0])
+    st["reserved0"] = 7
+    n = qsim.ctypes.c_uint32(0)
+    rc = qsim.lib().qsim_plan_describe(8, 0, st.ctypes.data, 1, None, qsim.ctypes.byref(n),
+                                       None, None, 0, None)
+    assert rc == qsim.ERR_INVALID
+
+
+def test_create_without_device_fails_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(qsim.QsimError):
+        qsim.State(10, "c64")
+
+
+def _check_plan(M, dtype, tg, cm, tuning):
+    masks, lens, order = qsim.plan_describe(M, dtype, tg, cm, tuning)
+    L = len(tg)
+    assert sorted(order.tolist()) == list(range(L))
+    assert int(lens.sum()) == L
+    K = min(tuning.get("tile_bits", 13 if dtype == "c64" else 12), M)
+    low = min(tuning.get("low_bits", 5 if dtype == "c64" else 4), K)
+    cap = tuning.get("max_seg_steps", 1024)
+    pos = 0
+    for p, (I, n) in enumerate(zip(masks.tolist(), lens.tolist())):
+        assert bin(I).count("1") == K, "a tile always has exactly K bits"
+        assert I & ((1 << low) - 1) == (1 << low) - 1, "tile must hold the low address bits"
+        assert I < (1 << M)
+        assert 1 <= n <= cap
+        for s in order[pos:pos + n]:
+            t, c = int(tg[s]), int(cm[s])
+            assert (I >> t) & 1 or not (c & I), f"step {s} splits tiles of pass {p}"
+        pos += n
+    return masks, lens, order
+
+
+@pytest.mark.parametrize("seed,M,dtype,tuning", [
+    (0, 12, "c64", {"tile_bits": 6, "low_bits": 2}),
+    (1, 14, "c128", {"tile_bits": 7, "low_bits": 3}),
+    (2, 16, "c64", {"tile_bits": 8, "max_seg_steps": 9}),
+    (3, 16, "c64", {"tile_bits": 8, "reorder": False}),
+    (4, 13, "c64", {"tile_bits": 5, "low_bits": 1}),
+])
+def test_planner_reorder_is_exact(seed, M, dtype, tuning):
+    """The planner's execution order has the same product as the original
+    list (checked with the oracle on an address-tag state)."""
+    rng = np.random.default_rng(seed)
+    tg, cm = W.random_steps(rng, M, 150, (0, 3))
+    masks, lens, order = _check_plan(M, dtype, tg, cm, tuning)
+    assert len(masks) > 1
+    k1 = W.tag_state(M)
+    a = oracle.apply(M, k1, tg, cm)
+    b = oracle.apply(M, k1, tg[order], cm[order])
+    assert a.tobytes() == b.tobytes()
+    if tuning.get("reorder") is False:
+        assert order.tolist() == list(range(len(tg)))
+
+
+def test_planner_on_benchmark_workloads():
+    tg, cm = W.m32_config()
+    masks, lens, order = _check_plan(32, "c64", tg, cm, {})
+    assert len(masks) < 80
+    tg, cm = W.m26_config()
+    _check_plan(26, "c128", tg, cm, {})
+
+
+def test_planner_same_target_run_is_one_pass():
+    """Steps that share a target commute (Sec. 2(i)): a long run of them with
+    controls spread over all bits fits in one pass."""
+    rng = np.random.default_rng(9)
+    M = 24
+    tg = np.full(200, 20, dtype=np.uint32)
+    cm = np.array([(1 << int(a)) | (1 << int(b)) for a, b in rng.integers(0, 20, size=(200, 2))],
+                  dtype=np.uint64)
+    masks, lens, order = _check_plan(M, "c64", tg, cm, {})
+    assert len(masks) == 1
