@@ -156,16 +156,43 @@ int qsim_apply_batch(qsim_state *const *states, const qsim_step *const *steps,
  * default for the state's dtype. */
 typedef struct {
     uint32_t tile_bits;    /* log2 entries per LDS tile (12..14)           */
-    uint32_t low_bits;     /* lowest address bits always inside a tile      */
+    uint32_t low_bits;     /* lowest address bits inside the tiles of the
+                              first and the last pass (natural layout)      */
     uint32_t max_seg_steps;/* cap on steps per pass                         */
     uint32_t reorder;      /* 1 = exact reordering of commuting steps, 2 = off */
     uint32_t small_bits;   /* largest M run whole inside one workgroup      */
-    uint32_t reserved[3];
+    uint32_t kernel_variant; /* tile kernel: 1 = one tile per workgroup,
+                                2 = persistent workgroups with the next
+                                tile's loads in flight, 3 = persistent with
+                                loads two tiles ahead (QSIM_C64 only)       */
+    uint32_t wg_per_cu;    /* persistent variant: workgroups per CU
+                              (0 = as many as fit)                          */
+    uint32_t outer_order;  /* order in which tiles are enumerated: 1 = the
+                              lowest outside address bit varies fastest,
+                              2 = the highest one does                      */
+    uint32_t remap;        /* 1 = between passes, store the state with its
+                              address bits permuted so that each pass's tile
+                              bits are low physical bits; 2 = keep the
+                              natural order throughout                      */
+    uint32_t mid_low_bits; /* low address bits forced into the tiles of the
+                              passes between the first and the last one    */
+    uint32_t reserved[2];
 } qsim_tuning;
 
 /* Set (tuning != NULL) or reset to defaults (NULL) the parameters used by
  * later applies on `state`.  QSIM_ERR_INVALID on out-of-range values. */
 int qsim_state_set_tuning(qsim_state *state, const qsim_tuning *tuning);
+
+/* Apply the steps, in the order given, as a single fused pass through
+ * tiles whose address bits are `tile_mask` (for callers that plan passes
+ * themselves, and for measuring one pass).  Every step must target a bit of
+ * tile_mask or have no control in it (Sec. 2(i): steps processed together);
+ * tile_mask must have 5..14 bits set (5..13 for QSIM_C128), all below bit
+ * 32 and below M, and must contain bit 0 for QSIM_C64.  L may be 0: the pass
+ * then moves every entry back to its own row.  QSIM_ERR_INVALID otherwise;
+ * nothing runs on error. */
+int qsim_apply_tile_pass(qsim_state *state, uint64_t tile_mask,
+                         const qsim_step *steps, uint64_t L, void *hip_stream);
 
 /* ---------------------------------------------------------------- planning */
 
@@ -185,6 +212,28 @@ int qsim_plan_describe(uint32_t M, qsim_dtype dtype, const qsim_step *steps,
                        uint64_t L, const qsim_tuning *tuning,
                        uint32_t *n_passes, uint64_t *pass_mask,
                        uint32_t *pass_len, uint32_t cap, uint32_t *order);
+
+/* ---------------------------------------------------------------- timing */
+
+/* Per-kernel device time of the applies on one state, taken with HIP events
+ * recorded on the stream of each launch (a few microseconds of gap per
+ * launch while enabled). */
+typedef struct {
+    uint64_t tile_launches;   /* fused tile passes                          */
+    double tile_ms;           /* summed device time of those launches       */
+    uint64_t tile_bytes;      /* algorithmic HBM bytes: 2 * 2^M * elem each */
+    uint64_t map_launches;    /* tile-map launches                          */
+    double map_ms;
+    uint64_t other_launches;  /* small-state, direct and plain-step launches */
+    double other_ms;
+} qsim_profile;
+
+/* enable = 1: clear the counters and time every later launch on `state`;
+ * enable = 0: stop timing. */
+int qsim_state_profile(qsim_state *state, int enable);
+
+/* Wait for the timed launches to finish and report their totals. */
+int qsim_state_profile_read(qsim_state *state, qsim_profile *out);
 
 /* ---------------------------------------------------------------- misc */
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <cstdlib>
 #include <cstring>
@@ -63,15 +64,25 @@ struct Tuning {
     int max_seg_steps;
     bool reorder;
     int small_bits;
+    uint32_t variant;     // 0 = one tile per workgroup, 1 = persistent
+    uint32_t wg_per_cu;
+    uint32_t outer_order; // 0 = lowest outside bit fastest, 1 = highest fastest
+    bool remap;           // permuted layouts between passes
+    int mid_low_bits;     // forced low bits of the passes in between
 };
 
 Tuning default_tuning(uint32_t elem) {
     Tuning t;
-    t.tile_bits = elem == 8 ? 13 : 12;   // 64 KiB of LDS per tile: two tiles per CU
+    t.tile_bits = 13;                    // 64 KiB (8 B entries) / 128 KiB (16 B) of LDS per tile
     t.low_bits = elem == 8 ? 5 : 4;      // >= 256 contiguous bytes per tile row run
     t.max_seg_steps = 1024;
     t.reorder = true;
     t.small_bits = elem == 8 ? 14 : 13;  // whole state in 128 KiB of LDS
+    t.variant = elem == 8 ? 0 : 1;       // 8 B: two one-tile workgroups per CU; 16 B: persistent
+    t.wg_per_cu = 0;
+    t.outer_order = 0;
+    t.remap = true;
+    t.mid_low_bits = 2;
     return t;
 }
 
@@ -83,7 +94,16 @@ int tuning_from(const qsim_tuning *in, uint32_t elem, Tuning *out) {
         if (in->max_seg_steps) t.max_seg_steps = (int)in->max_seg_steps;
         if (in->reorder) t.reorder = (in->reorder == 1);
         if (in->small_bits) t.small_bits = (int)in->small_bits;
+        if (in->kernel_variant) t.variant = in->kernel_variant - 1;
+        if (in->wg_per_cu) t.wg_per_cu = in->wg_per_cu;
+        if (in->outer_order) t.outer_order = in->outer_order - 1;
+        if (in->remap) t.remap = (in->remap == 1);
+        if (in->mid_low_bits) t.mid_low_bits = (int)in->mid_low_bits;
     }
+    if (t.mid_low_bits < 1 || t.mid_low_bits > t.low_bits) t.mid_low_bits = t.low_bits;
+    if (t.outer_order > 1) return fail(QSIM_ERR_INVALID, "outer_order out of range");
+    if (t.variant > 2 || (elem == 16 && t.variant > 1)) return fail(QSIM_ERR_INVALID, "kernel_variant out of range");
+    if (t.wg_per_cu > 8) return fail(QSIM_ERR_INVALID, "wg_per_cu out of range");
     const int max_tile = elem == 8 ? kMaxTileBits : kMaxTileBits - 1;
     if (t.tile_bits < 5 || t.tile_bits > max_tile)
         return fail(QSIM_ERR_INVALID, "tile_bits out of range");
@@ -98,6 +118,7 @@ PlanConfig plan_config(const Tuning &t) {
     PlanConfig c;
     c.tile_bits = t.tile_bits;
     c.low_bits = t.low_bits;
+    c.mid_low_bits = t.remap ? t.mid_low_bits : t.low_bits;
     c.max_seg_steps = t.max_seg_steps;
     c.reorder = t.reorder;
     return c;
@@ -187,6 +208,12 @@ struct qsim_state {
     DevBuf plan;   // uploaded step descriptors
     DevBuf rec;    // per-tile records of a pass
     HostStage stage;
+    // timing (qsim_state_profile)
+    bool profiling = false;
+    std::vector<hipEvent_t> ev_pool;
+    struct Timed { int kind; hipEvent_t a, b; uint64_t bytes; };
+    std::vector<Timed> timed;
+    qsim_profile prof{};
 };
 
 namespace {
@@ -234,6 +261,14 @@ size_t blob_push(std::vector<uint8_t> &blob, const void *data, size_t bytes) {
     return off;
 }
 
+// Inner step arrays are read eight entries at a time by the tile kernels:
+// pad with zero entries (never executed) to a multiple of eight.
+size_t push_inner(std::vector<uint8_t> &blob, std::vector<uint32_t> inner) {
+    inner.resize((inner.size() + 7) & ~size_t(7), 0u);
+    if (inner.empty()) inner.resize(8, 0u);
+    return blob_push(blob, inner.data(), inner.size() * 4);
+}
+
 // Small-state path: the whole state is one tile; every step is inner.
 void prepare_small(uint32_t M, uint32_t elem, const qsim_step *steps, uint64_t L, Prepared &pr) {
     std::vector<uint32_t> inner(L);
@@ -243,14 +278,15 @@ void prepare_small(uint32_t M, uint32_t elem, const qsim_step *steps, uint64_t L
     }
     Launch l;
     l.kind = Launch::SMALL;
-    l.inner_off = blob_push(pr.blob, inner.data(), inner.size() * 4);
+    l.inner_off = push_inner(pr.blob, inner);
     l.ta.n_inner = (uint32_t)L;
     l.ta.tb = M - 5;
     l.ta.n_out = 0;
     const uint32_t LO = elem == 8 ? 1 : 0;
-    for (uint32_t b = 0; b < 16; ++b) l.ta.in_pos[b] = (uint8_t)b;
+    for (uint32_t b = 0; b < 16; ++b) l.ta.pos_src[b] = l.ta.pos_dst[b] = (uint8_t)b;
     const uint32_t vpt = 32u >> LO;
-    for (uint32_t r = 0; r < 32; ++r) l.ta.off_r[r] = r < vpt ? (uint32_t)(r << (LO + l.ta.tb)) : 0u;
+    for (uint32_t r = 0; r < 32; ++r)
+        l.ta.off_r_src[r] = l.ta.off_r_dst[r] = r < vpt ? (uint32_t)(r << (LO + l.ta.tb)) : 0u;
     pr.launches.push_back(l);
 }
 
@@ -269,10 +305,47 @@ void prepare_direct(const qsim_step *steps, uint64_t L, Prepared &pr) {
     pr.launches.push_back(l);
 }
 
+// Layout of the state between pass p-1 (tile mask A) and pass p (tile mask
+// B): physical bit i holds logical bit order[i].  The bits every pass keeps
+// in its tile stay at the bottom in place; above them come the bits both
+// neighbours tile, then the rest of B (read side of pass p), then the rest
+// of A (write side of pass p-1), then everything else, so that both passes
+// see their tiles as a few long contiguous runs in few pages.
+void make_layout(uint32_t M, uint32_t fixed, uint64_t A, uint64_t B, uint8_t *lam) {
+    std::vector<uint32_t> order;
+    for (uint32_t b = 0; b < fixed; ++b) order.push_back(b);
+    auto add = [&](uint64_t set) {
+        for (uint32_t b = fixed; b < M; ++b)
+            if ((set >> b) & 1ull) order.push_back(b);
+    };
+    const uint64_t all = (1ull << M) - 1ull;
+    add(A & B);
+    add(B & ~A);
+    add(A & ~B);
+    add(all & ~(A | B));
+    for (uint32_t i = 0; i < M; ++i) lam[order[i]] = (uint8_t)i;
+}
+
 int prepare_passes(uint32_t M, uint32_t elem, const std::vector<Pass> &passes,
-                   const uint32_t *target, const uint64_t *cmask, Prepared &pr) {
+                   const uint32_t *target, const uint64_t *cmask, uint32_t outer_order, bool remap,
+                   Prepared &pr) {
     const uint32_t LO = elem == 8 ? 1 : 0;
-    for (const Pass &p : passes) {
+    const size_t P = passes.size();
+    // Layouts at the pass boundaries; the state enters and leaves in the
+    // natural order.
+    std::vector<std::array<uint8_t, 64>> lam(P + 1);
+    for (auto &l : lam)
+        for (uint32_t b = 0; b < 64; ++b) l[b] = (uint8_t)b;
+    if (remap && P > 1) {
+        uint64_t common = ~0ull;
+        for (const Pass &p : passes) common &= p.tile_mask;
+        uint32_t fixed = 0;
+        while (fixed < M && ((common >> fixed) & 1ull)) ++fixed;
+        for (size_t p = 1; p < P; ++p)
+            make_layout(M, fixed, passes[p - 1].tile_mask, passes[p].tile_mask, lam[p].data());
+    }
+    for (size_t pi = 0; pi < P; ++pi) {
+        const Pass &p = passes[pi];
         const uint64_t I = p.tile_mask;
         const uint32_t K = (uint32_t)__builtin_popcountll(I);
         // The tile kernel needs 32 entries per thread, at most 2^14 entries,
@@ -281,13 +354,31 @@ int prepare_passes(uint32_t M, uint32_t elem, const std::vector<Pass> &passes,
         if (K < 5 || K > (uint32_t)kMaxTileBits || (M - K) > (uint32_t)kMaxOuterBits ||
             (I >> 32) != 0 || (elem == 8 && !(I & 1ull)) || (elem == 16 && K > (uint32_t)kMaxTileBits - 1))
             return fail(QSIM_ERR_INVALID, "planner produced a tile the kernel cannot run");
-        uint8_t in_pos[16] = {0}, out_pos[kMaxOuterBits] = {0};
+        const uint8_t *ls = lam[pi].data(), *ld = lam[pi + 1].data();
+        uint8_t in_log[16] = {0}, out_log[kMaxOuterBits] = {0};
         uint8_t jpos[64];
         uint32_t ni = 0, no = 0;
         for (uint32_t b = 0; b < M; ++b) {
-            if ((I >> b) & 1ull) { jpos[b] = (uint8_t)ni; in_pos[ni++] = (uint8_t)b; }
-            else out_pos[no++] = (uint8_t)b;
+            if ((I >> b) & 1ull) { jpos[b] = (uint8_t)ni; in_log[ni++] = (uint8_t)b; }
+            else out_log[no++] = (uint8_t)b;
         }
+        // Tiles may be enumerated in any order: outer_order picks which
+        // outside bits (by physical position in the written layout) vary
+        // between tiles processed at the same time.
+        std::sort(out_log, out_log + no, [&](uint8_t x, uint8_t y) {
+            return outer_order == 1 ? ld[x] > ld[y] : ld[x] < ld[y];
+        });
+        TileArgs ta{};
+        for (uint32_t b = 0; b < K; ++b) {
+            ta.pos_src[b] = ls[in_log[b]];
+            ta.pos_dst[b] = ld[in_log[b]];
+            if (ta.pos_src[b] >= 32 || ta.pos_dst[b] >= 32)
+                return fail(QSIM_ERR_INVALID, "layout put a tile bit above bit 31");
+        }
+        if (elem == 8 && (ta.pos_src[0] != 0 || ta.pos_dst[0] != 0))
+            return fail(QSIM_ERR_INVALID, "layout moved address bit 0");
+        for (uint32_t q = 0; q < no; ++q) ta.out_dst[q] = ld[out_log[q]];
+
         std::vector<TmStep> tm;
         std::vector<uint32_t> inner;
         tm.reserve(p.steps.size());
@@ -323,21 +414,24 @@ int prepare_passes(uint32_t M, uint32_t elem, const std::vector<Pass> &passes,
         lm.tm.n_steps = (uint32_t)tm.size();
         lm.tm.rec_words = rec_words;
         lm.tm.n_out = no;
-        std::memcpy(lm.tm.out_pos, out_pos, sizeof(out_pos));
+        std::memcpy(lm.tm.out_pos, out_log, sizeof(out_log));
+        std::memcpy(lm.tm.lam_src, ls, 64);
 
         Launch lt;
         lt.kind = Launch::TILE;
-        lt.inner_off = blob_push(pr.blob, inner.data(), inner.size() * 4);
+        lt.inner_off = push_inner(pr.blob, inner);
         lt.n_tiles = n_tiles;
+        lt.ta = ta;
         lt.ta.n_inner = n_inner;
         lt.ta.rec_words = rec_words;
         lt.ta.tb = K - 5;
         lt.ta.n_out = no;
-        std::memcpy(lt.ta.in_pos, in_pos, sizeof(in_pos));
-        std::memcpy(lt.ta.out_pos, out_pos, sizeof(out_pos));
         const uint32_t vpt = 32u >> LO;
-        for (uint32_t r = 0; r < 32; ++r)
-            lt.ta.off_r[r] = r < vpt ? (uint32_t)pdep((uint64_t)r << (LO + lt.ta.tb), in_pos, K) : 0u;
+        for (uint32_t r = 0; r < 32; ++r) {
+            const uint64_t j = (uint64_t)r << (LO + lt.ta.tb);
+            lt.ta.off_r_src[r] = r < vpt ? (uint32_t)pdep(j, ta.pos_src, K) : 0u;
+            lt.ta.off_r_dst[r] = r < vpt ? (uint32_t)pdep(j, ta.pos_dst, K) : 0u;
+        }
         pr.launches.push_back(lm);
         pr.launches.push_back(lt);
         pr.rec_bytes = std::max<size_t>(pr.rec_bytes, (size_t)n_tiles * rec_words * 4);
@@ -367,7 +461,51 @@ int prepare(qsim_state *s, const qsim_step *steps, uint64_t L, Prepared &pr) {
     } catch (const std::exception &e) {
         return fail(QSIM_ERR_INVALID, std::string("planner: ") + e.what());
     }
-    return prepare_passes(M, s->elem, passes, tg.data(), cm.data(), pr);
+    return prepare_passes(M, s->elem, passes, tg.data(), cm.data(), s->tune.outer_order, s->tune.remap, pr);
+}
+
+// Timing helpers: a launch of `kind` (0 tile, 1 map, 2 other) is bracketed
+// by two events from the state's pool when profiling is on.
+hipError_t prof_event(qsim_state *s, hipEvent_t *ev) {
+    if (!s->ev_pool.empty()) {
+        *ev = s->ev_pool.back();
+        s->ev_pool.pop_back();
+        return hipSuccess;
+    }
+    return hipEventCreate(ev);
+}
+
+hipError_t prof_begin(qsim_state *s, hipStream_t st, hipEvent_t *a) {
+    if (!s->profiling) return hipSuccess;
+    hipError_t e = prof_event(s, a);
+    if (e == hipSuccess) e = hipEventRecord(*a, st);
+    return e;
+}
+
+hipError_t prof_end(qsim_state *s, hipStream_t st, int kind, hipEvent_t a, uint64_t bytes) {
+    if (!s->profiling) return hipSuccess;
+    hipEvent_t b;
+    hipError_t e = prof_event(s, &b);
+    if (e == hipSuccess) e = hipEventRecord(b, st);
+    if (e == hipSuccess) s->timed.push_back({kind, a, b, bytes});
+    return e;
+}
+
+// Fold finished timings into the totals (waits for them).
+hipError_t prof_collect(qsim_state *s) {
+    for (auto &t : s->timed) {
+        hipError_t e = hipEventSynchronize(t.b);
+        if (e != hipSuccess) return e;
+        float ms = 0.f;
+        if ((e = hipEventElapsedTime(&ms, t.a, t.b)) != hipSuccess) return e;
+        if (t.kind == 0) { s->prof.tile_launches++; s->prof.tile_ms += ms; s->prof.tile_bytes += t.bytes; }
+        else if (t.kind == 1) { s->prof.map_launches++; s->prof.map_ms += ms; }
+        else { s->prof.other_launches++; s->prof.other_ms += ms; }
+        s->ev_pool.push_back(t.a);
+        s->ev_pool.push_back(t.b);
+    }
+    s->timed.clear();
+    return hipSuccess;
 }
 
 int enqueue(qsim_state *s, Prepared &pr, hipStream_t st) {
@@ -382,9 +520,13 @@ int enqueue(qsim_state *s, Prepared &pr, hipStream_t st) {
     s->stage.pending = true;
     uint8_t *dev = static_cast<uint8_t *>(s->plan.p);
     const uint64_t n = 1ull << s->M;
+    const uint64_t pass_bytes = 2ull * n * s->elem;
     for (Launch &l : pr.launches) {
         const void *src = s->buf[s->cur];
         void *dst = s->buf[s->cur ^ 1];
+        hipEvent_t ev_a = nullptr;
+        if ((e = prof_begin(s, st, &ev_a)) != hipSuccess) return device_fail(s, e, "profiling event");
+        const int kind = l.kind == Launch::TILE ? 0 : (l.kind == Launch::TILEMAP ? 1 : 2);
         switch (l.kind) {
             case Launch::DIRECT:
                 e = launch_direct(s->elem, src, dst, n, reinterpret_cast<const TmStep *>(dev + l.steps_off), l.n, st);
@@ -404,11 +546,13 @@ int enqueue(qsim_state *s, Prepared &pr, hipStream_t st) {
             case Launch::TILE:
                 l.ta.inner = reinterpret_cast<const uint32_t *>(dev + l.inner_off);
                 l.ta.rec = static_cast<const uint32_t *>(s->rec.p);
-                e = launch_tile(s->elem, src, dst, l.n_tiles, l.ta, st);
+                e = launch_tile(s->elem, src, dst, l.n_tiles, l.ta, s->tune.variant, s->tune.wg_per_cu, st);
                 s->cur ^= 1;
                 break;
         }
         if (e != hipSuccess) return device_fail(s, e, "kernel launch");
+        if ((e = prof_end(s, st, kind, ev_a, kind == 1 ? 0 : pass_bytes)) != hipSuccess)
+            return device_fail(s, e, "profiling event");
     }
     s->last_stream = st;
     return QSIM_OK;
@@ -490,6 +634,9 @@ void qsim_state_destroy(qsim_state *s) {
     if (!s) return;
     DeviceGuard g(s->device);
     (void)hipStreamSynchronize(s->last_stream);
+    (void)prof_collect(s);
+    for (hipEvent_t ev : s->ev_pool) (void)hipEventDestroy(ev);
+    s->ev_pool.clear();
     s->stage.release();
     s->plan.release();
     s->rec.release();
@@ -534,6 +681,35 @@ int qsim_apply_steps(qsim_state *s, const qsim_step *steps, uint64_t L, void *hi
     return enqueue(s, pr, static_cast<hipStream_t>(hip_stream));
 }
 
+int qsim_apply_tile_pass(qsim_state *s, uint64_t tile_mask, const qsim_step *steps, uint64_t L, void *hip_stream) {
+    int rc = check_state(s);
+    if (rc) return rc;
+    if ((rc = validate_steps(s->M, steps, L))) return rc;
+    const uint64_t all = (1ull << s->M) - 1ull;
+    const int K = __builtin_popcountll(tile_mask);
+    const int kmax = s->elem == 8 ? kMaxTileBits : kMaxTileBits - 1;
+    if ((tile_mask & ~all) || (tile_mask >> 32) || K < 5 || K > kmax || (s->elem == 8 && !(tile_mask & 1ull)))
+        return fail(QSIM_ERR_INVALID, "tile_mask: 5..14 bits (13 for complex128) below min(M, 32), bit 0 for complex64");
+    std::vector<uint32_t> tg(L);
+    std::vector<uint64_t> cm(L);
+    Pass p;
+    p.tile_mask = tile_mask;
+    for (uint64_t i = 0; i < L; ++i) {
+        tg[i] = steps[i].target;
+        cm[i] = steps[i].control_mask;
+        if (!((tile_mask >> tg[i]) & 1ull) && (cm[i] & tile_mask))
+            return fail(QSIM_ERR_INVALID, "step " + std::to_string(i) + " has a control in the tile but its target outside");
+        p.steps.push_back((uint32_t)i);
+    }
+    Prepared pr;
+    if ((rc = prepare_passes(s->M, s->elem, std::vector<Pass>{p}, tg.data(), cm.data(), s->tune.outer_order, false,
+                             pr)))
+        return rc;
+    DeviceGuard g(s->device);
+    if (!g.ok) return device_fail(s, hipErrorInvalidDevice, "set device");
+    return enqueue(s, pr, static_cast<hipStream_t>(hip_stream));
+}
+
 int qsim_apply_steps_plain(qsim_state *s, const qsim_step *steps, uint64_t L, void *hip_stream) {
     int rc = check_state(s);
     if (rc) return rc;
@@ -542,7 +718,11 @@ int qsim_apply_steps_plain(qsim_state *s, const qsim_step *steps, uint64_t L, vo
     DeviceGuard g(s->device);
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     for (uint64_t i = 0; i < L; ++i) {
-        hipError_t e = launch_plain_step(s->elem, s->buf[s->cur], s->M, steps[i].target, steps[i].control_mask, st);
+        hipEvent_t ev_a = nullptr;
+        hipError_t e = prof_begin(s, st, &ev_a);
+        if (e == hipSuccess)
+            e = launch_plain_step(s->elem, s->buf[s->cur], s->M, steps[i].target, steps[i].control_mask, st);
+        if (e == hipSuccess) e = prof_end(s, st, 2, ev_a, 0);
         if (e != hipSuccess) return device_fail(s, e, "plain step launch");
     }
     s->last_stream = st;
@@ -643,6 +823,28 @@ int qsim_plan_describe(uint32_t M, qsim_dtype dtype, const qsim_step *steps, uin
         for (uint32_t s : passes[p].steps)
             if (order) order[k++] = s;
     }
+    return QSIM_OK;
+}
+
+int qsim_state_profile(qsim_state *s, int enable) {
+    int rc = check_state(s);
+    if (rc) return rc;
+    DeviceGuard g(s->device);
+    hipError_t e = prof_collect(s);
+    if (e != hipSuccess) return device_fail(s, e, "profiling");
+    s->profiling = enable != 0;
+    if (enable) s->prof = qsim_profile{};
+    return QSIM_OK;
+}
+
+int qsim_state_profile_read(qsim_state *s, qsim_profile *out) {
+    int rc = check_state(s);
+    if (rc) return rc;
+    if (!out) return fail(QSIM_ERR_INVALID, "out is NULL");
+    DeviceGuard g(s->device);
+    hipError_t e = prof_collect(s);
+    if (e != hipSuccess) return device_fail(s, e, "profiling");
+    *out = s->prof;
     return QSIM_OK;
 }
 

@@ -101,24 +101,36 @@ __device__ __forceinline__ void init_planes(uint32_t (&w)[kPlanes], uint32_t tid
 // Walk the inner steps (reverse execution order) on the bit-planes.  With
 // FLAGS the bit i of the tile record says whether inner step i's outside
 // controls hold for this tile; without, every step's controls lie inside.
+// Steps are fetched eight at a time with one scalar load (the step array is
+// padded to a multiple of eight entries).
+__device__ __forceinline__ void apply_inner(uint32_t (&w)[kPlanes], uint32_t d) {
+    uint32_t m = d >> 16;
+    uint32_t x = 0xFFFFFFFFu;
+    while (m) {
+        const uint32_t c = (uint32_t)__builtin_ctz(m);
+        m &= m - 1u;
+        x &= w[c];
+    }
+    w[d & 15u] ^= x;
+}
+
 template <bool FLAGS>
 __device__ __forceinline__ void walk_inner(uint32_t (&w)[kPlanes], const uint32_t *__restrict__ inner,
                                            uint32_t n_inner, const uint32_t *__restrict__ flags) {
-    uint32_t fw = 0;
-    for (uint32_t i = 0; i < n_inner; ++i) {
+    for (uint32_t i0 = 0; i0 < n_inner; i0 += 8u) {
+        uint32_t d[8];
+#pragma unroll
+        for (uint32_t j = 0; j < 8u; ++j) d[j] = uni(inner[i0 + j]);
+        uint32_t fb;
         if (FLAGS) {
-            if ((i & 31u) == 0u) fw = uni(flags[i >> 5]);
-            if (!((fw >> (i & 31u)) & 1u)) continue;
+            fb = uni(flags[i0 >> 5]) >> (i0 & 31u);
+        } else {
+            const uint32_t rem = n_inner - i0;
+            fb = rem >= 8u ? 0xFFu : ((1u << rem) - 1u);
         }
-        const uint32_t d = uni(inner[i]);
-        uint32_t m = d >> 16;
-        uint32_t x = 0xFFFFFFFFu;
-        while (m) {
-            const uint32_t c = (uint32_t)__builtin_ctz(m);
-            m &= m - 1u;
-            x &= w[c];
-        }
-        w[d & 15u] ^= x;
+#pragma unroll
+        for (uint32_t j = 0; j < 8u; ++j)
+            if ((fb >> j) & 1u) apply_inner(w, d[j]);
     }
 }
 
@@ -126,30 +138,47 @@ __device__ __forceinline__ uint32_t src_of(const uint32_t (&w)[kPlanes], uint32_
     return (w[p & 15u] >> ((p >> 4) * 16u)) & 0xFFFFu;
 }
 
-// One tile: load source tile -> LDS, walk, gather, store.  `src_base` and
-// `dst_base` are element offsets of the tiles' outer bits.
-template <int ELEM, bool FLAGS>
-__device__ __forceinline__ void tile_body(const vec16 *__restrict__ src, vec16 *__restrict__ dst,
-                                          uint64_t src_base, uint64_t dst_base,
-                                          const TileArgs &a, const uint32_t *__restrict__ flags,
-                                          vec16 *lds) {
+// Element offset of the thread bits of the tile index, for the physical
+// positions `pos` of the tile-index bits.
+template <int ELEM>
+__device__ __forceinline__ uint32_t thread_offset(const uint8_t *pos, uint32_t tb, uint32_t tid) {
     constexpr uint32_t LO = (ELEM == 8) ? 1u : 0u;
-    constexpr uint32_t VPT = 32u >> LO;            // 16-byte vectors per thread
-    constexpr uint32_t EPV = 16u / ELEM;           // entries per vector
-    const uint32_t tid = threadIdx.x;
-    const uint32_t tb = a.tb;
-
-    // element offset of the thread bits of the tile index
     uint32_t off_t = 0;
     for (uint32_t b = 0; b < tb; ++b)
-        if ((tid >> b) & 1u) off_t |= 1u << a.in_pos[LO + b];
+        if ((tid >> b) & 1u) off_t |= 1u << pos[LO + b];
+    return off_t;
+}
 
-    vec16 v[VPT];
+// Physical address (write layout) of the outer bits of output tile `tile`.
+__device__ __forceinline__ uint64_t outer_address(const TileArgs &a, uint64_t tile) {
+    uint64_t base = 0;
+    for (uint32_t q = 0; q < a.n_out; ++q)
+        if ((tile >> q) & 1u) base |= 1ull << a.out_dst[q];
+    return base;
+}
+
+template <int ELEM>
+__device__ __forceinline__ void load_tile(vec16 (&v)[32u >> ((ELEM == 8) ? 1 : 0)], const vec16 *__restrict__ src,
+                                          uint64_t base, const TileArgs &a) {
+    constexpr uint32_t VPT = 32u >> ((ELEM == 8) ? 1 : 0);
+    constexpr uint32_t EPV = 16u / ELEM;
 #pragma unroll
-    for (uint32_t r = 0; r < VPT; ++r) {
-        const uint64_t e = src_base + off_t + a.off_r[r];
-        v[r] = ld_nt(src + e / EPV);
-    }
+    for (uint32_t r = 0; r < VPT; ++r) v[r] = ld_nt(src + (base + a.off_r_src[r]) / EPV);
+}
+
+// Walk, stage the loaded tile in LDS, gather and store one output tile.
+// `v` holds the source tile's vectors on entry; when `next_base` is not
+// ~0 the loads of the next source tile are issued into `v` as soon as the
+// current one is in LDS, so they overlap the gather, the stores and the
+// next tile's walk.
+template <int ELEM, bool FLAGS>
+__device__ __forceinline__ void tile_step(vec16 (&v)[32u >> ((ELEM == 8) ? 1 : 0)], const vec16 *__restrict__ src,
+                                          vec16 *__restrict__ dst, uint64_t dst_base, uint64_t next_base,
+                                          const TileArgs &a, const uint32_t *__restrict__ flags, vec16 *lds) {
+    constexpr uint32_t VPT = 32u >> ((ELEM == 8) ? 1 : 0);
+    constexpr uint32_t EPV = 16u / ELEM;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t tb = a.tb;
 
     uint32_t w[kPlanes];
     init_planes<ELEM>(w, tid, tb);
@@ -159,6 +188,7 @@ __device__ __forceinline__ void tile_body(const vec16 *__restrict__ src, vec16 *
 #pragma unroll
     for (uint32_t r = 0; r < VPT; ++r) lds[tid | (r << tb)] = v[r];
     __syncthreads();
+    if (next_base != ~0ull) load_tile<ELEM>(v, src, next_base, a);
 
     if (ELEM == 8) {
         const uint2 *l2 = reinterpret_cast<const uint2 *>(lds);
@@ -166,30 +196,55 @@ __device__ __forceinline__ void tile_body(const vec16 *__restrict__ src, vec16 *
         for (uint32_t r = 0; r < VPT; ++r) {
             const uint2 e0 = l2[src_of(w, 2u * r)];
             const uint2 e1 = l2[src_of(w, 2u * r + 1u)];
-            const uint64_t e = dst_base + off_t + a.off_r[r];
-            st_nt(dst + e / EPV, make_uint4(e0.x, e0.y, e1.x, e1.y));
+            st_nt(dst + (dst_base + a.off_r_dst[r]) / EPV, make_uint4(e0.x, e0.y, e1.x, e1.y));
         }
     } else {
 #pragma unroll
         for (uint32_t r = 0; r < VPT; ++r) {
             const vec16 e0 = lds[src_of(w, r)];
-            const uint64_t e = dst_base + off_t + a.off_r[r];
-            st_nt(dst + e / EPV, e0);
+            st_nt(dst + (dst_base + a.off_r_dst[r]) / EPV, e0);
         }
     }
 }
 
+// Fused tile pass.  DEPTH = 0: one tile per workgroup.  DEPTH >= 1: a grid
+// sized to the resident workgroups walks tiles blockIdx.x, blockIdx.x +
+// gridDim.x, ...; the loads of each tile are issued DEPTH tiles ahead, into
+// one of DEPTH register buffers, so they overlap the gathers, stores and
+// walks of the tiles in between.
 template <int ELEM>
+__device__ __forceinline__ uint64_t rec_base(const uint32_t *rec) {
+    return (uint64_t)uni(rec[0]) | ((uint64_t)uni(rec[1]) << 32);
+}
+
+template <int ELEM, int DEPTH>
 __global__ void __launch_bounds__(512) k_tile(const vec16 *__restrict__ src, vec16 *__restrict__ dst,
-                                              TileArgs a) {
+                                              TileArgs a, uint64_t n_tiles) {
     extern __shared__ vec16 lds[];
-    const uint64_t tile = blockIdx.x;
-    uint64_t dst_base = 0;
-    for (uint32_t q = 0; q < a.n_out; ++q)
-        if ((tile >> q) & 1u) dst_base |= 1ull << a.out_pos[q];
-    const uint32_t *rec = a.rec + tile * a.rec_words;
-    const uint64_t src_base = (uint64_t)uni(rec[0]) | ((uint64_t)uni(rec[1]) << 32);
-    tile_body<ELEM, true>(src, dst, src_base, dst_base, a, rec + 2, lds);
+    constexpr uint32_t VPT = 32u >> ((ELEM == 8) ? 1 : 0);
+    constexpr int NB = DEPTH > 0 ? DEPTH : 1;
+    const uint32_t off_src = thread_offset<ELEM>(a.pos_src, a.tb, threadIdx.x);
+    const uint32_t off_dst = thread_offset<ELEM>(a.pos_dst, a.tb, threadIdx.x);
+    const uint64_t stride = DEPTH > 0 ? gridDim.x : n_tiles;
+    vec16 v[NB][VPT];
+#pragma unroll
+    for (int d = 0; d < NB; ++d) {
+        const uint64_t t = blockIdx.x + (uint64_t)d * stride;
+        if (t < n_tiles) load_tile<ELEM>(v[d], src, rec_base<ELEM>(a.rec + t * a.rec_words) + off_src, a);
+    }
+    for (uint64_t first = blockIdx.x;; first += (uint64_t)NB * stride) {
+#pragma unroll
+        for (int d = 0; d < NB; ++d) {
+            const uint64_t tile = first + (uint64_t)d * stride;
+            if (tile >= n_tiles) return;   // uniform over the workgroup
+            const uint64_t next = tile + (uint64_t)NB * stride;
+            const uint64_t next_base =
+                (DEPTH > 0 && next < n_tiles) ? rec_base<ELEM>(a.rec + next * a.rec_words) + off_src : ~0ull;
+            tile_step<ELEM, true>(v[d], src, dst, outer_address(a, tile) + off_dst, next_base, a,
+                                  a.rec + tile * a.rec_words + 2, lds);
+            __syncthreads();
+        }
+    }
 }
 
 // Whole state in one workgroup's LDS: one tile, every step is inner.
@@ -197,7 +252,11 @@ template <int ELEM>
 __global__ void __launch_bounds__(512) k_small(const vec16 *__restrict__ src, vec16 *__restrict__ dst,
                                                TileArgs a) {
     extern __shared__ vec16 lds[];
-    tile_body<ELEM, false>(src, dst, 0, 0, a, nullptr, lds);
+    constexpr uint32_t VPT = 32u >> ((ELEM == 8) ? 1 : 0);
+    vec16 v[VPT];
+    load_tile<ELEM>(v, src, thread_offset<ELEM>(a.pos_src, a.tb, threadIdx.x), a);
+    tile_step<ELEM, false>(v, src, dst, thread_offset<ELEM>(a.pos_dst, a.tb, threadIdx.x), ~0ull, a, nullptr,
+                           lds);
 }
 
 // Per-tile record of a pass: source tile address and the outside-control
@@ -210,6 +269,8 @@ __global__ void __launch_bounds__(256) k_tilemap(TileMapArgs a) {
         if ((tile >> q) & 1u) A |= 1ull << a.out_pos[q];
     uint32_t *rec = a.rec + tile * a.rec_words;
     uint32_t word = 0, k = 0;
+    // A is the logical outer address; the record holds its physical
+    // address in the layout the pass reads.
     for (uint32_t s = 0; s < a.n_steps; ++s) {
         const uint64_t cm = ((uint64_t)uni((uint32_t)(a.steps[s].cm >> 32)) << 32) |
                             uni((uint32_t)a.steps[s].cm);
@@ -225,8 +286,14 @@ __global__ void __launch_bounds__(256) k_tilemap(TileMapArgs a) {
         }
     }
     if (k & 31u) rec[2 + (k >> 5)] = word;
-    rec[0] = (uint32_t)A;
-    rec[1] = (uint32_t)(A >> 32);
+    uint64_t P = 0;
+    while (A) {
+        const uint32_t b = (uint32_t)__builtin_ctzll(A);
+        A &= A - 1;
+        P |= 1ull << a.lam_src[b];
+    }
+    rec[0] = (uint32_t)P;
+    rec[1] = (uint32_t)(P >> 32);
 }
 
 // Direct gather: each thread walks its own row backwards through every step
@@ -271,11 +338,25 @@ __global__ void __launch_bounds__(256) k_plain_step(uint8_t *__restrict__ buf, u
     }
 }
 
+// Plain streaming copy: each thread moves four 16-byte vectors per
+// iteration with all four loads in flight before the stores.
 __global__ void __launch_bounds__(256) k_copy(const vec16 *__restrict__ src, vec16 *__restrict__ dst,
                                               uint64_t nvec) {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvec; i += stride)
-        st_nt(dst + i, ld_nt(src + i));
+    const uint64_t chunk = (uint64_t)blockDim.x * 4u;
+    const uint64_t stride = (uint64_t)gridDim.x * chunk;
+    for (uint64_t base = (uint64_t)blockIdx.x * chunk; base < nvec; base += stride) {
+        vec16 v[4];
+#pragma unroll
+        for (uint32_t k = 0; k < 4u; ++k) {
+            const uint64_t i = base + threadIdx.x + (uint64_t)k * blockDim.x;
+            if (i < nvec) v[k] = ld_nt(src + i);
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < 4u; ++k) {
+            const uint64_t i = base + threadIdx.x + (uint64_t)k * blockDim.x;
+            if (i < nvec) st_nt(dst + i, v[k]);
+        }
+    }
 }
 
 template <typename KernelT>
@@ -322,21 +403,56 @@ hipError_t launch_tilemap(const TileMapArgs &a, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_tile(uint32_t elem, const void *src, void *dst, uint64_t n_tiles,
-                       const TileArgs &a, hipStream_t st) {
-    const size_t lds = (size_t)elem << (a.tb + 5);
+// Resident workgroups of a kernel on the current device (for the persistent
+// grid), cached per kernel and LDS size.
+template <typename KernelT>
+uint64_t resident_blocks(KernelT kernel, uint32_t threads, size_t lds) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kernel), (int)threads,
+                                                     lds) != hipSuccess)
+        return 0;
+    return (uint64_t)cus * (uint64_t)(per_cu > 0 ? per_cu : 1);
+}
+
+template <int ELEM, int DEPTH>
+hipError_t launch_tile_t(const void *src, void *dst, uint64_t n_tiles, const TileArgs &a, uint32_t wg_per_cu,
+                         hipStream_t st) {
+    const size_t lds = (size_t)ELEM << (a.tb + 5);
     const uint32_t threads = 1u << a.tb;
     hipError_t e;
-    if (elem == 8) {
-        if ((e = allow_lds(k_tile<8>, lds)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_tile<8>, dim3((uint32_t)n_tiles), dim3(threads), lds, st,
-                           (const vec16 *)src, (vec16 *)dst, a);
-    } else {
-        if ((e = allow_lds(k_tile<16>, lds)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_tile<16>, dim3((uint32_t)n_tiles), dim3(threads), lds, st,
-                           (const vec16 *)src, (vec16 *)dst, a);
+    if ((e = allow_lds(k_tile<ELEM, DEPTH>, lds)) != hipSuccess) return e;
+    uint64_t grid = n_tiles;
+    if (DEPTH > 0) {
+        uint64_t r = 0;
+        if (wg_per_cu) {
+            int dev = 0, cus = 0;
+            if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+            if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+            r = (uint64_t)cus * wg_per_cu;
+        } else {
+            r = resident_blocks(k_tile<ELEM, DEPTH>, threads, lds);
+        }
+        if (r > 0 && r < grid) grid = r;
     }
+    hipLaunchKernelGGL((k_tile<ELEM, DEPTH>), dim3((uint32_t)grid), dim3(threads), lds, st,
+                       (const vec16 *)src, (vec16 *)dst, a, n_tiles);
     return hipGetLastError();
+}
+
+// variant 0: one tile per workgroup; 1: persistent, loads one tile ahead;
+// 2: persistent, loads two tiles ahead (8-byte entries only: the two
+// register buffers of 16-byte entries would not fit).
+hipError_t launch_tile(uint32_t elem, const void *src, void *dst, uint64_t n_tiles, const TileArgs &a,
+                       uint32_t variant, uint32_t wg_per_cu, hipStream_t st) {
+    if (elem == 8) {
+        if (variant == 2) return launch_tile_t<8, 2>(src, dst, n_tiles, a, wg_per_cu, st);
+        if (variant == 1) return launch_tile_t<8, 1>(src, dst, n_tiles, a, wg_per_cu, st);
+        return launch_tile_t<8, 0>(src, dst, n_tiles, a, wg_per_cu, st);
+    }
+    if (variant >= 1) return launch_tile_t<16, 1>(src, dst, n_tiles, a, wg_per_cu, st);
+    return launch_tile_t<16, 0>(src, dst, n_tiles, a, wg_per_cu, st);
 }
 
 hipError_t launch_plain_step(uint32_t elem, void *buf, uint32_t M, uint32_t target,
@@ -355,10 +471,13 @@ hipError_t launch_plain_step(uint32_t elem, void *buf, uint32_t M, uint32_t targ
 
 hipError_t launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t st) {
     const uint64_t nvec = bytes / 16;
+    if (nvec == 0) return hipSuccess;
     const uint32_t bs = 256;
-    uint64_t grid = (nvec + bs - 1) / bs;
-    if (grid > 256ull * 64) grid = 256ull * 64;
-    if (grid == 0) return hipSuccess;
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    uint64_t grid = (nvec + bs * 4 - 1) / (bs * 4);
+    const uint64_t cap = (uint64_t)cus * 8;
+    if (grid > cap) grid = cap;
     hipLaunchKernelGGL(k_copy, dim3((uint32_t)grid), dim3(bs), 0, st, (const vec16 *)src, (vec16 *)dst, nvec);
     return hipGetLastError();
 }

@@ -81,7 +81,6 @@ std::vector<Pass> plan_passes(uint32_t M, const uint32_t *target, const uint64_t
 
     // state: 0 = pending, 1 = done in an earlier pass, 2 = taken now, 3 = blocked now
     std::vector<uint8_t> state(L, 0);
-    uint64_t remaining = L;
     std::vector<uint32_t> pending;
     pending.reserve(L);
     for (uint64_t s = 0; s < L; ++s) pending.push_back((uint32_t)s);
@@ -101,8 +100,9 @@ std::vector<Pass> plan_passes(uint32_t M, const uint32_t *target, const uint64_t
         return popc(allowed & ~I & ~U) >= K - popc(I);
     };
 
-    while (remaining > 0) {
-        uint64_t I = base;
+    // One pass over the pending steps, starting from tile mask `start`.
+    auto build_pass = [&](uint64_t start) {
+        uint64_t I = start;
         uint64_t U = 0;
         std::vector<uint32_t> taken;
         for (uint32_t s : pending) {
@@ -148,8 +148,6 @@ std::vector<Pass> plan_passes(uint32_t M, const uint32_t *target, const uint64_t
         Pass p;
         p.tile_mask = I;
         p.steps = taken;
-        passes.push_back(std::move(p));
-        remaining -= taken.size();
         std::vector<uint32_t> next;
         next.reserve(pending.size());
         for (uint32_t s : pending) {
@@ -157,6 +155,23 @@ std::vector<Pass> plan_passes(uint32_t M, const uint32_t *target, const uint64_t
             else { state[s] = 0; next.push_back(s); }
         }
         pending.swap(next);
+        return p;
+    };
+
+    // The first pass reads, and the last pass writes, the state in its
+    // natural bit order, so their tiles must hold the low address bits that
+    // make each tile a set of long contiguous runs.  Passes in between see
+    // layouts permuted to suit them and may start from fewer low bits.
+    const int mid_low = std::min<int>(std::max(cfg.mid_low_bits > 0 ? cfg.mid_low_bits : low, 1), low);
+    const uint64_t mid_base = (1ull << mid_low) - 1ull;
+    while (!pending.empty()) passes.push_back(build_pass(passes.empty() ? base : mid_base));
+    if ((passes.back().tile_mask & base) != base) {
+        // Re-plan the last pass's steps from the full base.
+        Pass last = passes.back();
+        passes.pop_back();
+        for (uint32_t s : last.steps) state[s] = 0;
+        pending = last.steps;
+        while (!pending.empty()) passes.push_back(build_pass(base));
     }
     return passes;
 }

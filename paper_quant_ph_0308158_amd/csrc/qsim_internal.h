@@ -34,6 +34,13 @@ __host__ __device__ inline uint32_t pack_inner(uint32_t tj, uint32_t icm) {
 }
 
 // Arguments of one pass of the fused tile kernel (passed by value).
+//
+// Between passes the state may be stored with its address bits permuted (a
+// layout): logical bit b of a row address lives at physical bit lam(b).  A
+// pass reads its source tiles in one layout and writes its output tiles in
+// the next, so each side has its own physical positions for the tile-index
+// bits (pos_src / pos_dst) and its own offset tables.  The walk itself works
+// on logical tile indices and does not see layouts.
 struct TileArgs {
     const uint32_t *inner;  // packed inner steps in reverse execution order
     const uint32_t *rec;    // per-tile records from the tile-map kernel (or null)
@@ -41,9 +48,11 @@ struct TileArgs {
     uint32_t rec_words;     // 2 + ceil(n_inner / 32)
     uint32_t tb;            // log2(threads per workgroup); tile bits = tb + 5
     uint32_t n_out;         // outer bits (M - tile bits)
-    uint32_t off_r[32];     // element offset of the tile-index bits above the thread bits, per r
-    uint8_t in_pos[16];     // address bit of tile-index bit b
-    uint8_t out_pos[kMaxOuterBits];  // address bit of outer-index bit q
+    uint32_t off_r_src[32]; // element offset of the tile-index bits above the thread bits, per r (read)
+    uint32_t off_r_dst[32]; // same for the write layout
+    uint8_t pos_src[16];    // physical bit of tile-index bit b in the read layout
+    uint8_t pos_dst[16];    // physical bit of tile-index bit b in the write layout
+    uint8_t out_dst[kMaxOuterBits];  // physical bit (write layout) of outer-index bit q
 };
 
 struct TileMapArgs {
@@ -54,7 +63,8 @@ struct TileMapArgs {
     uint32_t rec_words;
     uint32_t n_out;
     uint32_t pad;
-    uint8_t out_pos[kMaxOuterBits];
+    uint8_t out_pos[kMaxOuterBits];  // logical bit of outer-index bit q
+    uint8_t lam_src[64];             // physical bit of logical bit b in the read layout
 };
 
 // Host-side plan of the fused path.
@@ -65,7 +75,8 @@ struct Pass {
 
 struct PlanConfig {
     int tile_bits = 13;
-    int low_bits = 5;
+    int low_bits = 5;       // low address bits in the tiles of the first and last pass
+    int mid_low_bits = 0;   // same for the passes in between (0 = low_bits)
     int max_seg_steps = 1024;
     bool reorder = true;
 };
@@ -80,8 +91,8 @@ hipError_t launch_direct(uint32_t elem, const void *src, void *dst, uint64_t n,
 hipError_t launch_small(uint32_t elem, const void *src, void *dst, uint32_t M,
                         const TileArgs &a, hipStream_t st);
 hipError_t launch_tilemap(const TileMapArgs &a, hipStream_t st);
-hipError_t launch_tile(uint32_t elem, const void *src, void *dst, uint64_t n_tiles,
-                       const TileArgs &a, hipStream_t st);
+hipError_t launch_tile(uint32_t elem, const void *src, void *dst, uint64_t n_tiles, const TileArgs &a,
+                       uint32_t variant, uint32_t wg_per_cu, hipStream_t st);
 hipError_t launch_plain_step(uint32_t elem, void *buf, uint32_t M, uint32_t target,
                              uint64_t cmask, hipStream_t st);
 hipError_t launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t st);

@@ -34,7 +34,7 @@ EXPORTS = (
     "qsim_state_elem_bytes", "qsim_state_current", "qsim_write_portion", "qsim_apply_steps",
     "qsim_apply_steps_plain", "qsim_read_portion", "qsim_read_portion_async", "qsim_apply_batch",
     "qsim_state_set_tuning", "qsim_plan_describe", "qsim_copy_bytes", "qsim_last_error",
-    "qsim_version",
+    "qsim_version", "qsim_state_profile", "qsim_state_profile_read", "qsim_apply_tile_pass",
 )
 
 
@@ -44,10 +44,23 @@ class QsimError(RuntimeError):
         self.code = code
 
 
+class Profile(ctypes.Structure):
+    _fields_ = [("tile_launches", ctypes.c_uint64), ("tile_ms", ctypes.c_double),
+                ("tile_bytes", ctypes.c_uint64), ("map_launches", ctypes.c_uint64),
+                ("map_ms", ctypes.c_double), ("other_launches", ctypes.c_uint64),
+                ("other_ms", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("tile_bits", ctypes.c_uint32), ("low_bits", ctypes.c_uint32),
                 ("max_seg_steps", ctypes.c_uint32), ("reorder", ctypes.c_uint32),
-                ("small_bits", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
+                ("small_bits", ctypes.c_uint32), ("kernel_variant", ctypes.c_uint32),
+                ("wg_per_cu", ctypes.c_uint32), ("outer_order", ctypes.c_uint32),
+                ("remap", ctypes.c_uint32), ("mid_low_bits", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 2)]
 
 
 def _load() -> ctypes.CDLL:
@@ -82,6 +95,9 @@ def _load() -> ctypes.CDLL:
         "qsim_copy_bytes": (i32, [vp, vp, u64, vp]),
         "qsim_last_error": (ctypes.c_char_p, []),
         "qsim_version": (ctypes.c_char_p, []),
+        "qsim_state_profile": (i32, [vp, i32]),
+        "qsim_apply_tile_pass": (i32, [vp, u64, vp, u64, vp]),
+        "qsim_state_profile_read": (i32, [vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -160,7 +176,7 @@ def _tuning_struct(tuning: Optional[dict]) -> Optional[Tuning]:
         return None
     t = Tuning()
     for k, v in tuning.items():
-        if k == "reorder" and isinstance(v, bool):
+        if k in ("reorder", "remap") and isinstance(v, bool):
             v = 1 if v else 2
         setattr(t, k, int(v))
     return t
@@ -249,10 +265,23 @@ class State:
         _check(_lib.qsim_apply_steps(self._h, steps.ctypes.data if len(steps) else None, len(steps),
                                      ctypes.c_void_p(_stream_ptr(stream))))
 
+    def apply_tile_pass(self, tile_mask: int, target, cmask, stream=None):
+        st = pack_steps(target, cmask)
+        _check(_lib.qsim_apply_tile_pass(self._h, int(tile_mask), st.ctypes.data if len(st) else None,
+                                         len(st), ctypes.c_void_p(_stream_ptr(stream))))
+
     def apply_plain(self, target, cmask, stream=None):
         st = pack_steps(target, cmask)
         _check(_lib.qsim_apply_steps_plain(self._h, st.ctypes.data if len(st) else None, len(st),
                                            ctypes.c_void_p(_stream_ptr(stream))))
+
+    def profile(self, enable: bool = True):
+        _check(_lib.qsim_state_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        p = Profile()
+        _check(_lib.qsim_state_profile_read(self._h, ctypes.byref(p)))
+        return p.as_dict()
 
     def set_tuning(self, tuning: Optional[dict]):
         t = _tuning_struct(tuning)

@@ -80,13 +80,16 @@ def _check_plan(M, dtype, tg, cm, tuning):
     L = len(tg)
     assert sorted(order.tolist()) == list(range(L))
     assert int(lens.sum()) == L
-    K = min(tuning.get("tile_bits", 13 if dtype == "c64" else 12), M)
+    K = min(tuning.get("tile_bits", 13), M)
     low = min(tuning.get("low_bits", 5 if dtype == "c64" else 4), K)
     cap = tuning.get("max_seg_steps", 1024)
+    mid = tuning.get("mid_low_bits", 2)
+    mid = low if (tuning.get("remap", True) is False or mid > low) else mid
     pos = 0
     for p, (I, n) in enumerate(zip(masks.tolist(), lens.tolist())):
         assert bin(I).count("1") == K, "a tile always has exactly K bits"
-        assert I & ((1 << low) - 1) == (1 << low) - 1, "tile must hold the low address bits"
+        need = low if p in (0, len(masks) - 1) else mid
+        assert I & ((1 << need) - 1) == (1 << need) - 1, "tile must hold the low address bits"
         assert I < (1 << M)
         assert 1 <= n <= cap
         for s in order[pos:pos + n]:

@@ -92,6 +92,13 @@ def test_sizes_default_tuning(q, M, dt):
     (4, 17, np.complex64, {"tile_bits": 14}),
     (5, 17, np.complex128, {"tile_bits": 13}),
     (6, 18, np.complex64, {"tile_bits": 12, "low_bits": 8}),
+    (7, 19, np.complex64, {"tile_bits": 9, "remap": False, "small_bits": 5}),
+    (8, 19, np.complex128, {"tile_bits": 8, "remap": True, "outer_order": 2, "small_bits": 5}),
+    (9, 20, np.complex64, {"tile_bits": 13, "kernel_variant": 2}),
+    (11, 21, np.complex64, {"tile_bits": 14, "kernel_variant": 3}),
+    (12, 19, np.complex64, {"tile_bits": 10, "kernel_variant": 3, "wg_per_cu": 2}),
+    (13, 18, np.complex128, {"tile_bits": 12, "kernel_variant": 1}),
+    (10, 17, np.complex128, {"tile_bits": 11, "kernel_variant": 2, "wg_per_cu": 1, "remap": False}),
 ])
 def test_many_passes(q, seed, M, dt, tuning):
     """Small tiles force many passes, outer steps and tile relabelling."""
@@ -100,6 +107,31 @@ def test_many_passes(q, seed, M, dt, tuning):
     k1 = W.gaussian_state(rng, M, dt)
     say("many passes", seed, M, tuning)
     assert_same(run_gpu(q, M, k1, tg, cm, tuning), oracle.apply(M, k1, tg, cm), str(tuning))
+
+
+def test_tile_pass_entry(q):
+    """qsim_apply_tile_pass: one pass with a caller-chosen tile mask."""
+    rng = np.random.default_rng(12)
+    M = 18
+    I = 0x1F | (1 << 7) | (1 << 9) | (1 << 12) | (1 << 15) | (1 << 17) | (1 << 16) | (1 << 10) | (1 << 6)
+    tg, cm = [], []
+    while len(tg) < 40:
+        t, c = W.random_steps(rng, M, 1, (0, 3))
+        if (I >> int(t[0])) & 1 or not (int(c[0]) & I):
+            tg.append(int(t[0])); cm.append(int(c[0]))
+    tg = np.array(tg, dtype=np.uint32); cm = np.array(cm, dtype=np.uint64)
+    k1 = W.gaussian_state(rng, M, np.complex64)
+    say("tile pass entry")
+    with q.State(M, "c64") as s:
+        s.write(k1)
+        s.apply_tile_pass(I, tg, cm, stream=0)
+        assert_same(s.read(), oracle.apply(M, k1, tg, cm), "tile pass")
+        with pytest.raises(q.QsimError):
+            bad_t = [int(b) for b in range(M) if not (I >> b) & 1][0]
+            s.apply_tile_pass(I, [bad_t], [1], stream=0)
+        t0, c0 = W.empty_steps()
+        s.apply_tile_pass(I, t0, c0, stream=0)
+        assert_same(s.read(), oracle.apply(M, k1, tg, cm), "empty tile pass")
 
 
 def test_special_values(q):
