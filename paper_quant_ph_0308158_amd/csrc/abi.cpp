@@ -12,6 +12,8 @@
 #include <new>
 #include <string>
 #include <vector>
+#include <unordered_set>
+#include <thread>
 
 #include "../../include/qsim.h"
 #include "qsim_internal.h"
@@ -566,6 +568,260 @@ int check_state(const qsim_state *s) {
 
 }  // namespace
 
+namespace {
+
+// ------------------------------------------------------------ batched mode
+
+// Process-wide workspace of the batched launch (one batch in flight at a
+// time; a new batch waits for the previous one to finish with its buffers).
+struct BatchWorkspace {
+    std::mutex mu;
+    DevBuf ws;          // counters, items, pass and circuit descriptors, step arrays
+    DevBuf rec;         // tile-map records of every pass
+    HostStage stage;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+    uint32_t *ctr_dev = nullptr;
+    int last_status = QSIM_OK;
+};
+
+BatchWorkspace &batch_ws() {
+    static BatchWorkspace w;
+    return w;
+}
+
+// Wait for the last batched launch and read its error flag.
+int batch_collect(BatchWorkspace &w) {
+    if (!w.pending) return w.last_status;
+    w.pending = false;
+    hipError_t e = hipEventSynchronize(w.done);
+    if (e != hipSuccess) return w.last_status = fail(QSIM_ERR_DEVICE, std::string("batch: ") + hipGetErrorString(e));
+    uint32_t hdr[kBatchCtrHeader];
+    e = hipMemcpy(hdr, w.ctr_dev, sizeof(hdr), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return w.last_status = fail(QSIM_ERR_DEVICE, std::string("batch: ") + hipGetErrorString(e));
+    if (hdr[2]) return w.last_status = fail(QSIM_ERR_DEVICE, "batch: a dependency wait timed out; results are invalid");
+    return w.last_status = QSIM_OK;
+}
+
+int batch_status() {
+    BatchWorkspace &w = batch_ws();
+    std::lock_guard<std::mutex> lk(w.mu);
+    return batch_collect(w);
+}
+
+// Per-circuit host preparation (run in parallel over circuits).
+struct BatchCircuitPlan {
+    Prepared pr;                 // blob of this circuit + its launches
+    bool small = false, direct = false;
+    int rc = QSIM_OK;
+    std::string err;
+};
+
+int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, const uint64_t *Ls, uint32_t n,
+                  hipStream_t st) {
+    const uint32_t elem = states[0]->elem;
+    const uint32_t tb = elem == 8 ? 8u : 7u;      // 2^13 (8 B) / 2^12 (16 B) entries per tile
+    const uint32_t Kb = tb + 5;
+    const uint32_t threads = 1u << tb;
+
+    // 1. plan every circuit (host threads)
+    std::vector<BatchCircuitPlan> plans(n);
+    auto plan_one = [&](uint32_t c) {
+        qsim_state *s = states[c];
+        const uint64_t L = Ls[c];
+        BatchCircuitPlan &bp = plans[c];
+        if (L == 0) return;
+        if (s->M <= 4) {
+            bp.direct = true;
+            prepare_direct(steps[c], L, bp.pr);
+        } else if (s->M <= Kb) {
+            bp.small = true;
+            prepare_small(s->M, elem, steps[c], L, bp.pr);
+        } else {
+            std::vector<uint32_t> tg(L);
+            std::vector<uint64_t> cm(L);
+            for (uint64_t i = 0; i < L; ++i) {
+                tg[i] = steps[c][i].target;
+                cm[i] = steps[c][i].control_mask;
+            }
+            PlanConfig pc = plan_config(s->tune);
+            pc.tile_bits = (int)Kb;
+            pc.low_bits = std::min(pc.low_bits, (int)Kb);
+            pc.mid_low_bits = std::min(pc.mid_low_bits, pc.low_bits);
+            try {
+                std::vector<Pass> passes = plan_passes(s->M, tg.data(), cm.data(), L, pc);
+                bp.rc = prepare_passes(s->M, elem, passes, tg.data(), cm.data(), s->tune.outer_order, s->tune.remap,
+                                       bp.pr);
+                if (bp.rc) bp.err = g_err;
+            } catch (const std::exception &e) {
+                bp.rc = QSIM_ERR_INVALID;
+                bp.err = std::string("planner: ") + e.what();
+            }
+        }
+    };
+    {
+        const uint32_t hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        const uint32_t nt = std::min<uint32_t>(hw, (n + 63) / 64);
+        std::atomic<uint32_t> next{0};
+        auto worker = [&]() {
+            for (uint32_t c; (c = next.fetch_add(1)) < n;) plan_one(c);
+        };
+        std::vector<std::thread> pool;
+        for (uint32_t t = 1; t < nt; ++t) pool.emplace_back(worker);
+        worker();
+        for (auto &t : pool) t.join();
+    }
+    for (uint32_t c = 0; c < n; ++c)
+        if (plans[c].rc) return fail(plans[c].rc, "circuit " + std::to_string(c) + ": " + plans[c].err);
+
+    // 2. lay out the workspace: header counters, items, passes, smalls, blob
+    std::vector<BatchPass> bpass;
+    std::vector<BatchSmall> bsmall;
+    std::vector<size_t> small_blob_off, pass_blob_off;   // per entry: offset of its circuit blob
+    std::vector<uint32_t> small_circuit;
+    std::vector<size_t> pass_rec_off;                     // word offset of each pass's records
+    std::vector<size_t> circuit_blob_off(n, 0);
+    size_t blob_size = 0, rec_words_total = 0;
+    uint32_t max_level = 0;
+    for (uint32_t c = 0; c < n; ++c) {
+        circuit_blob_off[c] = blob_size;
+        blob_size += (plans[c].pr.blob.size() + 255) & ~size_t(255);
+    }
+    for (uint32_t c = 0; c < n; ++c) {
+        BatchCircuitPlan &bp = plans[c];
+        qsim_state *s = states[c];
+        if (bp.pr.launches.empty()) continue;
+        if (bp.direct || bp.small) {
+            const Launch &l = bp.pr.launches[0];
+            BatchSmall sm{};
+            sm.ta = l.ta;
+            sm.src = s->buf[s->cur];
+            sm.dst = s->buf[s->cur ^ 1];
+            sm.L = l.n;
+            sm.M = s->M;
+            sm.direct = bp.direct ? 1u : 0u;
+            bsmall.push_back(sm);
+            small_blob_off.push_back(circuit_blob_off[c] + (bp.direct ? l.steps_off : l.inner_off));
+            small_circuit.push_back(c);
+            continue;
+        }
+        uint32_t level = 0;
+        for (size_t i = 0; i + 1 < bp.pr.launches.size(); i += 2, ++level) {
+            const Launch &lm = bp.pr.launches[i], &lt = bp.pr.launches[i + 1];
+            BatchPass p{};
+            p.ta = lt.ta;
+            p.tm = lm.tm;
+            p.src = s->buf[s->cur ^ (level & 1u)];
+            p.dst = s->buf[s->cur ^ ((level + 1) & 1u)];
+            p.n_tiles = lt.n_tiles;
+            p.circuit = c;
+            p.level = level;
+            bpass.push_back(p);
+            pass_blob_off.push_back(circuit_blob_off[c]);
+            // remember both step-array offsets inside the circuit blob
+            bpass.back().ta.inner = reinterpret_cast<const uint32_t *>(lt.inner_off);
+            bpass.back().tm.steps = reinterpret_cast<const TmStep *>(lm.steps_off);
+            pass_rec_off.push_back(rec_words_total);
+            rec_words_total += (size_t)lt.n_tiles * lt.ta.rec_words;
+        }
+        max_level = std::max(max_level, level);
+    }
+
+    // 3. the queue: record blocks, then tiles level by level with the small
+    // circuits spread between the levels as fillers (every item's
+    // dependencies come earlier in the queue)
+    std::vector<uint64_t> items;
+    uint32_t n_rec_blocks = 0;
+    for (size_t g = 0; g < bpass.size(); ++g) {
+        const uint64_t nb = (bpass[g].n_tiles + threads - 1) / threads;
+        for (uint64_t b = 0; b < nb; ++b) items.push_back(batch_item(kItemRec, (uint32_t)g, (uint32_t)b));
+        n_rec_blocks += (uint32_t)nb;
+    }
+    std::vector<std::vector<uint32_t>> by_level(max_level);
+    for (size_t g = 0; g < bpass.size(); ++g) by_level[bpass[g].level].push_back((uint32_t)g);
+    const size_t n_small = bsmall.size();
+    size_t small_next = 0;
+    const size_t levels = std::max<size_t>(max_level, 1);
+    for (size_t lv = 0; lv < levels; ++lv) {
+        if (lv < by_level.size())
+            for (uint32_t g : by_level[lv])
+                for (uint64_t t = 0; t < bpass[g].n_tiles; ++t) items.push_back(batch_item(kItemTile, g, (uint32_t)t));
+        const size_t upto = n_small * (lv + 1) / levels;
+        for (; small_next < upto; ++small_next) items.push_back(batch_item(kItemSmall, (uint32_t)small_next, 0));
+    }
+    for (; small_next < n_small; ++small_next) items.push_back(batch_item(kItemSmall, (uint32_t)small_next, 0));
+    if (items.size() > 0xFFFFFFF0ull) return fail(QSIM_ERR_INVALID, "batch too large");
+
+    const size_t ctr_bytes = ((kBatchCtrHeader + n) * 4 + 255) & ~size_t(255);
+    const size_t items_off = ctr_bytes;
+    const size_t pass_off = (items_off + items.size() * 8 + 255) & ~size_t(255);
+    const size_t small_off = (pass_off + bpass.size() * sizeof(BatchPass) + 255) & ~size_t(255);
+    const size_t blob_off = (small_off + bsmall.size() * sizeof(BatchSmall) + 255) & ~size_t(255);
+    const size_t total = blob_off + blob_size;
+
+    BatchWorkspace &w = batch_ws();
+    std::lock_guard<std::mutex> lk(w.mu);
+    (void)batch_collect(w);
+    hipError_t e;
+    if ((e = w.ws.ensure(total)) != hipSuccess) return fail(QSIM_ERR_NOMEM, "batch workspace");
+    if (rec_words_total && (e = w.rec.ensure(rec_words_total * 4)) != hipSuccess)
+        return fail(QSIM_ERR_NOMEM, "batch tile records");
+    if ((e = w.stage.ensure(total)) != hipSuccess) return fail(QSIM_ERR_DEVICE, "batch staging");
+    if (!w.done && (e = hipEventCreateWithFlags(&w.done, hipEventDisableTiming)) != hipSuccess)
+        return fail(QSIM_ERR_DEVICE, "batch event");
+    uint8_t *dev = static_cast<uint8_t *>(w.ws.p);
+    uint32_t *rec_dev = static_cast<uint32_t *>(w.rec.p);
+    // device pointers inside the descriptors
+    for (size_t g = 0; g < bpass.size(); ++g) {
+        const size_t cb = blob_off + pass_blob_off[g];
+        bpass[g].ta.inner = reinterpret_cast<const uint32_t *>(dev + cb + reinterpret_cast<size_t>(bpass[g].ta.inner));
+        bpass[g].tm.steps = reinterpret_cast<const TmStep *>(dev + cb + reinterpret_cast<size_t>(bpass[g].tm.steps));
+        bpass[g].ta.rec = rec_dev + pass_rec_off[g];
+        bpass[g].tm.rec = rec_dev + pass_rec_off[g];
+    }
+    for (size_t k = 0; k < bsmall.size(); ++k) {
+        const uint8_t *p = dev + blob_off + small_blob_off[k];
+        if (bsmall[k].direct) bsmall[k].steps_rev = reinterpret_cast<const TmStep *>(p);
+        else bsmall[k].ta.inner = reinterpret_cast<const uint32_t *>(p);
+    }
+    uint8_t *h = static_cast<uint8_t *>(w.stage.p);
+    std::memset(h, 0, ctr_bytes);
+    std::memcpy(h + items_off, items.data(), items.size() * 8);
+    if (!bpass.empty()) std::memcpy(h + pass_off, bpass.data(), bpass.size() * sizeof(BatchPass));
+    if (!bsmall.empty()) std::memcpy(h + small_off, bsmall.data(), bsmall.size() * sizeof(BatchSmall));
+    for (uint32_t c = 0; c < n; ++c)
+        if (!plans[c].pr.blob.empty())
+            std::memcpy(h + blob_off + circuit_blob_off[c], plans[c].pr.blob.data(), plans[c].pr.blob.size());
+    if ((e = hipMemcpyAsync(dev, h, total, hipMemcpyHostToDevice, st)) != hipSuccess)
+        return fail(QSIM_ERR_DEVICE, std::string("batch upload: ") + hipGetErrorString(e));
+    if ((e = hipEventRecord(w.stage.ev, st)) != hipSuccess) return fail(QSIM_ERR_DEVICE, "batch event");
+    w.stage.pending = true;
+    w.ctr_dev = reinterpret_cast<uint32_t *>(dev);
+    if (!items.empty()) {
+        e = launch_batch(elem, tb, reinterpret_cast<const BatchPass *>(dev + pass_off),
+                         reinterpret_cast<const BatchSmall *>(dev + small_off),
+                         reinterpret_cast<const uint64_t *>(dev + items_off), (uint32_t)items.size(), w.ctr_dev,
+                         n_rec_blocks, 1u << 24, st);
+        if (e != hipSuccess) {
+            for (uint32_t c = 0; c < n; ++c) states[c]->poisoned = true;
+            return fail(QSIM_ERR_DEVICE, std::string("batch launch: ") + hipGetErrorString(e));
+        }
+    }
+    if ((e = hipEventRecord(w.done, st)) != hipSuccess) return fail(QSIM_ERR_DEVICE, "batch event");
+    w.pending = true;
+    // every circuit's result sits in the buffer its last pass wrote
+    std::vector<uint32_t> flips(n, 0);
+    for (size_t k = 0; k < bsmall.size(); ++k) flips[small_circuit[k]] = 1;
+    for (const BatchPass &p : bpass) flips[p.circuit] = p.level + 1;
+    for (uint32_t c = 0; c < n; ++c) {
+        states[c]->cur ^= (int)(flips[c] & 1u);
+        states[c]->last_stream = st;
+    }
+    return QSIM_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 qsim_state *qsim_state_create(uint32_t M, qsim_dtype dtype) {
@@ -767,19 +1023,22 @@ int qsim_apply_batch(qsim_state *const *states, const qsim_step *const *steps, c
                      void *hip_stream) {
     if (n == 0) return QSIM_OK;
     if (!states || !steps || !Ls) return fail(QSIM_ERR_INVALID, "NULL array");
+    std::unordered_set<const qsim_state *> seen;
     for (uint32_t c = 0; c < n; ++c) {
         int rc = check_state(states[c]);
         if (rc) return rc;
         if (states[c]->dtype != states[0]->dtype) return fail(QSIM_ERR_INVALID, "states differ in dtype");
+        if (states[c]->device != states[0]->device) return fail(QSIM_ERR_INVALID, "states differ in device");
         if ((rc = validate_steps(states[c]->M, steps[c], Ls[c]))) return rc;
-        for (uint32_t d = 0; d < c; ++d)
-            if (states[d] == states[c]) return fail(QSIM_ERR_INVALID, "a state appears twice in the batch");
+        if (!seen.insert(states[c]).second) return fail(QSIM_ERR_INVALID, "a state appears twice in the batch");
     }
-    for (uint32_t c = 0; c < n; ++c) {
-        int rc = qsim_apply_steps(states[c], steps[c], Ls[c], hip_stream);
-        if (rc) return rc;
-    }
-    return QSIM_OK;
+    DeviceGuard g(states[0]->device);
+    if (!g.ok) return fail(QSIM_ERR_DEVICE, "set device");
+    return batch_enqueue(states, steps, Ls, n, static_cast<hipStream_t>(hip_stream));
+}
+
+int qsim_batch_last_status(void) {
+    return batch_status();
 }
 
 int qsim_state_set_tuning(qsim_state *s, const qsim_tuning *tuning) {

@@ -166,30 +166,30 @@ __device__ __forceinline__ void load_tile(vec16 (&v)[32u >> ((ELEM == 8) ? 1 : 0
     for (uint32_t r = 0; r < VPT; ++r) v[r] = ld_nt(src + (base + a.off_r_src[r]) / EPV);
 }
 
-// Walk, stage the loaded tile in LDS, gather and store one output tile.
-// `v` holds the source tile's vectors on entry; when `next_base` is not
-// ~0 the loads of the next source tile are issued into `v` as soon as the
-// current one is in LDS, so they overlap the gather, the stores and the
-// next tile's walk.
+// Source tile index of each of the calling thread's 32 output positions,
+// as bit-planes transposed to 16-bit indices (see src_of).
 template <int ELEM, bool FLAGS>
-__device__ __forceinline__ void tile_step(vec16 (&v)[32u >> ((ELEM == 8) ? 1 : 0)], const vec16 *__restrict__ src,
-                                          vec16 *__restrict__ dst, uint64_t dst_base, uint64_t next_base,
-                                          const TileArgs &a, const uint32_t *__restrict__ flags, vec16 *lds) {
-    constexpr uint32_t VPT = 32u >> ((ELEM == 8) ? 1 : 0);
-    constexpr uint32_t EPV = 16u / ELEM;
-    const uint32_t tid = threadIdx.x;
-    const uint32_t tb = a.tb;
-
-    uint32_t w[kPlanes];
-    init_planes<ELEM>(w, tid, tb);
+__device__ __forceinline__ void tile_sources(uint32_t (&w)[kPlanes], const TileArgs &a,
+                                             const uint32_t *__restrict__ flags) {
+    init_planes<ELEM>(w, threadIdx.x, a.tb);
     walk_inner<FLAGS>(w, a.inner, a.n_inner, flags);
     transpose_planes(w);
+}
 
+template <int ELEM>
+__device__ __forceinline__ void tile_stage(const vec16 (&v)[32u >> ((ELEM == 8) ? 1 : 0)], uint32_t tb, vec16 *lds) {
+    constexpr uint32_t VPT = 32u >> ((ELEM == 8) ? 1 : 0);
 #pragma unroll
-    for (uint32_t r = 0; r < VPT; ++r) lds[tid | (r << tb)] = v[r];
-    __syncthreads();
-    if (next_base != ~0ull) load_tile<ELEM>(v, src, next_base, a);
+    for (uint32_t r = 0; r < VPT; ++r) lds[threadIdx.x | (r << tb)] = v[r];
+}
 
+// Gather the calling thread's output entries from the staged source tile
+// and store them with 16-byte stores.
+template <int ELEM>
+__device__ __forceinline__ void tile_emit(const uint32_t (&w)[kPlanes], vec16 *__restrict__ dst, uint64_t dst_base,
+                                          const TileArgs &a, const vec16 *lds) {
+    constexpr uint32_t VPT = 32u >> ((ELEM == 8) ? 1 : 0);
+    constexpr uint32_t EPV = 16u / ELEM;
     if (ELEM == 8) {
         const uint2 *l2 = reinterpret_cast<const uint2 *>(lds);
 #pragma unroll
@@ -205,6 +205,23 @@ __device__ __forceinline__ void tile_step(vec16 (&v)[32u >> ((ELEM == 8) ? 1 : 0
             st_nt(dst + (dst_base + a.off_r_dst[r]) / EPV, e0);
         }
     }
+}
+
+// Walk, stage the loaded tile in LDS, gather and store one output tile.
+// `v` holds the source tile's vectors on entry; when `next_base` is not
+// ~0 the loads of the next source tile are issued into `v` as soon as the
+// current one is in LDS, so they overlap the gather, the stores and the
+// next tile's walk.
+template <int ELEM, bool FLAGS>
+__device__ __forceinline__ void tile_step(vec16 (&v)[32u >> ((ELEM == 8) ? 1 : 0)], const vec16 *__restrict__ src,
+                                          vec16 *__restrict__ dst, uint64_t dst_base, uint64_t next_base,
+                                          const TileArgs &a, const uint32_t *__restrict__ flags, vec16 *lds) {
+    uint32_t w[kPlanes];
+    tile_sources<ELEM, FLAGS>(w, a, flags);
+    tile_stage<ELEM>(v, a.tb, lds);
+    __syncthreads();
+    if (next_base != ~0ull) load_tile<ELEM>(v, src, next_base, a);
+    tile_emit<ELEM>(w, dst, dst_base, a, lds);
 }
 
 // Fused tile pass.  DEPTH = 0: one tile per workgroup.  DEPTH >= 1: a grid
@@ -261,9 +278,7 @@ __global__ void __launch_bounds__(512) k_small(const vec16 *__restrict__ src, ve
 
 // Per-tile record of a pass: source tile address and the outside-control
 // flags of the inner steps, from a backward walk of the outer address.
-__global__ void __launch_bounds__(256) k_tilemap(TileMapArgs a) {
-    const uint64_t tile = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (tile >= a.n_tiles) return;
+__device__ __forceinline__ void tilemap_one(const TileMapArgs &a, uint64_t tile) {
     uint64_t A = 0;
     for (uint32_t q = 0; q < a.n_out; ++q)
         if ((tile >> q) & 1u) A |= 1ull << a.out_pos[q];
@@ -294,6 +309,11 @@ __global__ void __launch_bounds__(256) k_tilemap(TileMapArgs a) {
     }
     rec[0] = (uint32_t)P;
     rec[1] = (uint32_t)(P >> 32);
+}
+
+__global__ void __launch_bounds__(256) k_tilemap(TileMapArgs a) {
+    const uint64_t tile = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tile < a.n_tiles) tilemap_one(a, tile);
 }
 
 // Direct gather: each thread walks its own row backwards through every step
@@ -356,6 +376,117 @@ __global__ void __launch_bounds__(256) k_copy(const vec16 *__restrict__ src, vec
             const uint64_t i = base + threadIdx.x + (uint64_t)k * blockDim.x;
             if (i < nvec) st_nt(dst + i, v[k]);
         }
+    }
+}
+
+// ------------------------------------------------------------ batched mode
+
+__device__ __forceinline__ void release_agent() { __atomic_thread_fence(__ATOMIC_RELEASE); }
+
+// Thread 0 waits until *p >= target (agent-scope acquire); a wait that runs
+// past `limit` polls raises the error flag and gives up, so the launch
+// always ends.
+__device__ __forceinline__ void wait_at_least(uint32_t *p, uint32_t target, uint32_t *err, uint32_t limit) {
+    uint32_t n = 0;
+    while (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (++n > limit) {
+            __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(4);
+    }
+}
+
+// Whole small circuit (2^M entries in LDS, every step inner) with the
+// first 2^tb threads of the workgroup; states of fewer than 32 rows use a
+// direct walk per row.
+template <int ELEM>
+__device__ __forceinline__ void small_item(const BatchSmall &sm, vec16 *lds) {
+    constexpr uint32_t VPT = 32u >> ((ELEM == 8) ? 1 : 0);
+    const uint32_t tid = threadIdx.x;
+    if (sm.direct) {
+        if (tid < (1u << sm.M)) {
+            uint64_t x = tid;
+            for (uint32_t s = 0; s < sm.L; ++s) {
+                const uint64_t cm = sm.steps_rev[s].cm;
+                if ((x & cm) == cm) x ^= 1ull << sm.steps_rev[s].tbit;
+            }
+            if (ELEM == 8)
+                reinterpret_cast<uint64_t *>(sm.dst)[tid] = reinterpret_cast<const uint64_t *>(sm.src)[x];
+            else
+                reinterpret_cast<vec16 *>(sm.dst)[tid] = reinterpret_cast<const vec16 *>(sm.src)[x];
+        }
+        return;
+    }
+    const TileArgs &a = sm.ta;
+    const bool active = tid < (1u << a.tb);
+    const vec16 *src = static_cast<const vec16 *>(sm.src);
+    vec16 *dst = static_cast<vec16 *>(sm.dst);
+    uint32_t w[kPlanes];
+    const uint32_t off = active ? thread_offset<ELEM>(a.pos_src, a.tb, tid) : 0u;
+    if (active) {
+        vec16 v[VPT];
+        load_tile<ELEM>(v, src, off, a);
+        tile_sources<ELEM, false>(w, a, nullptr);
+        tile_stage<ELEM>(v, a.tb, lds);
+    }
+    __syncthreads();
+    if (active) tile_emit<ELEM>(w, dst, off, a, lds);
+}
+
+template <int ELEM>
+__global__ void __launch_bounds__(256) k_batch(const BatchPass *__restrict__ passes,
+                                               const BatchSmall *__restrict__ smalls,
+                                               const uint64_t *__restrict__ items, uint32_t n_items,
+                                               uint32_t *ctr, uint32_t n_rec_blocks, uint32_t spin_limit) {
+    extern __shared__ vec16 lds[];
+    __shared__ uint32_t s_item;
+    constexpr uint32_t VPT = 32u >> ((ELEM == 8) ? 1 : 0);
+    const uint32_t tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) s_item = __hip_atomic_fetch_add(&ctr[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const uint32_t it = s_item;
+        if (it >= n_items) break;   // the same value for the whole workgroup
+        const uint64_t e = items[it];
+        const uint32_t kind = (uint32_t)(e >> 62);
+        const uint32_t idx = (uint32_t)(e >> 32) & 0x3FFFFFFFu;
+        const uint32_t sub = (uint32_t)e;
+        if (kind == kItemRec) {
+            const BatchPass &bp = passes[idx];
+            const uint64_t tile = (uint64_t)sub * blockDim.x + tid;
+            if (tile < bp.n_tiles) tilemap_one(bp.tm, tile);
+            release_agent();
+            __syncthreads();
+            if (tid == 0) __hip_atomic_fetch_add(&ctr[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else if (kind == kItemSmall) {
+            small_item<ELEM>(smalls[idx], lds);
+        } else {
+            const BatchPass &bp = passes[idx];
+            if (tid == 0) {
+                wait_at_least(&ctr[1], n_rec_blocks, &ctr[2], spin_limit);
+                wait_at_least(&ctr[kBatchCtrHeader + bp.circuit], bp.level * (uint32_t)bp.n_tiles, &ctr[2],
+                              spin_limit);
+            }
+            __syncthreads();
+            __atomic_thread_fence(__ATOMIC_ACQUIRE);
+            const TileArgs &a = bp.ta;
+            const uint64_t tile = sub;
+            const uint32_t *rec = a.rec + tile * a.rec_words;
+            const uint32_t off_src = thread_offset<ELEM>(a.pos_src, a.tb, tid);
+            const uint32_t off_dst = thread_offset<ELEM>(a.pos_dst, a.tb, tid);
+            vec16 v[VPT];
+            load_tile<ELEM>(v, static_cast<const vec16 *>(bp.src),
+                            ((uint64_t)uni(rec[0]) | ((uint64_t)uni(rec[1]) << 32)) + off_src, a);
+            tile_step<ELEM, true>(v, static_cast<const vec16 *>(bp.src), static_cast<vec16 *>(bp.dst),
+                                  outer_address(a, tile) + off_dst, ~0ull, a, rec + 2, lds);
+            release_agent();
+            __syncthreads();
+            if (tid == 0)
+                __hip_atomic_fetch_add(&ctr[kBatchCtrHeader + bp.circuit], 1u, __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
     }
 }
 
@@ -466,6 +597,33 @@ hipError_t launch_plain_step(uint32_t elem, void *buf, uint32_t M, uint32_t targ
     else
         hipLaunchKernelGGL(k_plain_step<16>, dim3((uint32_t)grid), dim3(bs), 0, st, (uint8_t *)buf, half_n,
                            target, cmask);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(uint32_t elem, uint32_t tb, const BatchPass *passes, const BatchSmall *smalls,
+                        const uint64_t *items, uint32_t n_items, uint32_t *counters, uint32_t n_rec_blocks,
+                        uint32_t spin_limit, hipStream_t st) {
+    const uint32_t threads = 1u << tb;
+    const size_t lds = (size_t)elem << (tb + 5);
+    if (threads > 256) return hipErrorInvalidValue;
+    hipError_t e;
+    uint64_t grid = 0;
+    if (elem == 8) {
+        if ((e = allow_lds(k_batch<8>, lds)) != hipSuccess) return e;
+        grid = resident_blocks(k_batch<8>, threads, lds);
+    } else {
+        if ((e = allow_lds(k_batch<16>, lds)) != hipSuccess) return e;
+        grid = resident_blocks(k_batch<16>, threads, lds);
+    }
+    if (grid == 0) grid = 256;
+    if (grid > n_items) grid = n_items;
+    if (grid == 0) return hipSuccess;
+    if (elem == 8)
+        hipLaunchKernelGGL(k_batch<8>, dim3((uint32_t)grid), dim3(threads), lds, st, passes, smalls, items,
+                           n_items, counters, n_rec_blocks, spin_limit);
+    else
+        hipLaunchKernelGGL(k_batch<16>, dim3((uint32_t)grid), dim3(threads), lds, st, passes, smalls, items,
+                           n_items, counters, n_rec_blocks, spin_limit);
     return hipGetLastError();
 }
 

@@ -67,6 +67,42 @@ struct TileMapArgs {
     uint8_t lam_src[64];             // physical bit of logical bit b in the read layout
 };
 
+// Batched mode: many circuits in one persistent launch.  Work items are
+// read from a queue in order; each names a tile-map record block of a pass,
+// a whole small circuit, or one tile of one pass.  A tile of pass p of a
+// circuit waits until every tile of pass p-1 of that circuit is done.
+struct BatchPass {
+    TileArgs ta;            // inner / rec pointers filled in
+    TileMapArgs tm;         // steps / rec pointers filled in
+    const void *src;
+    void *dst;
+    uint64_t n_tiles;
+    uint32_t circuit;       // index of the circuit's completion counter
+    uint32_t level;         // pass index within its circuit
+};
+
+struct BatchSmall {
+    TileArgs ta;            // whole state as one tile (identity positions)
+    const void *src;
+    void *dst;
+    const TmStep *steps_rev; // direct walk for states of fewer than 32 rows
+    uint32_t L;
+    uint32_t M;
+    uint32_t direct;
+    uint32_t pad;
+};
+
+enum : uint32_t { kItemRec = 0, kItemSmall = 1, kItemTile = 2 };
+
+__host__ __device__ inline uint64_t batch_item(uint32_t kind, uint32_t index, uint32_t sub) {
+    return ((uint64_t)kind << 62) | ((uint64_t)(index & 0x3FFFFFFFu) << 32) | sub;
+}
+
+// Counter words of a batched launch: [0] queue head, [1] finished record
+// blocks, [2] error flag (a dependency wait ran out), [3] reserved,
+// [4 + c] finished tiles of circuit c.
+constexpr uint32_t kBatchCtrHeader = 4;
+
 // Host-side plan of the fused path.
 struct Pass {
     uint64_t tile_mask = 0;          // address bits inside a tile
@@ -96,5 +132,8 @@ hipError_t launch_tile(uint32_t elem, const void *src, void *dst, uint64_t n_til
 hipError_t launch_plain_step(uint32_t elem, void *buf, uint32_t M, uint32_t target,
                              uint64_t cmask, hipStream_t st);
 hipError_t launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t st);
+hipError_t launch_batch(uint32_t elem, uint32_t tb, const BatchPass *passes, const BatchSmall *smalls,
+                        const uint64_t *items, uint32_t n_items, uint32_t *counters, uint32_t n_rec_blocks,
+                        uint32_t spin_limit, hipStream_t st);
 
 }  // namespace qsim

@@ -35,6 +35,7 @@ EXPORTS = (
     "qsim_apply_steps_plain", "qsim_read_portion", "qsim_read_portion_async", "qsim_apply_batch",
     "qsim_state_set_tuning", "qsim_plan_describe", "qsim_copy_bytes", "qsim_last_error",
     "qsim_version", "qsim_state_profile", "qsim_state_profile_read", "qsim_apply_tile_pass",
+    "qsim_batch_last_status",
 )
 
 
@@ -97,6 +98,7 @@ def _load() -> ctypes.CDLL:
         "qsim_version": (ctypes.c_char_p, []),
         "qsim_state_profile": (i32, [vp, i32]),
         "qsim_apply_tile_pass": (i32, [vp, u64, vp, u64, vp]),
+        "qsim_batch_last_status": (i32, []),
         "qsim_state_profile_read": (i32, [vp, vp]),
     }
     for name, (res, args) in sig.items():
@@ -302,6 +304,11 @@ def apply_batch(states: Sequence[State], steps: Sequence[Tuple[np.ndarray, np.nd
     ls = (ctypes.c_uint64 * n)(*[len(p) for p in packed])
     _check(_lib.qsim_apply_batch(ctypes.cast(hs, ctypes.c_void_p), ctypes.cast(ps, ctypes.c_void_p),
                                  ctypes.cast(ls, ctypes.c_void_p), n, ctypes.c_void_p(_stream_ptr(stream))))
+
+
+def batch_status():
+    """Wait for the last batched launch; raise if it did not complete cleanly."""
+    _check(_lib.qsim_batch_last_status())
 
 
 def plan_describe(M: int, dtype, target, cmask, tuning: Optional[dict] = None):

@@ -223,21 +223,63 @@ def test_wrap_torch_buffers(q):
     s.close()
 
 
-def test_batch_matches_solo(q):
-    rng = np.random.default_rng(11)
-    circuits = W.batched_config(n=24, seed=123, m_range=(3, 18), l_range=(0, 120))
+@pytest.mark.parametrize("dt,n,mr,lr,seed", [
+    (np.complex64, 24, (1, 18), (0, 120), 123),
+    (np.complex128, 24, (1, 17), (0, 120), 124),
+    (np.complex64, 300, (8, 16), (10, 200), 125),
+])
+def test_batch_matches_oracle(q, dt, n, mr, lr, seed):
+    """One persistent launch over circuits of mixed size and depth: every
+    circuit's result equals the oracle's, bit for bit."""
+    rng = np.random.default_rng(seed)
+    circuits = W.batched_config(n=n, seed=seed, m_range=mr, l_range=lr)
     states, ins = [], []
+    code = "c64" if dt == np.complex64 else "c128"
     for c in circuits:
-        k1 = W.gaussian_state(rng, c.M, np.complex64)
-        s = q.State(c.M, "c64")
+        k1 = W.gaussian_state(rng, c.M, dt)
+        s = q.State(c.M, code)
         s.write(k1)
         states.append(s)
         ins.append(k1)
-    say("batch", len(circuits))
+    say("batch", n, dt.__name__)
     q.apply_batch(states, [(c.target, c.cmask) for c in circuits], stream=0)
+    q.batch_status()
     for c, s, k1 in zip(circuits, states, ins):
-        assert_same(s.read(), oracle.apply(c.M, k1, c.target, c.cmask), f"batch circuit M={c.M} L={c.L}")
+        assert_same(s.read(), oracle.apply(c.M, k1, c.target, c.cmask, threads=8), f"batch circuit M={c.M} L={c.L}")
         s.close()
+
+
+def test_batch_config_matches_solo(q):
+    """The batched configuration (4096 circuits, M 8..20, L 10..500, 0..3
+    controls): every circuit of the single batched launch equals its solo
+    qsim_apply_steps result bit for bit; a sample is also checked against
+    the oracle."""
+    import torch
+    circuits = W.batched_config()
+    say("batch config: setup")
+    solo, batch, ins = [], [], []
+    for i, c in enumerate(circuits):
+        k1 = W.gaussian_state_torch(c.M, "c64", seed=1000 + i)
+        a = q.State(c.M, "c64", buffers=(k1.clone(), torch.empty_like(k1)))
+        b = q.State(c.M, "c64", buffers=(k1.clone(), torch.empty_like(k1)))
+        solo.append(a); batch.append(b); ins.append(k1)
+    say("batch config: solo applies")
+    for c, a in zip(circuits, solo):
+        a.apply(c.target, c.cmask)
+    say("batch config: batched launch")
+    q.apply_batch(batch, [(c.target, c.cmask) for c in circuits])
+    q.batch_status()
+    torch.cuda.synchronize()
+    say("batch config: compare")
+    for i, (c, a, b) in enumerate(zip(circuits, solo, batch)):
+        ra = a._keep[0] if a.current_ptr() == a._keep[0].data_ptr() else a._keep[1]
+        rb = b._keep[0] if b.current_ptr() == b._keep[0].data_ptr() else b._keep[1]
+        assert torch.equal(ra.view(torch.int64), rb.view(torch.int64)), f"circuit {i} M={c.M} L={c.L}"
+        if i % 256 == 0:
+            ref = oracle.apply(c.M, ins[i].cpu().numpy(), c.target, c.cmask, threads=8)
+            assert_same(rb.cpu().numpy(), ref, f"batch circuit {i} vs oracle")
+    for a, b in zip(solo, batch):
+        a.close(); b.close()
 
 
 # ------------------------------------------------------------------ full-size configurations
