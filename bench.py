@@ -96,12 +96,107 @@ def cpu_baseline(wl, k1_host, seconds: float):
                       f"input (plain pair-swap loop, OpenMP over rows, {dt:.1f} s)"}
 
 
+def bench_batched(reps: int = 3):
+    """The batched configuration: 4096 independent circuits (M uniform in
+    8..20, L uniform in 10..500, 0..3 controls, complex64), all states
+    resident on the device.  Timed three ways on the same states and
+    circuits, each including host planning: plain (one qsim_apply_steps per
+    circuit, serially on one stream) and batched (one qsim_apply_batch)."""
+    import torch
+    import workloads as W
+    from paper_quant_ph_0308158_amd import qsim
+    circuits = W.batched_config()
+    states = []
+    for i, c in enumerate(circuits):
+        k1 = W.gaussian_state_torch(c.M, "c64", seed=1000 + i)
+        states.append(qsim.State(c.M, "c64", buffers=(k1, torch.empty_like(k1))))
+    steps = [(c.target, c.cmask) for c in circuits]
+    packed = [qsim.pack_steps(t, cm) for t, cm in steps]
+    updates = float(sum((1 << c.M) * c.L for c in circuits))
+    torch.cuda.synchronize()
+
+    def plain():
+        for st, pk in zip(states, packed):
+            st.apply_packed(pk)
+
+    def batched():
+        qsim.apply_batch(states, steps)
+
+    out = {}
+    for name, fn in (("plain", plain), ("batched", batched)):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        out[name] = {"ms": round(dt * 1e3, 3), "updates_per_s": updates / dt}
+    qsim.batch_status()
+    for st in states:
+        st.close()
+    return {"workload": "batched_4096_M8-20_L10-500_c64", "circuits": len(circuits),
+            "amplitude_step_updates": updates, "plain": out["plain"], "batched": out["batched"],
+            "speedup_vs_plain": round(out["plain"]["ms"] / out["batched"]["ms"], 2)}
+
+
+def bench_served(n: int, rate: float, slots: int = 8, budget: float = 200e9, calibrate: bool = False):
+    """The served configuration: Poisson arrivals of circuit requests (M
+    log-uniform over [12, 29) floored, L uniform in 50..2000, 0..3 controls,
+    complex64, the alternating input generated on the device), admitted into
+    a 200 GB HBM arena.  Each result is read back in 2^20-row portions.
+    Latency = arrival to the last portion on the host.  The same trace is
+    served with continuous batching (`slots` requests on the device at once)
+    and plain first-come-first-served (one at a time).  With calibrate, all
+    requests arrive at t = 0 (measures service capacity)."""
+    import workloads as W
+    from paper_quant_ph_0308158_amd import qsim
+    trace = W.served_trace(n, rate)
+    packed = [qsim.pack_steps(r.circuit.target, r.circuit.cmask) for r in trace]
+    updates = float(sum((1 << r.circuit.M) * r.circuit.L for r in trace))
+
+    def run(fcfs: bool):
+        srv = qsim.Server(budget_bytes=int(budget), max_slots=slots, fcfs=fcfs)
+        w = srv.submit(12, "c64", [0], [0])   # warm the slot workers
+        srv.drain()
+        ids = []
+        t0 = time.perf_counter()
+        for r, pk in zip(trace, packed):
+            if not calibrate:
+                delay = t0 + r.arrival_s - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+            ids.append(srv.submit(r.circuit.M, "c64", pk["target"], pk["control_mask"]))
+        srv.drain()
+        infos = [srv.info(i) for i in ids]
+        srv.close()
+        if any(x["status"] != 0 for x in infos):
+            raise RuntimeError("a served request failed")
+        lat = sorted((x["t_done_ns"] - x["t_submit_ns"]) / 1e6 for x in infos)
+        span = (max(x["t_done_ns"] for x in infos) - min(x["t_submit_ns"] for x in infos)) / 1e9
+        pct = lambda p: lat[min(len(lat) - 1, int(round(p / 100.0 * (len(lat) - 1))))]
+        return {"p50_ms": round(pct(50), 2), "p99_ms": round(pct(99), 2), "mean_ms": round(sum(lat) / len(lat), 2),
+                "span_s": round(span, 3), "requests_per_s": round(len(infos) / span, 2),
+                "updates_per_s": updates / span}
+
+    cont = run(False)
+    plain = run(True)
+    return {"workload": f"served_poisson_{n}req_rate{rate:g}_M12-28_L50-2000_c64", "requests": n,
+            "rate_per_s": rate, "calibration": calibrate, "slots": slots, "budget_bytes": budget,
+            "amplitude_step_updates": updates, "continuous": cont, "plain_fcfs": plain,
+            "throughput_speedup_vs_plain": round(cont["updates_per_s"] / plain["updates_per_s"], 2),
+            "p99_speedup_vs_plain": round(plain["p99_ms"] / cont["p99_ms"], 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="m32", choices=["m32", "m26", "small"])
+    ap.add_argument("--workload", default="m32", choices=["m32", "m26", "small", "batched", "served"])
+    ap.add_argument("--requests", type=int, default=200)
+    ap.add_argument("--rate", type=float, default=None, help="served: arrivals per second")
+    ap.add_argument("--calibrate", action="store_true", help="served: all requests arrive at once")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tuning", default=None, help="JSON dict of qsim_tuning fields")
@@ -120,6 +215,13 @@ def main():
     from paper_quant_ph_0308158_amd import qsim
 
     torch.cuda.set_device(0)
+    if args.workload == "batched":
+        print(json.dumps(bench_batched(max(1, args.steps))), flush=True)
+        return
+    if args.workload == "served":
+        rate = args.rate if args.rate is not None else W.SERVED_RATE
+        print(json.dumps(bench_served(args.requests, rate, calibrate=args.calibrate)), flush=True)
+        return
     wl = workload(args.workload)
     M, dt = wl["M"], wl["dtype"]
     tg, cm = wl["target"], wl["cmask"]

@@ -156,6 +156,73 @@ int qsim_apply_batch(qsim_state *const *states, const qsim_step *const *steps,
  * (the results of that batch are then invalid). */
 int qsim_batch_last_status(void);
 
+/* ---------------------------------------------------------------- serving */
+
+/* A request server: wiring diagrams submitted over time run on one device
+ * with their states kept in an HBM arena.  Requests are admitted in arrival
+ * order (a later request may overtake one that does not fit yet, a bounded
+ * number of times) whenever a slot and arena room are free, and admitted
+ * requests run concurrently, each on its own stream: requests that arrive
+ * while others are on the device join them (continuous batching).  Each
+ * result is read back in contiguous portions of portion_entries rows (the
+ * state vector produced top to bottom in continuous portions, Abstract and
+ * Conclusions) and folded into a 64-bit digest as it lands.  With fcfs = 1
+ * one request runs at a time in arrival order (the plain comparator). */
+typedef struct qsim_server qsim_server;
+
+typedef struct {
+    uint64_t hbm_budget_bytes; /* arena size (0 = 200e9 bytes)               */
+    uint32_t max_slots;        /* requests on the device at once (0 = 8)      */
+    uint32_t portion_entries;  /* rows per read-back portion (0 = 2^20)       */
+    uint32_t fcfs;             /* 1 = one request at a time, arrival order    */
+    uint32_t max_bypass;       /* times the queue head may be overtaken (0 = 64) */
+    uint32_t digest;           /* 1 = fold every portion into the request's digest */
+    uint32_t reserved;
+} qsim_server_config;
+
+typedef struct {
+    int32_t status;       /* QSIM_OK or the error the request ended with    */
+    int32_t done;         /* 1 once the last portion has been read back      */
+    uint64_t t_submit_ns; /* steady-clock times of submission, admission    */
+    uint64_t t_admit_ns;  /* and completion (last portion digested)          */
+    uint64_t t_done_ns;
+    uint64_t digest;      /* digest of the result's bytes in row order (0
+                             unless the server computes digests)            */
+    uint64_t bytes;       /* bytes read back                                 */
+} qsim_request_info;
+
+/* Create a server on the current device; allocates the arena.  cfg may be
+ * NULL (defaults).  NULL on failure (no device, arena allocation failed,
+ * max_slots > 64). */
+qsim_server *qsim_server_create(const qsim_server_config *cfg);
+
+/* Queue a request: M address bits, entry type, initial state host_k1 (2^M
+ * entries, copied before the call returns; NULL = the alternating input
+ * |S|(1, -1, 1, -1, ...) of Sec. 2(b) and Sec. 4) and the wiring diagram
+ * steps[0..L-1] (copied).  Returns the request id (>= 0), QSIM_ERR_INVALID
+ * for an invalid request, QSIM_ERR_NOMEM if its two buffers exceed the
+ * whole arena.  Never blocks on the device. */
+int64_t qsim_server_submit(qsim_server *server, uint32_t M, qsim_dtype dtype,
+                           const void *host_k1, const qsim_step *steps,
+                           uint64_t L);
+
+/* Wait until every submitted request is done. */
+int qsim_server_drain(qsim_server *server);
+
+/* Status, timestamps and digest of request `id` (QSIM_ERR_RANGE for an
+ * unknown id). */
+int qsim_server_request_info(qsim_server *server, int64_t id,
+                             qsim_request_info *out);
+
+/* Arena size and use, queued and running request counts (any pointer may
+ * be NULL). */
+int qsim_server_stats(qsim_server *server, uint64_t *arena_bytes,
+                      uint64_t *arena_used, uint32_t *queued,
+                      uint32_t *running);
+
+/* Drain, stop the workers and free the arena.  NULL is ignored. */
+void qsim_server_destroy(qsim_server *server);
+
 /* ---------------------------------------------------------------- tuning */
 
 /* Launch parameters of the fused path.  Zero in any field selects the

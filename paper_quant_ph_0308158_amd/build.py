@@ -17,7 +17,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libqsim.so")
 ARCH = os.environ.get("QSIM_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["kernels.hip", "planner.cpp", "abi.cpp"]
+SOURCES = ["kernels.hip", "planner.cpp", "abi.cpp", "server.cpp"]
 # -packed-fp32-ops: the library does no floating-point arithmetic at all, and
 # packed FP32 instructions are kept out of its code on principle.
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

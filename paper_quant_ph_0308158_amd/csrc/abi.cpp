@@ -822,6 +822,24 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
 
 }  // namespace
 
+int qsim::state_rebind(qsim_state *s, uint32_t M, int dtype, void *buf0, void *buf1) {
+    if (!s || s->owned) return fail(QSIM_ERR_INVALID, "state_rebind needs a wrapped state");
+    const uint32_t elem = elem_of((qsim_dtype)dtype);
+    if (!elem || M < 1 || M > QSIM_MAX_M || !buf0 || !buf1) return fail(QSIM_ERR_INVALID, "state_rebind arguments");
+    DeviceGuard g(s->device);
+    hipError_t e = hipStreamSynchronize(s->last_stream);
+    if (e != hipSuccess) return device_fail(s, e, "synchronize");
+    if (s->elem != elem) s->tune = default_tuning(elem);
+    s->M = M;
+    s->dtype = (qsim_dtype)dtype;
+    s->elem = elem;
+    s->buf[0] = buf0;
+    s->buf[1] = buf1;
+    s->cur = 0;
+    s->poisoned = false;
+    return QSIM_OK;
+}
+
 extern "C" {
 
 qsim_state *qsim_state_create(uint32_t M, qsim_dtype dtype) {

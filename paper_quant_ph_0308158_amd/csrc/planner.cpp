@@ -68,17 +68,6 @@ std::vector<Pass> plan_passes(uint32_t M, const uint32_t *target, const uint64_t
     const uint64_t base = (1ull << low) - 1ull;
     const int cap = std::max(cfg.max_seg_steps, 1);
 
-    // Dependencies: preds[j] = earlier steps that j does not commute with.
-    std::vector<std::vector<uint32_t>> preds(L);
-    for (uint64_t j = 1; j < L; ++j) {
-        if (!cfg.reorder) {
-            preds[j].push_back((uint32_t)(j - 1));
-            continue;
-        }
-        for (uint64_t i = 0; i < j; ++i)
-            if (!commute(target[i], cmask[i], target[j], cmask[j])) preds[j].push_back((uint32_t)i);
-    }
-
     // state: 0 = pending, 1 = done in an earlier pass, 2 = taken now, 3 = blocked now
     std::vector<uint8_t> state(L, 0);
     std::vector<uint32_t> pending;
@@ -101,16 +90,26 @@ std::vector<Pass> plan_passes(uint32_t M, const uint32_t *target, const uint64_t
     };
 
     // One pass over the pending steps, starting from tile mask `start`.
+    // A step may join the pass only if it commutes with every earlier
+    // pending step left behind in this scan: with BT the targets and BC the
+    // controls of the steps left behind, step s is blocked exactly when one
+    // of its controls is in BT or its target is in BC.
     auto build_pass = [&](uint64_t start) {
         uint64_t I = start;
         uint64_t U = 0;
+        uint64_t BT = 0, BC = 0;
+        bool any_blocked = false;
         std::vector<uint32_t> taken;
         for (uint32_t s : pending) {
             if ((int)taken.size() >= cap) break;
-            bool ready = true;
-            for (uint32_t p : preds[s])
-                if (state[p] != 1 && state[p] != 2) { ready = false; break; }
-            if (!ready) { state[s] = 3; continue; }
+            const bool ready = cfg.reorder ? !((cmask[s] & BT) || ((BC >> target[s]) & 1ull)) : !any_blocked;
+            if (!ready) {
+                state[s] = 3;
+                BT |= 1ull << target[s];
+                BC |= cmask[s];
+                any_blocked = true;
+                continue;
+            }
             const uint64_t T = 1ull << target[s];
             bool took = false;
             if (I & T) {
@@ -135,6 +134,9 @@ std::vector<Pass> plan_passes(uint32_t M, const uint32_t *target, const uint64_t
                 state[s] = 2;
             } else {
                 state[s] = 3;
+                BT |= 1ull << target[s];
+                BC |= cmask[s];
+                any_blocked = true;
             }
         }
         if (taken.empty()) throw std::logic_error("planner made no progress");

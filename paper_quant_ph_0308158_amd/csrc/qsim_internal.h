@@ -121,6 +121,17 @@ struct PlanConfig {
 std::vector<Pass> plan_passes(uint32_t M, const uint32_t *target, const uint64_t *cmask,
                               uint64_t L, const PlanConfig &cfg);
 
+}  // namespace qsim
+
+struct qsim_state;
+
+namespace qsim {
+
+// Point an existing wrapped state at new buffers (another M or dtype),
+// keeping its plan, record and staging buffers.  Waits for the state's
+// earlier work.  For the serving workers, which reuse one state per slot.
+int state_rebind(qsim_state *s, uint32_t M, int dtype, void *buf0, void *buf1);
+
 // Kernel launchers (kernels.hip).  All return hipSuccess or the launch error.
 hipError_t launch_direct(uint32_t elem, const void *src, void *dst, uint64_t n,
                          const TmStep *steps_rev, uint32_t L, hipStream_t st);

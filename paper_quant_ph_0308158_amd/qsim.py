@@ -35,7 +35,8 @@ EXPORTS = (
     "qsim_apply_steps_plain", "qsim_read_portion", "qsim_read_portion_async", "qsim_apply_batch",
     "qsim_state_set_tuning", "qsim_plan_describe", "qsim_copy_bytes", "qsim_last_error",
     "qsim_version", "qsim_state_profile", "qsim_state_profile_read", "qsim_apply_tile_pass",
-    "qsim_batch_last_status",
+    "qsim_batch_last_status", "qsim_server_create", "qsim_server_submit", "qsim_server_drain",
+    "qsim_server_request_info", "qsim_server_stats", "qsim_server_destroy",
 )
 
 
@@ -50,6 +51,21 @@ class Profile(ctypes.Structure):
                 ("tile_bytes", ctypes.c_uint64), ("map_launches", ctypes.c_uint64),
                 ("map_ms", ctypes.c_double), ("other_launches", ctypes.c_uint64),
                 ("other_ms", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_uint32),
+                ("portion_entries", ctypes.c_uint32), ("fcfs", ctypes.c_uint32),
+                ("max_bypass", ctypes.c_uint32), ("digest", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("done", ctypes.c_int32), ("t_submit_ns", ctypes.c_uint64),
+                ("t_admit_ns", ctypes.c_uint64), ("t_done_ns", ctypes.c_uint64), ("digest", ctypes.c_uint64),
+                ("bytes", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -99,6 +115,12 @@ def _load() -> ctypes.CDLL:
         "qsim_state_profile": (i32, [vp, i32]),
         "qsim_apply_tile_pass": (i32, [vp, u64, vp, u64, vp]),
         "qsim_batch_last_status": (i32, []),
+        "qsim_server_create": (vp, [vp]),
+        "qsim_server_submit": (ctypes.c_int64, [vp, u32, i32, vp, vp, u64]),
+        "qsim_server_drain": (i32, [vp]),
+        "qsim_server_request_info": (i32, [vp, ctypes.c_int64, vp]),
+        "qsim_server_stats": (i32, [vp, vp, vp, vp, vp]),
+        "qsim_server_destroy": (None, [vp]),
         "qsim_state_profile_read": (i32, [vp, vp]),
     }
     for name, (res, args) in sig.items():
@@ -331,3 +353,87 @@ def plan_describe(M: int, dtype, target, cmask, tuning: Optional[dict] = None):
 def copy_bytes(dst_ptr: int, src_ptr: int, nbytes: int, stream=None):
     _check(_lib.qsim_copy_bytes(ctypes.c_void_p(dst_ptr), ctypes.c_void_p(src_ptr), nbytes,
                                 ctypes.c_void_p(_stream_ptr(stream))))
+
+
+class Server:
+    """Request server (qsim_server_*): continuous batching over slot streams
+    with an HBM arena, or one request at a time with ``fcfs=True``."""
+
+    def __init__(self, budget_bytes: int = 0, max_slots: int = 0, portion_entries: int = 0,
+                 fcfs: bool = False, max_bypass: int = 0, digest: bool = False):
+        cfg = ServerConfig()
+        cfg.hbm_budget_bytes = int(budget_bytes)
+        cfg.max_slots = int(max_slots)
+        cfg.portion_entries = int(portion_entries)
+        cfg.fcfs = 1 if fcfs else 0
+        cfg.max_bypass = int(max_bypass)
+        cfg.digest = 1 if digest else 0
+        h = _lib.qsim_server_create(ctypes.byref(cfg))
+        if not h:
+            raise QsimError(ERR_NOMEM, "qsim_server_create failed")
+        self._h = ctypes.c_void_p(h)
+
+    def submit(self, M: int, dtype, target, cmask, k1: Optional[np.ndarray] = None) -> int:
+        st = pack_steps(target, cmask)
+        ptr = None
+        if k1 is not None:
+            k1 = np.ascontiguousarray(k1)
+            if k1.dtype != np_dtype(dtype_code(dtype)) or k1.size != (1 << M):
+                raise ValueError("k1 must hold 2^M entries of the request's dtype")
+            ptr = k1.ctypes.data
+        rid = _lib.qsim_server_submit(self._h, M, dtype_code(dtype), ptr, st.ctypes.data if len(st) else None,
+                                      len(st))
+        if rid < 0:
+            raise QsimError(int(rid), "submit rejected")
+        return int(rid)
+
+    def drain(self):
+        _check(_lib.qsim_server_drain(self._h))
+
+    def info(self, rid: int) -> dict:
+        r = RequestInfo()
+        _check(_lib.qsim_server_request_info(self._h, rid, ctypes.byref(r)))
+        return r.as_dict()
+
+    def stats(self) -> dict:
+        a, u = ctypes.c_uint64(0), ctypes.c_uint64(0)
+        qd, rn = ctypes.c_uint32(0), ctypes.c_uint32(0)
+        _check(_lib.qsim_server_stats(self._h, ctypes.byref(a), ctypes.byref(u), ctypes.byref(qd),
+                                      ctypes.byref(rn)))
+        return {"arena_bytes": a.value, "arena_used": u.value, "queued": qd.value, "running": rn.value}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.qsim_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def digest_bytes(data: bytes) -> int:
+    """The server's 64-bit digest of a result, recomputed on the host (for
+    checking a read-back result against a reference)."""
+    M64 = (1 << 64) - 1
+
+    def rotl(x, r):
+        return ((x << r) | (x >> (64 - r))) & M64
+
+    w = np.frombuffer(data, dtype=np.uint64)
+    h = [0x9E3779B97F4A7C15, 0xC2B2AE3D27D4EB4F, 0x165667B19E3779F9, 0x27D4EB2F165667C5]
+    for i, x in enumerate(w.tolist()):
+        k = i & 3
+        h[k] = (rotl(h[k] ^ ((x * 0x9FB21C651E98DF25) & M64), 27) * 0x9E3779B97F4A7C15) & M64
+    x = (len(data) * 0xFF51AFD7ED558CCD) & M64
+    for k in range(4):
+        x = (rotl(x ^ h[k], 31) * 0xC4CEB9FE1A85EC53) & M64
+    return x ^ (x >> 29)

@@ -332,3 +332,69 @@ def test_m32_config_sampled(q):
     s.close()
     k1_again = W.gaussian_state_torch(M, "c64", seed=W.SEED_M32)
     assert torch.equal(cur.view(torch.int64), k1_again.view(torch.int64))
+
+
+# ------------------------------------------------------------------ serving
+
+def _server_requests(seed, n, m_range, l_max):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(n):
+        M = int(rng.integers(m_range[0], m_range[1] + 1))
+        L = int(rng.integers(0, l_max + 1))
+        tg, cm = W.random_steps(rng, M, L, (0, 3))
+        k1 = W.gaussian_state(rng, M, np.complex64) if i % 3 else None
+        reqs.append((M, tg, cm, k1))
+    return reqs
+
+
+def test_server_alone_and_in_mix(q):
+    """Continuous batching: every request's read-back result is the same
+    (digest of all its bytes) whether it runs alone or among others, and
+    equals the oracle's result."""
+    reqs = _server_requests(21, 24, (5, 16), 300)
+    say("server: mix")
+    with q.Server(budget_bytes=1 << 30, max_slots=8, portion_entries=1 << 12, digest=True) as srv:
+        ids = [srv.submit(M, "c64", tg, cm, k1) for (M, tg, cm, k1) in reqs]
+        srv.drain()
+        mix = [srv.info(i) for i in ids]
+    say("server: alone")
+    alone = []
+    with q.Server(budget_bytes=1 << 30, fcfs=True, portion_entries=1 << 12, digest=True) as srv:
+        for (M, tg, cm, k1) in reqs:
+            rid = srv.submit(M, "c64", tg, cm, k1)
+            srv.drain()
+            alone.append(srv.info(rid))
+    for i, (a, b, (M, tg, cm, k1)) in enumerate(zip(alone, mix, reqs)):
+        assert a["status"] == 0 and b["status"] == 0 and a["done"] and b["done"]
+        assert a["bytes"] == b["bytes"] == 8 << M
+        assert a["digest"] == b["digest"], f"request {i} differs alone and in the mix"
+        k = k1 if k1 is not None else W.alternating_state(M, np.complex64)
+        ref = oracle.apply(M, k, tg, cm)
+        assert q.digest_bytes(ref.tobytes()) == b["digest"], f"request {i} differs from the oracle"
+
+
+def test_server_small_budget_queues(q):
+    """With an arena that holds two requests at a time, the others wait in the
+    queue (admission never exceeds the budget) and all complete correctly."""
+    reqs = _server_requests(22, 10, (16, 16), 100)   # 2 x 512 KiB each -> one 2 MiB granule
+    say("server: small budget")
+    with q.Server(budget_bytes=4 << 20, max_slots=8, portion_entries=1 << 12, digest=True) as srv:
+        ids = [srv.submit(M, "c64", tg, cm, k1) for (M, tg, cm, k1) in reqs]
+        peak = 0
+        import time
+        t_end = time.time() + 60
+        while any(not srv.info(i)["done"] for i in ids) and time.time() < t_end:
+            st = srv.stats()
+            assert st["arena_used"] <= st["arena_bytes"]
+            peak = max(peak, st["running"])
+            time.sleep(0.001)
+        srv.drain()
+        infos = [srv.info(i) for i in ids]
+        assert peak <= 2
+        with pytest.raises(q.QsimError):
+            srv.submit(20, "c64", [0], [0])        # 16 MiB of buffers > the whole arena
+    for (M, tg, cm, k1), inf in zip(reqs, infos):
+        assert inf["status"] == 0
+        k = k1 if k1 is not None else W.alternating_state(M, np.complex64)
+        assert q.digest_bytes(oracle.apply(M, k, tg, cm).tobytes()) == inf["digest"]
