@@ -199,6 +199,8 @@ def main():
     ap.add_argument("--calibrate", action="store_true", help="served: all requests arrive at once")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-modes", action="store_true",
+                    help="skip the batched and served comparisons of the default run")
     ap.add_argument("--tuning", default=None, help="JSON dict of qsim_tuning fields")
     args = ap.parse_args()
 
@@ -284,16 +286,26 @@ def main():
     torch.cuda.synchronize()
     copy_gbps = 3 * 2 * nbytes / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
 
+    modes = None
+    if not args.no_modes and args.workload == "m32":
+        st.close()
+        del k1, other
+        torch.cuda.empty_cache()
+        k1 = other = None
+        modes = {"batched": bench_batched(2), "served": bench_served(args.requests, W.SERVED_RATE)}
+        torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu_baseline:
-        host = k1.cpu().numpy()   # the same input bytes (state after the timed steps)
-        del k1, other
+        if k1 is None:   # the benchmark's input, regenerated from its seed
+            k1 = W.gaussian_state_torch(M, dt, seed=wl["seed"])
+        host = k1.cpu().numpy()
         st.close()
+        del k1, other
         torch.cuda.empty_cache()
         cpu = cpu_baseline(wl, host, args.cpu_seconds)
         del host
-    else:
-        st.close()
+    st.close()
 
     out = {
         "metric": "amplitude-step updates/s (2^M x L per applied wiring diagram)",
@@ -313,6 +325,7 @@ def main():
         "roofline": roofline,
         "copy_probe_GBps": round(copy_gbps, 1),
         "cpu_baseline": cpu,
+        "modes": modes,
         "profile": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in prof.items()},
     }
     print(json.dumps(out), flush=True)

@@ -249,7 +249,11 @@ typedef struct {
                               natural order throughout                      */
     uint32_t mid_low_bits; /* low address bits forced into the tiles of the
                               passes between the first and the last one    */
-    uint32_t reserved[2];
+    uint32_t min_overlap;  /* tile bits each middle pass shares with the
+                              previous pass (with remap: the length, as a
+                              power of two, of the runs written between
+                              passes)                                       */
+    uint32_t reserved;
 } qsim_tuning;
 
 /* Set (tuning != NULL) or reset to defaults (NULL) the parameters used by

@@ -71,6 +71,7 @@ struct Tuning {
     uint32_t outer_order; // 0 = lowest outside bit fastest, 1 = highest fastest
     bool remap;           // permuted layouts between passes
     int mid_low_bits;     // forced low bits of the passes in between
+    int min_overlap;      // tile bits shared by consecutive passes
 };
 
 Tuning default_tuning(uint32_t elem) {
@@ -85,6 +86,7 @@ Tuning default_tuning(uint32_t elem) {
     t.outer_order = 0;
     t.remap = true;
     t.mid_low_bits = 2;
+    t.min_overlap = 1;                   // no overlap requirement (measured best)
     return t;
 }
 
@@ -101,6 +103,7 @@ int tuning_from(const qsim_tuning *in, uint32_t elem, Tuning *out) {
         if (in->outer_order) t.outer_order = in->outer_order - 1;
         if (in->remap) t.remap = (in->remap == 1);
         if (in->mid_low_bits) t.mid_low_bits = (int)in->mid_low_bits;
+        if (in->min_overlap) t.min_overlap = (int)in->min_overlap;
     }
     if (t.mid_low_bits < 1 || t.mid_low_bits > t.low_bits) t.mid_low_bits = t.low_bits;
     if (t.outer_order > 1) return fail(QSIM_ERR_INVALID, "outer_order out of range");
@@ -121,6 +124,7 @@ PlanConfig plan_config(const Tuning &t) {
     c.tile_bits = t.tile_bits;
     c.low_bits = t.low_bits;
     c.mid_low_bits = t.remap ? t.mid_low_bits : t.low_bits;
+    c.min_overlap = t.remap ? t.min_overlap : 0;
     c.max_seg_steps = t.max_seg_steps;
     c.reorder = t.reorder;
     return c;
@@ -361,9 +365,15 @@ int prepare_passes(uint32_t M, uint32_t elem, const std::vector<Pass> &passes,
         uint8_t jpos[64];
         uint32_t ni = 0, no = 0;
         for (uint32_t b = 0; b < M; ++b) {
-            if ((I >> b) & 1ull) { jpos[b] = (uint8_t)ni; in_log[ni++] = (uint8_t)b; }
+            if ((I >> b) & 1ull) in_log[ni++] = (uint8_t)b;
             else out_log[no++] = (uint8_t)b;
         }
+        // Tile-index bit j of the kernel is tile bit in_log[j].  Ordering them
+        // by physical position in the written layout makes the lanes of one
+        // wave store cover whole contiguous lines; bit 0 stays first (its
+        // physical position is 0 in every layout, which the 8-byte pairs need).
+        std::sort(in_log, in_log + ni, [&](uint8_t x, uint8_t y) { return ld[x] < ld[y]; });
+        for (uint32_t j = 0; j < ni; ++j) jpos[in_log[j]] = (uint8_t)j;
         // Tiles may be enumerated in any order: outer_order picks which
         // outside bits (by physical position in the written layout) vary
         // between tiles processed at the same time.

@@ -139,7 +139,10 @@ std::vector<Pass> plan_passes(uint32_t M, const uint32_t *target, const uint64_t
                 any_blocked = true;
             }
         }
-        if (taken.empty()) throw std::logic_error("planner made no progress");
+        if (taken.empty()) {
+            for (uint32_t s : pending) state[s] = 0;
+            return Pass{};
+        }
         // Widen the tile to K bits with the lowest bits that no outer step of
         // the pass is controlled by; every taken step stays admissible.
         for (uint32_t b = 0; b < M && popc(I) < K; ++b) {
@@ -166,14 +169,42 @@ std::vector<Pass> plan_passes(uint32_t M, const uint32_t *target, const uint64_t
     // layouts permuted to suit them and may start from fewer low bits.
     const int mid_low = std::min<int>(std::max(cfg.mid_low_bits > 0 ? cfg.mid_low_bits : low, 1), low);
     const uint64_t mid_base = (1ull << mid_low) - 1ull;
-    while (!pending.empty()) passes.push_back(build_pass(passes.empty() ? base : mid_base));
+    // Consecutive tiles must share at least min_overlap bits: between passes
+    // the state is laid out with the shared bits lowest, so the pass that
+    // writes it does so in runs of 2^(shared bits) entries, which should fill
+    // whole cache lines.  A middle pass therefore starts from the low bits
+    // plus bits of the previous tile, preferring the targets of the next
+    // pending steps (which the tile would take in anyway).
+    const int min_ov = std::min(cfg.min_overlap, K - 1);
+    auto seed_from = [&](uint64_t prev) {
+        uint64_t I = mid_base;
+        for (uint32_t s : pending) {
+            if (popc(I & prev) >= min_ov) break;
+            const uint64_t T = 1ull << target[s];
+            if ((prev & T) && (allowed & T)) I |= T;
+        }
+        for (uint32_t b = 0; b < M && popc(I & prev) < min_ov; ++b)
+            if ((prev >> b) & 1ull) I |= 1ull << b;
+        return I;
+    };
+    // A seeded start can leave no step admissible; the plain start always
+    // admits the first pending step.
+    auto next_pass = [&](uint64_t start, uint64_t fallback) {
+        Pass p = build_pass(start);
+        if (p.steps.empty() && start != fallback) p = build_pass(fallback);
+        if (p.steps.empty()) throw std::logic_error("planner made no progress");
+        return p;
+    };
+    while (!pending.empty())
+        passes.push_back(passes.empty() ? next_pass(base, base)
+                                        : next_pass(seed_from(passes.back().tile_mask), mid_base));
     if ((passes.back().tile_mask & base) != base) {
         // Re-plan the last pass's steps from the full base.
         Pass last = passes.back();
         passes.pop_back();
         for (uint32_t s : last.steps) state[s] = 0;
         pending = last.steps;
-        while (!pending.empty()) passes.push_back(build_pass(base));
+        while (!pending.empty()) passes.push_back(next_pass(base, base));
     }
     return passes;
 }

@@ -113,6 +113,7 @@ struct PlanConfig {
     int tile_bits = 13;
     int low_bits = 5;       // low address bits in the tiles of the first and last pass
     int mid_low_bits = 0;   // same for the passes in between (0 = low_bits)
+    int min_overlap = 0;    // tile bits a middle pass shares with the previous one
     int max_seg_steps = 1024;
     bool reorder = true;
 };

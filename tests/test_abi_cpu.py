@@ -105,6 +105,8 @@ def _check_plan(M, dtype, tg, cm, tuning):
     (2, 16, "c64", {"tile_bits": 8, "max_seg_steps": 9}),
     (3, 16, "c64", {"tile_bits": 8, "reorder": False}),
     (4, 13, "c64", {"tile_bits": 5, "low_bits": 1}),
+    (5, 13, "c64", {"tile_bits": 5, "low_bits": 1, "min_overlap": 5}),
+    (6, 16, "c128", {"tile_bits": 8, "min_overlap": 4, "mid_low_bits": 1}),
 ])
 def test_planner_reorder_is_exact(seed, M, dtype, tuning):
     """The planner's execution order has the same product as the original
