@@ -253,7 +253,9 @@ typedef struct {
                               previous pass (with remap: the length, as a
                               power of two, of the runs written between
                               passes)                                       */
-    uint32_t reserved;
+    uint32_t rows_per_thread; /* tile rows per thread of the fused pass:
+                              8, 16 or 32 (threads per tile = 2^tile_bits /
+                              rows_per_thread, at most 1024)               */
 } qsim_tuning;
 
 /* Set (tuning != NULL) or reset to defaults (NULL) the parameters used by

@@ -72,6 +72,7 @@ struct Tuning {
     bool remap;           // permuted layouts between passes
     int mid_low_bits;     // forced low bits of the passes in between
     int min_overlap;      // tile bits shared by consecutive passes
+    uint32_t rows_eb;     // log2 of the tile rows each thread owns
 };
 
 Tuning default_tuning(uint32_t elem) {
@@ -87,6 +88,7 @@ Tuning default_tuning(uint32_t elem) {
     t.remap = true;
     t.mid_low_bits = 2;
     t.min_overlap = 1;                   // no overlap requirement (measured best)
+    t.rows_eb = 5;
     return t;
 }
 
@@ -104,6 +106,11 @@ int tuning_from(const qsim_tuning *in, uint32_t elem, Tuning *out) {
         if (in->remap) t.remap = (in->remap == 1);
         if (in->mid_low_bits) t.mid_low_bits = (int)in->mid_low_bits;
         if (in->min_overlap) t.min_overlap = (int)in->min_overlap;
+        if (in->rows_per_thread) {
+            if (in->rows_per_thread != 8 && in->rows_per_thread != 16 && in->rows_per_thread != 32)
+                return fail(QSIM_ERR_INVALID, "rows_per_thread must be 8, 16 or 32");
+            t.rows_eb = (uint32_t)__builtin_ctz(in->rows_per_thread);
+        }
     }
     if (t.mid_low_bits < 1 || t.mid_low_bits > t.low_bits) t.mid_low_bits = t.low_bits;
     if (t.outer_order > 1) return fail(QSIM_ERR_INVALID, "outer_order out of range");
@@ -112,6 +119,8 @@ int tuning_from(const qsim_tuning *in, uint32_t elem, Tuning *out) {
     const int max_tile = elem == 8 ? kMaxTileBits : kMaxTileBits - 1;
     if (t.tile_bits < 5 || t.tile_bits > max_tile)
         return fail(QSIM_ERR_INVALID, "tile_bits out of range");
+    if ((uint32_t)t.tile_bits < t.rows_eb || (uint32_t)t.tile_bits - t.rows_eb > 10)
+        return fail(QSIM_ERR_INVALID, "tile_bits and rows_per_thread need 1..1024 threads per tile");
     if (t.low_bits < 1 || t.low_bits > t.tile_bits) return fail(QSIM_ERR_INVALID, "low_bits out of range");
     if (t.max_seg_steps < 1 || t.max_seg_steps > 4096) return fail(QSIM_ERR_INVALID, "max_seg_steps out of range");
     if (t.small_bits < 4 || t.small_bits > max_tile) return fail(QSIM_ERR_INVALID, "small_bits out of range");
@@ -287,6 +296,7 @@ void prepare_small(uint32_t M, uint32_t elem, const qsim_step *steps, uint64_t L
     l.inner_off = push_inner(pr.blob, inner);
     l.ta.n_inner = (uint32_t)L;
     l.ta.tb = M - 5;
+    l.ta.eb = 5;
     l.ta.n_out = 0;
     const uint32_t LO = elem == 8 ? 1 : 0;
     for (uint32_t b = 0; b < 16; ++b) l.ta.pos_src[b] = l.ta.pos_dst[b] = (uint8_t)b;
@@ -334,7 +344,7 @@ void make_layout(uint32_t M, uint32_t fixed, uint64_t A, uint64_t B, uint8_t *la
 
 int prepare_passes(uint32_t M, uint32_t elem, const std::vector<Pass> &passes,
                    const uint32_t *target, const uint64_t *cmask, uint32_t outer_order, bool remap,
-                   Prepared &pr) {
+                   uint32_t eb, Prepared &pr) {
     const uint32_t LO = elem == 8 ? 1 : 0;
     const size_t P = passes.size();
     // Layouts at the pass boundaries; the state enters and leaves in the
@@ -357,7 +367,7 @@ int prepare_passes(uint32_t M, uint32_t elem, const std::vector<Pass> &passes,
         // The tile kernel needs 32 entries per thread, at most 2^14 entries,
         // tile offsets below 2^32 and, for 8-byte entries, address bit 0 in
         // the tile (entries travel in adjacent pairs).
-        if (K < 5 || K > (uint32_t)kMaxTileBits || (M - K) > (uint32_t)kMaxOuterBits ||
+        if (K < eb || K - eb > 10 || K > (uint32_t)kMaxTileBits || (M - K) > (uint32_t)kMaxOuterBits ||
             (I >> 32) != 0 || (elem == 8 && !(I & 1ull)) || (elem == 16 && K > (uint32_t)kMaxTileBits - 1))
             return fail(QSIM_ERR_INVALID, "planner produced a tile the kernel cannot run");
         const uint8_t *ls = lam[pi].data(), *ld = lam[pi + 1].data();
@@ -436,9 +446,10 @@ int prepare_passes(uint32_t M, uint32_t elem, const std::vector<Pass> &passes,
         lt.ta = ta;
         lt.ta.n_inner = n_inner;
         lt.ta.rec_words = rec_words;
-        lt.ta.tb = K - 5;
+        lt.ta.tb = K - eb;
+        lt.ta.eb = eb;
         lt.ta.n_out = no;
-        const uint32_t vpt = 32u >> LO;
+        const uint32_t vpt = (1u << eb) >> LO;
         for (uint32_t r = 0; r < 32; ++r) {
             const uint64_t j = (uint64_t)r << (LO + lt.ta.tb);
             lt.ta.off_r_src[r] = r < vpt ? (uint32_t)pdep(j, ta.pos_src, K) : 0u;
@@ -473,7 +484,8 @@ int prepare(qsim_state *s, const qsim_step *steps, uint64_t L, Prepared &pr) {
     } catch (const std::exception &e) {
         return fail(QSIM_ERR_INVALID, std::string("planner: ") + e.what());
     }
-    return prepare_passes(M, s->elem, passes, tg.data(), cm.data(), s->tune.outer_order, s->tune.remap, pr);
+    return prepare_passes(M, s->elem, passes, tg.data(), cm.data(), s->tune.outer_order, s->tune.remap,
+                          s->tune.rows_eb, pr);
 }
 
 // Timing helpers: a launch of `kind` (0 tile, 1 map, 2 other) is bracketed
@@ -661,7 +673,7 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
             try {
                 std::vector<Pass> passes = plan_passes(s->M, tg.data(), cm.data(), L, pc);
                 bp.rc = prepare_passes(s->M, elem, passes, tg.data(), cm.data(), s->tune.outer_order, s->tune.remap,
-                                       bp.pr);
+                                       5u, bp.pr);
                 if (bp.rc) bp.err = g_err;
             } catch (const std::exception &e) {
                 bp.rc = QSIM_ERR_INVALID;
@@ -987,7 +999,7 @@ int qsim_apply_tile_pass(qsim_state *s, uint64_t tile_mask, const qsim_step *ste
     }
     Prepared pr;
     if ((rc = prepare_passes(s->M, s->elem, std::vector<Pass>{p}, tg.data(), cm.data(), s->tune.outer_order, false,
-                             pr)))
+                             s->tune.rows_eb, pr)))
         return rc;
     DeviceGuard g(s->device);
     if (!g.ok) return device_fail(s, hipErrorInvalidDevice, "set device");

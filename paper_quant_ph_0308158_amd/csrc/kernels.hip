@@ -78,15 +78,28 @@ __device__ __forceinline__ void transpose_planes(uint32_t (&w)[kPlanes]) {
         if (!(r & 1)) { uint32_t t = ((w[r] >> 1) ^ w[r + 1]) & 0x55555555u; w[r + 1] ^= t; w[r] ^= t << 1; }
 }
 
-// Tile index of lane position p of the calling thread.  For 8-byte entries
-// a thread's 16-byte vector r holds positions p = 2r, 2r+1 (adjacent rows);
-// for 16-byte entries vector r holds position p = r.
+// A thread owns E = 2^EB tile rows (EB = 3, 4 or 5), held in
+// VPT = E / (16 / ELEM) 16-byte vectors.  Tile index of lane position
+// p < E of the calling thread (for 8-byte entries vector r holds positions
+// p = 2r, 2r+1, adjacent rows; for 16-byte entries vector r holds p = r):
 //   8 B : j = (p & 1) | tid << 1 | (p >> 1) << (1 + tb)
 //   16 B: j = tid | p << tb
-template <int ELEM>
+// where 2^tb is the number of threads; the tile has tb + EB bits.
+template <int ELEM, int EB>
+struct Shape {
+    static constexpr uint32_t LO = (ELEM == 8) ? 1u : 0u;
+    static constexpr uint32_t E = 1u << EB;
+    static constexpr uint32_t VPT = E >> LO;   // 16-byte vectors per thread
+    static constexpr uint32_t EPV = 16u / ELEM;
+};
+
+template <int ELEM, int EB>
+using TileVecs = vec16[Shape<ELEM, EB>::VPT];
+
+template <int ELEM, int EB>
 __device__ __forceinline__ void init_planes(uint32_t (&w)[kPlanes], uint32_t tid, uint32_t tb) {
-    constexpr uint32_t LO = (ELEM == 8) ? 1u : 0u;
-    const uint32_t K = tb + 5u;
+    constexpr uint32_t LO = Shape<ELEM, EB>::LO;
+    const uint32_t K = tb + EB;
 #pragma unroll
     for (uint32_t b = 0; b < (uint32_t)kPlanes; ++b) {
         uint32_t v;
@@ -157,39 +170,37 @@ __device__ __forceinline__ uint64_t outer_address(const TileArgs &a, uint64_t ti
     return base;
 }
 
-template <int ELEM>
-__device__ __forceinline__ void load_tile(vec16 (&v)[32u >> ((ELEM == 8) ? 1 : 0)], const vec16 *__restrict__ src,
+template <int ELEM, int EB>
+__device__ __forceinline__ void load_tile(TileVecs<ELEM, EB> &v, const vec16 *__restrict__ src,
                                           uint64_t base, const TileArgs &a) {
-    constexpr uint32_t VPT = 32u >> ((ELEM == 8) ? 1 : 0);
-    constexpr uint32_t EPV = 16u / ELEM;
 #pragma unroll
-    for (uint32_t r = 0; r < VPT; ++r) v[r] = ld_nt(src + (base + a.off_r_src[r]) / EPV);
+    for (uint32_t r = 0; r < Shape<ELEM, EB>::VPT; ++r)
+        v[r] = ld_nt(src + (base + a.off_r_src[r]) / Shape<ELEM, EB>::EPV);
 }
 
-// Source tile index of each of the calling thread's 32 output positions,
-// as bit-planes transposed to 16-bit indices (see src_of).
-template <int ELEM, bool FLAGS>
+// Source tile index of each of the calling thread's output positions, as
+// bit-planes transposed to 16-bit indices (see src_of).
+template <int ELEM, int EB, bool FLAGS>
 __device__ __forceinline__ void tile_sources(uint32_t (&w)[kPlanes], const TileArgs &a,
                                              const uint32_t *__restrict__ flags) {
-    init_planes<ELEM>(w, threadIdx.x, a.tb);
+    init_planes<ELEM, EB>(w, threadIdx.x, a.tb);
     walk_inner<FLAGS>(w, a.inner, a.n_inner, flags);
     transpose_planes(w);
 }
 
-template <int ELEM>
-__device__ __forceinline__ void tile_stage(const vec16 (&v)[32u >> ((ELEM == 8) ? 1 : 0)], uint32_t tb, vec16 *lds) {
-    constexpr uint32_t VPT = 32u >> ((ELEM == 8) ? 1 : 0);
+template <int ELEM, int EB>
+__device__ __forceinline__ void tile_stage(const TileVecs<ELEM, EB> &v, uint32_t tb, vec16 *lds) {
 #pragma unroll
-    for (uint32_t r = 0; r < VPT; ++r) lds[threadIdx.x | (r << tb)] = v[r];
+    for (uint32_t r = 0; r < Shape<ELEM, EB>::VPT; ++r) lds[threadIdx.x | (r << tb)] = v[r];
 }
 
 // Gather the calling thread's output entries from the staged source tile
 // and store them with 16-byte stores.
-template <int ELEM>
+template <int ELEM, int EB>
 __device__ __forceinline__ void tile_emit(const uint32_t (&w)[kPlanes], vec16 *__restrict__ dst, uint64_t dst_base,
                                           const TileArgs &a, const vec16 *lds) {
-    constexpr uint32_t VPT = 32u >> ((ELEM == 8) ? 1 : 0);
-    constexpr uint32_t EPV = 16u / ELEM;
+    constexpr uint32_t VPT = Shape<ELEM, EB>::VPT;
+    constexpr uint32_t EPV = Shape<ELEM, EB>::EPV;
     if (ELEM == 8) {
         const uint2 *l2 = reinterpret_cast<const uint2 *>(lds);
 #pragma unroll
@@ -212,16 +223,20 @@ __device__ __forceinline__ void tile_emit(const uint32_t (&w)[kPlanes], vec16 *_
 // ~0 the loads of the next source tile are issued into `v` as soon as the
 // current one is in LDS, so they overlap the gather, the stores and the
 // next tile's walk.
-template <int ELEM, bool FLAGS>
-__device__ __forceinline__ void tile_step(vec16 (&v)[32u >> ((ELEM == 8) ? 1 : 0)], const vec16 *__restrict__ src,
+template <int ELEM, int EB, bool FLAGS>
+__device__ __forceinline__ void tile_step(TileVecs<ELEM, EB> &v, const vec16 *__restrict__ src,
                                           vec16 *__restrict__ dst, uint64_t dst_base, uint64_t next_base,
                                           const TileArgs &a, const uint32_t *__restrict__ flags, vec16 *lds) {
     uint32_t w[kPlanes];
-    tile_sources<ELEM, FLAGS>(w, a, flags);
-    tile_stage<ELEM>(v, a.tb, lds);
+    tile_sources<ELEM, EB, FLAGS>(w, a, flags);
+    tile_stage<ELEM, EB>(v, a.tb, lds);
     __syncthreads();
-    if (next_base != ~0ull) load_tile<ELEM>(v, src, next_base, a);
-    tile_emit<ELEM>(w, dst, dst_base, a, lds);
+    if (next_base != ~0ull) load_tile<ELEM, EB>(v, src, next_base, a);
+    tile_emit<ELEM, EB>(w, dst, dst_base, a, lds);
+}
+
+__device__ __forceinline__ uint64_t rec_base(const uint32_t *rec) {
+    return (uint64_t)uni(rec[0]) | ((uint64_t)uni(rec[1]) << 32);
 }
 
 // Fused tile pass.  DEPTH = 0: one tile per workgroup.  DEPTH >= 1: a grid
@@ -229,16 +244,12 @@ __device__ __forceinline__ void tile_step(vec16 (&v)[32u >> ((ELEM == 8) ? 1 : 0
 // gridDim.x, ...; the loads of each tile are issued DEPTH tiles ahead, into
 // one of DEPTH register buffers, so they overlap the gathers, stores and
 // walks of the tiles in between.
-template <int ELEM>
-__device__ __forceinline__ uint64_t rec_base(const uint32_t *rec) {
-    return (uint64_t)uni(rec[0]) | ((uint64_t)uni(rec[1]) << 32);
-}
-
-template <int ELEM, int DEPTH>
-__global__ void __launch_bounds__(512) k_tile(const vec16 *__restrict__ src, vec16 *__restrict__ dst,
-                                              TileArgs a, uint64_t n_tiles) {
+template <int ELEM, int DEPTH, int EB>
+__global__ void __launch_bounds__(EB == 5 ? 512 : 1024) k_tile(const vec16 *__restrict__ src,
+                                                              vec16 *__restrict__ dst, TileArgs a,
+                                                              uint64_t n_tiles) {
     extern __shared__ vec16 lds[];
-    constexpr uint32_t VPT = 32u >> ((ELEM == 8) ? 1 : 0);
+    constexpr uint32_t VPT = Shape<ELEM, EB>::VPT;
     constexpr int NB = DEPTH > 0 ? DEPTH : 1;
     const uint32_t off_src = thread_offset<ELEM>(a.pos_src, a.tb, threadIdx.x);
     const uint32_t off_dst = thread_offset<ELEM>(a.pos_dst, a.tb, threadIdx.x);
@@ -247,7 +258,7 @@ __global__ void __launch_bounds__(512) k_tile(const vec16 *__restrict__ src, vec
 #pragma unroll
     for (int d = 0; d < NB; ++d) {
         const uint64_t t = blockIdx.x + (uint64_t)d * stride;
-        if (t < n_tiles) load_tile<ELEM>(v[d], src, rec_base<ELEM>(a.rec + t * a.rec_words) + off_src, a);
+        if (t < n_tiles) load_tile<ELEM, EB>(v[d], src, rec_base(a.rec + t * a.rec_words) + off_src, a);
     }
     for (uint64_t first = blockIdx.x;; first += (uint64_t)NB * stride) {
 #pragma unroll
@@ -256,9 +267,9 @@ __global__ void __launch_bounds__(512) k_tile(const vec16 *__restrict__ src, vec
             if (tile >= n_tiles) return;   // uniform over the workgroup
             const uint64_t next = tile + (uint64_t)NB * stride;
             const uint64_t next_base =
-                (DEPTH > 0 && next < n_tiles) ? rec_base<ELEM>(a.rec + next * a.rec_words) + off_src : ~0ull;
-            tile_step<ELEM, true>(v[d], src, dst, outer_address(a, tile) + off_dst, next_base, a,
-                                  a.rec + tile * a.rec_words + 2, lds);
+                (DEPTH > 0 && next < n_tiles) ? rec_base(a.rec + next * a.rec_words) + off_src : ~0ull;
+            tile_step<ELEM, EB, true>(v[d], src, dst, outer_address(a, tile) + off_dst, next_base, a,
+                                      a.rec + tile * a.rec_words + 2, lds);
             __syncthreads();
         }
     }
@@ -269,11 +280,10 @@ template <int ELEM>
 __global__ void __launch_bounds__(512) k_small(const vec16 *__restrict__ src, vec16 *__restrict__ dst,
                                                TileArgs a) {
     extern __shared__ vec16 lds[];
-    constexpr uint32_t VPT = 32u >> ((ELEM == 8) ? 1 : 0);
-    vec16 v[VPT];
-    load_tile<ELEM>(v, src, thread_offset<ELEM>(a.pos_src, a.tb, threadIdx.x), a);
-    tile_step<ELEM, false>(v, src, dst, thread_offset<ELEM>(a.pos_dst, a.tb, threadIdx.x), ~0ull, a, nullptr,
-                           lds);
+    vec16 v[Shape<ELEM, 5>::VPT];
+    load_tile<ELEM, 5>(v, src, thread_offset<ELEM>(a.pos_src, a.tb, threadIdx.x), a);
+    tile_step<ELEM, 5, false>(v, src, dst, thread_offset<ELEM>(a.pos_dst, a.tb, threadIdx.x), ~0ull, a, nullptr,
+                              lds);
 }
 
 // Per-tile record of a pass: source tile address and the outside-control
@@ -402,7 +412,7 @@ __device__ __forceinline__ void wait_at_least(uint32_t *p, uint32_t target, uint
 // direct walk per row.
 template <int ELEM>
 __device__ __forceinline__ void small_item(const BatchSmall &sm, vec16 *lds) {
-    constexpr uint32_t VPT = 32u >> ((ELEM == 8) ? 1 : 0);
+    constexpr uint32_t VPT = Shape<ELEM, 5>::VPT;
     const uint32_t tid = threadIdx.x;
     if (sm.direct) {
         if (tid < (1u << sm.M)) {
@@ -426,12 +436,12 @@ __device__ __forceinline__ void small_item(const BatchSmall &sm, vec16 *lds) {
     const uint32_t off = active ? thread_offset<ELEM>(a.pos_src, a.tb, tid) : 0u;
     if (active) {
         vec16 v[VPT];
-        load_tile<ELEM>(v, src, off, a);
-        tile_sources<ELEM, false>(w, a, nullptr);
-        tile_stage<ELEM>(v, a.tb, lds);
+        load_tile<ELEM, 5>(v, src, off, a);
+        tile_sources<ELEM, 5, false>(w, a, nullptr);
+        tile_stage<ELEM, 5>(v, a.tb, lds);
     }
     __syncthreads();
-    if (active) tile_emit<ELEM>(w, dst, off, a, lds);
+    if (active) tile_emit<ELEM, 5>(w, dst, off, a, lds);
 }
 
 template <int ELEM>
@@ -441,7 +451,7 @@ __global__ void __launch_bounds__(256) k_batch(const BatchPass *__restrict__ pas
                                                uint32_t *ctr, uint32_t n_rec_blocks, uint32_t spin_limit) {
     extern __shared__ vec16 lds[];
     __shared__ uint32_t s_item;
-    constexpr uint32_t VPT = 32u >> ((ELEM == 8) ? 1 : 0);
+    constexpr uint32_t VPT = Shape<ELEM, 5>::VPT;
     const uint32_t tid = threadIdx.x;
     for (;;) {
         if (tid == 0) s_item = __hip_atomic_fetch_add(&ctr[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -476,10 +486,9 @@ __global__ void __launch_bounds__(256) k_batch(const BatchPass *__restrict__ pas
             const uint32_t off_src = thread_offset<ELEM>(a.pos_src, a.tb, tid);
             const uint32_t off_dst = thread_offset<ELEM>(a.pos_dst, a.tb, tid);
             vec16 v[VPT];
-            load_tile<ELEM>(v, static_cast<const vec16 *>(bp.src),
-                            ((uint64_t)uni(rec[0]) | ((uint64_t)uni(rec[1]) << 32)) + off_src, a);
-            tile_step<ELEM, true>(v, static_cast<const vec16 *>(bp.src), static_cast<vec16 *>(bp.dst),
-                                  outer_address(a, tile) + off_dst, ~0ull, a, rec + 2, lds);
+            load_tile<ELEM, 5>(v, static_cast<const vec16 *>(bp.src), rec_base(rec) + off_src, a);
+            tile_step<ELEM, 5, true>(v, static_cast<const vec16 *>(bp.src), static_cast<vec16 *>(bp.dst),
+                                     outer_address(a, tile) + off_dst, ~0ull, a, rec + 2, lds);
             release_agent();
             __syncthreads();
             if (tid == 0)
@@ -547,13 +556,14 @@ uint64_t resident_blocks(KernelT kernel, uint32_t threads, size_t lds) {
     return (uint64_t)cus * (uint64_t)(per_cu > 0 ? per_cu : 1);
 }
 
-template <int ELEM, int DEPTH>
+template <int ELEM, int DEPTH, int EB>
 hipError_t launch_tile_t(const void *src, void *dst, uint64_t n_tiles, const TileArgs &a, uint32_t wg_per_cu,
                          hipStream_t st) {
-    const size_t lds = (size_t)ELEM << (a.tb + 5);
+    const size_t lds = (size_t)ELEM << (a.tb + EB);
     const uint32_t threads = 1u << a.tb;
+    if (threads > (EB == 5 ? 512u : 1024u)) return hipErrorInvalidValue;
     hipError_t e;
-    if ((e = allow_lds(k_tile<ELEM, DEPTH>, lds)) != hipSuccess) return e;
+    if ((e = allow_lds(k_tile<ELEM, DEPTH, EB>, lds)) != hipSuccess) return e;
     uint64_t grid = n_tiles;
     if (DEPTH > 0) {
         uint64_t r = 0;
@@ -563,27 +573,38 @@ hipError_t launch_tile_t(const void *src, void *dst, uint64_t n_tiles, const Til
             if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
             r = (uint64_t)cus * wg_per_cu;
         } else {
-            r = resident_blocks(k_tile<ELEM, DEPTH>, threads, lds);
+            r = resident_blocks(k_tile<ELEM, DEPTH, EB>, threads, lds);
         }
         if (r > 0 && r < grid) grid = r;
     }
-    hipLaunchKernelGGL((k_tile<ELEM, DEPTH>), dim3((uint32_t)grid), dim3(threads), lds, st,
+    hipLaunchKernelGGL((k_tile<ELEM, DEPTH, EB>), dim3((uint32_t)grid), dim3(threads), lds, st,
                        (const vec16 *)src, (vec16 *)dst, a, n_tiles);
     return hipGetLastError();
 }
 
+template <int ELEM, int EB>
+hipError_t launch_tile_e(const void *src, void *dst, uint64_t n_tiles, const TileArgs &a, uint32_t variant,
+                         uint32_t wg_per_cu, hipStream_t st) {
+    if constexpr (ELEM == 8)
+        if (variant == 2) return launch_tile_t<ELEM, 2, EB>(src, dst, n_tiles, a, wg_per_cu, st);
+    if (variant >= 1) return launch_tile_t<ELEM, 1, EB>(src, dst, n_tiles, a, wg_per_cu, st);
+    return launch_tile_t<ELEM, 0, EB>(src, dst, n_tiles, a, wg_per_cu, st);
+}
+
 // variant 0: one tile per workgroup; 1: persistent, loads one tile ahead;
 // 2: persistent, loads two tiles ahead (8-byte entries only: the two
-// register buffers of 16-byte entries would not fit).
+// register buffers of 16-byte entries would not fit).  a.eb = log2 of the
+// rows per thread (3, 4 or 5).
 hipError_t launch_tile(uint32_t elem, const void *src, void *dst, uint64_t n_tiles, const TileArgs &a,
                        uint32_t variant, uint32_t wg_per_cu, hipStream_t st) {
     if (elem == 8) {
-        if (variant == 2) return launch_tile_t<8, 2>(src, dst, n_tiles, a, wg_per_cu, st);
-        if (variant == 1) return launch_tile_t<8, 1>(src, dst, n_tiles, a, wg_per_cu, st);
-        return launch_tile_t<8, 0>(src, dst, n_tiles, a, wg_per_cu, st);
+        if (a.eb == 3) return launch_tile_e<8, 3>(src, dst, n_tiles, a, variant, wg_per_cu, st);
+        if (a.eb == 4) return launch_tile_e<8, 4>(src, dst, n_tiles, a, variant, wg_per_cu, st);
+        return launch_tile_e<8, 5>(src, dst, n_tiles, a, variant, wg_per_cu, st);
     }
-    if (variant >= 1) return launch_tile_t<16, 1>(src, dst, n_tiles, a, wg_per_cu, st);
-    return launch_tile_t<16, 0>(src, dst, n_tiles, a, wg_per_cu, st);
+    if (a.eb == 3) return launch_tile_e<16, 3>(src, dst, n_tiles, a, variant, wg_per_cu, st);
+    if (a.eb == 4) return launch_tile_e<16, 4>(src, dst, n_tiles, a, variant, wg_per_cu, st);
+    return launch_tile_e<16, 5>(src, dst, n_tiles, a, variant, wg_per_cu, st);
 }
 
 hipError_t launch_plain_step(uint32_t elem, void *buf, uint32_t M, uint32_t target,

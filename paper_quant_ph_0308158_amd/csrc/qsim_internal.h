@@ -10,9 +10,9 @@
 
 namespace qsim {
 
-// Entries per LDS tile are 2^(tb + 5): every thread of a tile workgroup owns
-// 32 entries (one bit lane of each 32-bit bit-plane word), so a workgroup of
-// 2^tb threads covers one tile.
+// Entries per LDS tile are 2^(tb + eb): every thread of a tile workgroup owns
+// 2^eb entries (eb <= 5: one bit lane of each 32-bit bit-plane word per
+// entry), so a workgroup of 2^tb threads covers one tile.
 constexpr int kPlanes = 16;        // bit-plane registers per thread (tile bits <= 15)
 constexpr int kMaxTileBits = 14;   // 2^14 entries * 8 B = 128 KiB of LDS
 constexpr int kMaxOuterBits = 48;
@@ -46,8 +46,10 @@ struct TileArgs {
     const uint32_t *rec;    // per-tile records from the tile-map kernel (or null)
     uint32_t n_inner;
     uint32_t rec_words;     // 2 + ceil(n_inner / 32)
-    uint32_t tb;            // log2(threads per workgroup); tile bits = tb + 5
+    uint32_t tb;            // log2(threads per workgroup); tile bits = tb + eb
     uint32_t n_out;         // outer bits (M - tile bits)
+    uint32_t eb;            // log2(tile rows per thread): 3, 4 or 5
+    uint32_t pad;
     uint32_t off_r_src[32]; // element offset of the tile-index bits above the thread bits, per r (read)
     uint32_t off_r_dst[32]; // same for the write layout
     uint8_t pos_src[16];    // physical bit of tile-index bit b in the read layout

@@ -98,6 +98,11 @@ def test_sizes_default_tuning(q, M, dt):
     (11, 21, np.complex64, {"tile_bits": 14, "kernel_variant": 3}),
     (12, 19, np.complex64, {"tile_bits": 10, "kernel_variant": 3, "wg_per_cu": 2}),
     (13, 18, np.complex128, {"tile_bits": 12, "kernel_variant": 1}),
+    (14, 20, np.complex64, {"tile_bits": 13, "rows_per_thread": 8}),
+    (15, 20, np.complex64, {"tile_bits": 13, "rows_per_thread": 16, "kernel_variant": 2}),
+    (16, 19, np.complex128, {"tile_bits": 12, "rows_per_thread": 8}),
+    (17, 19, np.complex128, {"tile_bits": 13, "rows_per_thread": 16, "kernel_variant": 2}),
+    (18, 18, np.complex64, {"tile_bits": 9, "rows_per_thread": 8, "kernel_variant": 3, "small_bits": 5}),
     (10, 17, np.complex128, {"tile_bits": 11, "kernel_variant": 2, "wg_per_cu": 1, "remap": False}),
 ])
 def test_many_passes(q, seed, M, dt, tuning):
