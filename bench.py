@@ -120,7 +120,7 @@ def bench_batched(reps: int = 3):
             st.apply_packed(pk)
 
     def batched():
-        qsim.apply_batch(states, steps)
+        qsim.apply_batch_packed(states, packed)
 
     out = {}
     for name, fn in (("plain", plain), ("batched", batched)):

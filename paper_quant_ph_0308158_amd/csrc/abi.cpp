@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <chrono>
 #include <array>
 #include <atomic>
 #include <cstdlib>
@@ -646,6 +648,17 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
     const uint32_t Kb = tb + 5;
     const uint32_t threads = 1u << tb;
 
+    // Phase timings on stderr when QSIM_TRACE_BATCH is set.
+    const bool trace = std::getenv("QSIM_TRACE_BATCH") != nullptr;
+    auto t_prev = std::chrono::steady_clock::now();
+    auto lap = [&](const char *what) {
+        if (!trace) return;
+        const auto t = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "qsim batch: %-10s %8.3f ms\n", what,
+                     std::chrono::duration<double, std::milli>(t - t_prev).count());
+        t_prev = t;
+    };
+
     // 1. plan every circuit (host threads)
     std::vector<BatchCircuitPlan> plans(n);
     auto plan_one = [&](uint32_t c) {
@@ -695,6 +708,7 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
     }
     for (uint32_t c = 0; c < n; ++c)
         if (plans[c].rc) return fail(plans[c].rc, "circuit " + std::to_string(c) + ": " + plans[c].err);
+    lap("plan");
 
     // 2. lay out the workspace: header counters, items, passes, smalls, blob
     std::vector<BatchPass> bpass;
@@ -767,12 +781,14 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
     for (size_t lv = 0; lv < levels; ++lv) {
         if (lv < by_level.size())
             for (uint32_t g : by_level[lv])
-                for (uint64_t t = 0; t < bpass[g].n_tiles; ++t) items.push_back(batch_item(kItemTile, g, (uint32_t)t));
+                for (uint64_t t = 0; t * kBatchTiles < bpass[g].n_tiles; ++t)
+                    items.push_back(batch_item(kItemTile, g, (uint32_t)t));
         const size_t upto = n_small * (lv + 1) / levels;
         for (; small_next < upto; ++small_next) items.push_back(batch_item(kItemSmall, (uint32_t)small_next, 0));
     }
     for (; small_next < n_small; ++small_next) items.push_back(batch_item(kItemSmall, (uint32_t)small_next, 0));
     if (items.size() > 0xFFFFFFF0ull) return fail(QSIM_ERR_INVALID, "batch too large");
+    lap("queue");
 
     const size_t ctr_bytes = ((kBatchCtrHeader + n) * 4 + 255) & ~size_t(255);
     const size_t items_off = ctr_bytes;
@@ -814,6 +830,7 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
     for (uint32_t c = 0; c < n; ++c)
         if (!plans[c].pr.blob.empty())
             std::memcpy(h + blob_off + circuit_blob_off[c], plans[c].pr.blob.data(), plans[c].pr.blob.size());
+    lap("stage");
     if ((e = hipMemcpyAsync(dev, h, total, hipMemcpyHostToDevice, st)) != hipSuccess)
         return fail(QSIM_ERR_DEVICE, std::string("batch upload: ") + hipGetErrorString(e));
     if ((e = hipEventRecord(w.stage.ev, st)) != hipSuccess) return fail(QSIM_ERR_DEVICE, "batch event");
@@ -831,6 +848,7 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
     }
     if ((e = hipEventRecord(w.done, st)) != hipSuccess) return fail(QSIM_ERR_DEVICE, "batch event");
     w.pending = true;
+    lap("launch");
     // every circuit's result sits in the buffer its last pass wrote
     std::vector<uint32_t> flips(n, 0);
     for (size_t k = 0; k < bsmall.size(); ++k) flips[small_circuit[k]] = 1;

@@ -391,14 +391,23 @@ __global__ void __launch_bounds__(256) k_copy(const vec16 *__restrict__ src, vec
 
 // ------------------------------------------------------------ batched mode
 
-__device__ __forceinline__ void release_agent() { __atomic_thread_fence(__ATOMIC_RELEASE); }
+// Publishing an item's results to workgroups on other XCDs (separate L2
+// caches): every wave first waits until its own stores have reached its
+// XCD's L2 (s_waitcnt 0 — a workgroup-scope fence alone does not wait for
+// them), the workgroup barrier then orders them before thread 0's
+// agent-scope release (one L2 writeback) and counter increment.
+__device__ __forceinline__ void publish(uint32_t *counter, uint32_t count) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(counter, count, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
 
-// Thread 0 waits until *p >= target (agent-scope acquire); a wait that runs
-// past `limit` polls raises the error flag and gives up, so the launch
-// always ends.
+// Thread 0 waits until *p >= target (relaxed polls); a wait that runs past
+// `limit` polls raises the error flag and gives up, so the launch always
+// ends.  The caller follows with one agent-scope acquire and a barrier.
 __device__ __forceinline__ void wait_at_least(uint32_t *p, uint32_t target, uint32_t *err, uint32_t limit) {
     uint32_t n = 0;
-    while (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
         if (++n > limit) {
             __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             break;
@@ -453,10 +462,18 @@ __global__ void __launch_bounds__(256) k_batch(const BatchPass *__restrict__ pas
     __shared__ uint32_t s_item;
     constexpr uint32_t VPT = Shape<ELEM, 5>::VPT;
     const uint32_t tid = threadIdx.x;
-    for (;;) {
-        if (tid == 0) s_item = __hip_atomic_fetch_add(&ctr[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
-        const uint32_t it = s_item;
+    // Items are taken from the queue kBatchGroup at a time (one atomic per
+    // group) and processed in queue order; every item depends only on
+    // earlier items, so holding a group cannot deadlock.
+    for (uint32_t it = 0, end = 0;; ++it) {
+        if (it >= end) {
+            __syncthreads();
+            if (tid == 0)
+                s_item = __hip_atomic_fetch_add(&ctr[0], kBatchGroup, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();
+            it = s_item;
+            end = it + kBatchGroup;
+        }
         if (it >= n_items) break;   // the same value for the whole workgroup
         const uint64_t e = items[it];
         const uint32_t kind = (uint32_t)(e >> 62);
@@ -466,9 +483,7 @@ __global__ void __launch_bounds__(256) k_batch(const BatchPass *__restrict__ pas
             const BatchPass &bp = passes[idx];
             const uint64_t tile = (uint64_t)sub * blockDim.x + tid;
             if (tile < bp.n_tiles) tilemap_one(bp.tm, tile);
-            release_agent();
-            __syncthreads();
-            if (tid == 0) __hip_atomic_fetch_add(&ctr[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            publish(&ctr[1], 1u);
         } else if (kind == kItemSmall) {
             small_item<ELEM>(smalls[idx], lds);
         } else {
@@ -477,23 +492,28 @@ __global__ void __launch_bounds__(256) k_batch(const BatchPass *__restrict__ pas
                 wait_at_least(&ctr[1], n_rec_blocks, &ctr[2], spin_limit);
                 wait_at_least(&ctr[kBatchCtrHeader + bp.circuit], bp.level * (uint32_t)bp.n_tiles, &ctr[2],
                               spin_limit);
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
             __syncthreads();
-            __atomic_thread_fence(__ATOMIC_ACQUIRE);
+            // a block of up to kBatchTiles tiles of one pass, the loads of
+            // each tile issued while the previous one is gathered and stored
             const TileArgs &a = bp.ta;
-            const uint64_t tile = sub;
-            const uint32_t *rec = a.rec + tile * a.rec_words;
+            const uint64_t t0 = (uint64_t)sub * kBatchTiles;
+            const uint64_t t1 = t0 + kBatchTiles < bp.n_tiles ? t0 + kBatchTiles : bp.n_tiles;
+            const vec16 *src = static_cast<const vec16 *>(bp.src);
+            vec16 *dst = static_cast<vec16 *>(bp.dst);
             const uint32_t off_src = thread_offset<ELEM>(a.pos_src, a.tb, tid);
             const uint32_t off_dst = thread_offset<ELEM>(a.pos_dst, a.tb, tid);
             vec16 v[VPT];
-            load_tile<ELEM, 5>(v, static_cast<const vec16 *>(bp.src), rec_base(rec) + off_src, a);
-            tile_step<ELEM, 5, true>(v, static_cast<const vec16 *>(bp.src), static_cast<vec16 *>(bp.dst),
-                                     outer_address(a, tile) + off_dst, ~0ull, a, rec + 2, lds);
-            release_agent();
-            __syncthreads();
-            if (tid == 0)
-                __hip_atomic_fetch_add(&ctr[kBatchCtrHeader + bp.circuit], 1u, __ATOMIC_RELEASE,
-                                       __HIP_MEMORY_SCOPE_AGENT);
+            load_tile<ELEM, 5>(v, src, rec_base(a.rec + t0 * a.rec_words) + off_src, a);
+            for (uint64_t tile = t0; tile < t1; ++tile) {
+                const uint64_t next_base =
+                    tile + 1 < t1 ? rec_base(a.rec + (tile + 1) * a.rec_words) + off_src : ~0ull;
+                tile_step<ELEM, 5, true>(v, src, dst, outer_address(a, tile) + off_dst, next_base, a,
+                                         a.rec + tile * a.rec_words + 2, lds);
+                __syncthreads();
+            }
+            publish(&ctr[kBatchCtrHeader + bp.circuit], (uint32_t)(t1 - t0));
         }
         __syncthreads();
     }

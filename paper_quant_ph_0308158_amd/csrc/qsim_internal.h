@@ -104,6 +104,8 @@ __host__ __device__ inline uint64_t batch_item(uint32_t kind, uint32_t index, ui
 // blocks, [2] error flag (a dependency wait ran out), [3] reserved,
 // [4 + c] finished tiles of circuit c.
 constexpr uint32_t kBatchCtrHeader = 4;
+constexpr uint32_t kBatchGroup = 4;   // queue items taken per atomic
+constexpr uint32_t kBatchTiles = 8;   // tiles of one pass per tile item
 
 // Host-side plan of the fused path.
 struct Pass {

@@ -328,6 +328,16 @@ def apply_batch(states: Sequence[State], steps: Sequence[Tuple[np.ndarray, np.nd
                                  ctypes.cast(ls, ctypes.c_void_p), n, ctypes.c_void_p(_stream_ptr(stream))))
 
 
+def apply_batch_packed(states: Sequence[State], packed: Sequence[np.ndarray], stream=None):
+    """apply_batch with step arrays already packed by pack_steps."""
+    n = len(states)
+    hs = (ctypes.c_void_p * n)(*[s.handle.value for s in states])
+    ps = (ctypes.c_void_p * n)(*[p.ctypes.data if len(p) else None for p in packed])
+    ls = (ctypes.c_uint64 * n)(*[len(p) for p in packed])
+    _check(_lib.qsim_apply_batch(ctypes.cast(hs, ctypes.c_void_p), ctypes.cast(ps, ctypes.c_void_p),
+                                 ctypes.cast(ls, ctypes.c_void_p), n, ctypes.c_void_p(_stream_ptr(stream))))
+
+
 def batch_status():
     """Wait for the last batched launch; raise if it did not complete cleanly."""
     _check(_lib.qsim_batch_last_status())
