@@ -109,6 +109,18 @@ const void *qsim_state_current(const qsim_state *state);
 int qsim_write_portion(qsim_state *state, uint64_t offset, uint64_t count,
                        const void *host_src);
 
+/* Set the current vector to the Kronecker product q_M (x) ... (x) q_1 of M
+ * qubit pairs, computed on the device (the input calculated on the fly of
+ * Appendix 1): entry i = q_M(bit M-1 of i) * ... * q_1(bit 0 of i).  The
+ * product is taken from q_M down to q_1 in the entries' precision (float
+ * for QSIM_C64, double for QSIM_C128), each complex product formed as
+ * (ac - bd) + (ad + bc)i with every operation rounded separately, so the
+ * result does not depend on the device.  `qubits` (host memory, read
+ * before the call returns) holds 2M complex numbers of the entry type:
+ * q_b(v) at index 2(b-1) + v.  Enqueued on hip_stream; one write of the
+ * state, no read. */
+int qsim_state_set_product(qsim_state *state, const void *qubits, void *hip_stream);
+
 /* Apply the wiring diagram: current <- U_L ... U_1 current, with steps[0]
  * acting first (Sec. 2(a), 2(h)).  `steps` is caller-owned and is read
  * before the call returns.  Work is enqueued on `hip_stream` (a

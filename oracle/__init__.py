@@ -59,6 +59,11 @@ def _load():
     lib.oracle_sample_rows.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p,
                                        u32p, u64p, ctypes.c_uint64, u64p, ctypes.c_uint64,
                                        ctypes.c_void_p, ctypes.c_int]
+    lib.oracle_product_state.restype = ctypes.c_int
+    lib.oracle_product_state.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p]
+    lib.oracle_product_entry.restype = ctypes.c_int
+    lib.oracle_product_entry.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint64,
+                                         ctypes.c_void_p]
     lib.oracle_max_threads.restype = ctypes.c_int
     lib.oracle_max_threads.argtypes = []
     _lib = lib
@@ -150,6 +155,30 @@ def sample_rows(M: int, k1: np.ndarray, target, cmask, idx, threads: int = 1) ->
                                       ix.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
                                       len(ix), out.ctypes.data, int(threads)), "sample_rows")
     return out
+
+
+def product_state(M: int, qubits: np.ndarray) -> np.ndarray:
+    """k1 = q_M (x) ... (x) q_1 (Appendix 1) from qubits[b-1] = (q_b(0), q_b(1)),
+    an (M, 2) complex64 or complex128 array; the product runs from q_M down
+    to q_1 in the array's precision without fused multiply-adds."""
+    q = np.ascontiguousarray(qubits)
+    if q.shape != (M, 2):
+        raise ValueError("qubits must have shape (M, 2)")
+    eb = _elem_bytes(q.reshape(-1))
+    out = np.empty(1 << M, dtype=q.dtype)
+    _check(_load().oracle_product_state(M, eb, q.ctypes.data, out.ctypes.data), "product_state")
+    return out
+
+
+def product_entry(M: int, qubits: np.ndarray, i: int):
+    """k1(i) of product_state(M, qubits), computed for one row."""
+    q = np.ascontiguousarray(qubits)
+    if q.shape != (M, 2):
+        raise ValueError("qubits must have shape (M, 2)")
+    eb = _elem_bytes(q.reshape(-1))
+    out = np.empty(1, dtype=q.dtype)
+    _check(_load().oracle_product_entry(M, eb, q.ctypes.data, int(i), out.ctypes.data), "product_entry")
+    return out[0]
 
 
 def max_threads() -> int:

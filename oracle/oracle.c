@@ -229,6 +229,101 @@ int oracle_sample_rows(uint32_t M, uint32_t elem_bytes, const void *k1,
     return 0;
 }
 
+/*
+ * Input calculated from a Kronecker product of M qubit pairs (Appendix 1):
+ * k1 = q_M (x) q_{M-1} (x) ... (x) q_1, so entry i is the product of
+ * q_b(bit b-1 of i) over b = 1..M; e.g. k1(5) = q3(1) q2(0) q1(1).
+ * The product is formed in the order printed there, from q_M down to q_1,
+ * in the precision of the entries (float for elem_bytes 8, double for 16),
+ * each complex product as (ac - bd) + (ad + bc)i with every operation
+ * rounded separately (this file is compiled as ISO C, without contraction
+ * of multiply-adds).  qubits holds q_b(v) at index 2(b-1) + v as
+ * interleaved (re, im) pairs; out holds 2^M entries.
+ */
+int oracle_product_state(uint32_t M, uint32_t elem_bytes, const void *qubits, void *out)
+{
+    if (M < 1u || M > 30u) return -1;
+    if (elem_bytes != 8u && elem_bytes != 16u) return -1;
+    if (qubits == NULL || out == NULL) return -1;
+    const uint64_t n = 1ull << M;
+    if (elem_bytes == 8u) {
+        const float *q = (const float *)qubits;
+        float *o = (float *)out;
+        for (uint64_t i = 0; i < n; ++i) {
+            uint32_t b = M;                 /* qubit q_b, address bit b-1 */
+            uint64_t v = (i >> (b - 1)) & 1u;
+            float re = q[2 * (2 * (b - 1) + v)], im = q[2 * (2 * (b - 1) + v) + 1];
+            for (b = M - 1; b >= 1; --b) {
+                v = (i >> (b - 1)) & 1u;
+                const float c = q[2 * (2 * (b - 1) + v)], d = q[2 * (2 * (b - 1) + v) + 1];
+                const float ac = re * c, bd = im * d, ad = re * d, bc = im * c;
+                re = ac - bd;
+                im = ad + bc;
+            }
+            o[2 * i] = re;
+            o[2 * i + 1] = im;
+        }
+    } else {
+        const double *q = (const double *)qubits;
+        double *o = (double *)out;
+        for (uint64_t i = 0; i < n; ++i) {
+            uint32_t b = M;
+            uint64_t v = (i >> (b - 1)) & 1u;
+            double re = q[2 * (2 * (b - 1) + v)], im = q[2 * (2 * (b - 1) + v) + 1];
+            for (b = M - 1; b >= 1; --b) {
+                v = (i >> (b - 1)) & 1u;
+                const double c = q[2 * (2 * (b - 1) + v)], d = q[2 * (2 * (b - 1) + v) + 1];
+                const double ac = re * c, bd = im * d, ad = re * d, bc = im * c;
+                re = ac - bd;
+                im = ad + bc;
+            }
+            o[2 * i] = re;
+            o[2 * i + 1] = im;
+        }
+    }
+    return 0;
+}
+
+/* One entry k1(i) of the same product (for rows of states too large to
+ * form whole); out receives one entry of elem_bytes. */
+int oracle_product_entry(uint32_t M, uint32_t elem_bytes, const void *qubits, uint64_t i, void *out)
+{
+    if (M < 1u || M > 40u || qubits == NULL || out == NULL) return -1;
+    if (elem_bytes == 8u) {
+        const float *q = (const float *)qubits;
+        uint32_t b = M;
+        uint64_t v = (i >> (b - 1)) & 1u;
+        float re = q[2 * (2 * (b - 1) + v)], im = q[2 * (2 * (b - 1) + v) + 1];
+        for (b = M - 1; b >= 1; --b) {
+            v = (i >> (b - 1)) & 1u;
+            const float c = q[2 * (2 * (b - 1) + v)], d = q[2 * (2 * (b - 1) + v) + 1];
+            const float ac = re * c, bd = im * d, ad = re * d, bc = im * c;
+            re = ac - bd;
+            im = ad + bc;
+        }
+        ((float *)out)[0] = re;
+        ((float *)out)[1] = im;
+        return 0;
+    }
+    if (elem_bytes == 16u) {
+        const double *q = (const double *)qubits;
+        uint32_t b = M;
+        uint64_t v = (i >> (b - 1)) & 1u;
+        double re = q[2 * (2 * (b - 1) + v)], im = q[2 * (2 * (b - 1) + v) + 1];
+        for (b = M - 1; b >= 1; --b) {
+            v = (i >> (b - 1)) & 1u;
+            const double c = q[2 * (2 * (b - 1) + v)], d = q[2 * (2 * (b - 1) + v) + 1];
+            const double ac = re * c, bd = im * d, ad = re * d, bc = im * c;
+            re = ac - bd;
+            im = ad + bc;
+        }
+        ((double *)out)[0] = re;
+        ((double *)out)[1] = im;
+        return 0;
+    }
+    return -1;
+}
+
 /* Number of threads an OpenMP region would use (1 without OpenMP). */
 int oracle_max_threads(void)
 {

@@ -983,6 +983,18 @@ int qsim_write_portion(qsim_state *s, uint64_t offset, uint64_t count, const voi
     return QSIM_OK;
 }
 
+int qsim_state_set_product(qsim_state *s, const void *qubits, void *hip_stream) {
+    int rc = check_state(s);
+    if (rc) return rc;
+    if (!qubits) return fail(QSIM_ERR_INVALID, "qubits is NULL");
+    DeviceGuard g(s->device);
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    hipError_t e = launch_product(s->elem, s->buf[s->cur], s->M, qubits, st);
+    if (e != hipSuccess) return device_fail(s, e, "product-state launch");
+    s->last_stream = st;
+    return QSIM_OK;
+}
+
 int qsim_apply_steps(qsim_state *s, const qsim_step *steps, uint64_t L, void *hip_stream) {
     int rc = check_state(s);
     if (rc) return rc;

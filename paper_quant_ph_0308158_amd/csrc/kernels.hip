@@ -24,6 +24,8 @@
 //   * the planes are transposed back to 16-bit indices, entries are gathered
 //     from LDS and stored to the output tile with coalesced 16-byte stores.
 // One pass therefore costs one read and one write of the state.
+#include <cstring>
+
 #include "qsim_internal.h"
 
 namespace qsim {
@@ -519,6 +521,70 @@ __global__ void __launch_bounds__(256) k_batch(const BatchPass *__restrict__ pas
     }
 }
 
+// ------------------------------------------------------------ product-state input
+
+// Entry i of q_M (x) ... (x) q_1 (Appendix 1: the input from M qubit pairs,
+// entry i the product of q_b(bit b-1 of i)), formed from q_M down to q_1 in
+// the entries' precision; every complex product is (ac - bd) + (ad + bc)i
+// with each operation rounded on its own (no contraction into fused
+// multiply-adds), so the value is a fixed function of the qubits.
+template <typename T>
+struct ProductArgs {
+    T q[2 * 2 * kMaxQubits];   // q_b(v) at 2 * (2(b-1) + v): (re, im)
+    uint32_t M;
+};
+
+template <typename T>
+__device__ __forceinline__ void cmul(T &re, T &im, T c, T d) {
+#pragma clang fp contract(off)
+    const T ac = re * c, bd = im * d, ad = re * d, bc = im * c;
+    re = ac - bd;
+    im = ad + bc;
+}
+
+// Fold q_b for b = hi down to lo (address bits hi-1 .. lo-1 of i) into acc.
+template <typename T>
+__device__ __forceinline__ void fold_bits(const ProductArgs<T> &a, uint64_t i, uint32_t hi, uint32_t lo, T &re,
+                                          T &im) {
+    for (uint32_t b = hi; b >= lo && b >= 1; --b) {
+        const uint32_t v = (uint32_t)((i >> (b - 1)) & 1u);
+        cmul(re, im, a.q[2 * (2 * (b - 1) + v)], a.q[2 * (2 * (b - 1) + v) + 1]);
+    }
+}
+
+// Each thread writes 16 entries i = base + 64k + lane (k = 0..15) of a
+// 1024-entry block, so a wave store covers 64 consecutive entries; the
+// factors of address bits 10 and up (q_11 .. q_M) are folded once per
+// thread.  States with M < 11 use one entry per thread.
+template <typename T>
+__global__ void __launch_bounds__(256) k_product(T *__restrict__ out, ProductArgs<T> a, uint64_t n) {
+    const uint32_t M = a.M;
+    if (M < 11) {
+        const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        if (i >= n) return;
+        const uint32_t v = (uint32_t)((i >> (M - 1)) & 1u);
+        T re = a.q[2 * (2 * (M - 1) + v)], im = a.q[2 * (2 * (M - 1) + v) + 1];
+        fold_bits(a, i, M - 1, 1, re, im);
+        out[2 * i] = re;
+        out[2 * i + 1] = im;
+        return;
+    }
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t lane = (uint32_t)(t & 63u);
+    const uint64_t base = (t >> 6) << 10;
+    if (base >= n) return;
+    const uint32_t vtop = (uint32_t)((base >> (M - 1)) & 1u);
+    T pre_re = a.q[2 * (2 * (M - 1) + vtop)], pre_im = a.q[2 * (2 * (M - 1) + vtop) + 1];
+    fold_bits(a, base, M - 1, 11, pre_re, pre_im);
+    for (uint32_t k = 0; k < 16u; ++k) {
+        const uint64_t i = base + (uint64_t)k * 64u + lane;
+        T re = pre_re, im = pre_im;
+        fold_bits(a, i, 10, 1, re, im);
+        out[2 * i] = re;
+        out[2 * i + 1] = im;
+    }
+}
+
 template <typename KernelT>
 hipError_t allow_lds(KernelT kernel, size_t bytes) {
     if (bytes <= 65536) return hipSuccess;
@@ -665,6 +731,26 @@ hipError_t launch_batch(uint32_t elem, uint32_t tb, const BatchPass *passes, con
     else
         hipLaunchKernelGGL(k_batch<16>, dim3((uint32_t)grid), dim3(threads), lds, st, passes, smalls, items,
                            n_items, counters, n_rec_blocks, spin_limit);
+    return hipGetLastError();
+}
+
+hipError_t launch_product(uint32_t elem, void *out, uint32_t M, const void *qubits, hipStream_t st) {
+    const uint64_t n = 1ull << M;
+    const uint32_t bs = 256;
+    const uint64_t threads = M < 11 ? n : n / 16;
+    const uint64_t grid = (threads + bs - 1) / bs;
+    if (M < 1 || M > kMaxQubits) return hipErrorInvalidValue;
+    if (elem == 8) {
+        ProductArgs<float> a{};
+        std::memcpy(a.q, qubits, sizeof(float) * 4 * M);
+        a.M = M;
+        hipLaunchKernelGGL(k_product<float>, dim3((uint32_t)grid), dim3(bs), 0, st, (float *)out, a, n);
+    } else {
+        ProductArgs<double> a{};
+        std::memcpy(a.q, qubits, sizeof(double) * 4 * M);
+        a.M = M;
+        hipLaunchKernelGGL(k_product<double>, dim3((uint32_t)grid), dim3(bs), 0, st, (double *)out, a, n);
+    }
     return hipGetLastError();
 }
 

@@ -16,6 +16,7 @@ namespace qsim {
 constexpr int kPlanes = 16;        // bit-plane registers per thread (tile bits <= 15)
 constexpr int kMaxTileBits = 14;   // 2^14 entries * 8 B = 128 KiB of LDS
 constexpr int kMaxOuterBits = 48;
+constexpr uint32_t kMaxQubits = 36;    // largest M of a state
 
 // A step as the tile-map kernel sees it (16 bytes).  `cm` is the part of the
 // control mask outside the tile; `tbit` is the address bit of the target;
@@ -148,6 +149,7 @@ hipError_t launch_tile(uint32_t elem, const void *src, void *dst, uint64_t n_til
 hipError_t launch_plain_step(uint32_t elem, void *buf, uint32_t M, uint32_t target,
                              uint64_t cmask, hipStream_t st);
 hipError_t launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t st);
+hipError_t launch_product(uint32_t elem, void *out, uint32_t M, const void *qubits, hipStream_t st);
 hipError_t launch_batch(uint32_t elem, uint32_t tb, const BatchPass *passes, const BatchSmall *smalls,
                         const uint64_t *items, uint32_t n_items, uint32_t *counters, uint32_t n_rec_blocks,
                         uint32_t spin_limit, hipStream_t st);

@@ -36,7 +36,7 @@ EXPORTS = (
     "qsim_state_set_tuning", "qsim_plan_describe", "qsim_copy_bytes", "qsim_last_error",
     "qsim_version", "qsim_state_profile", "qsim_state_profile_read", "qsim_apply_tile_pass",
     "qsim_batch_last_status", "qsim_server_create", "qsim_server_submit", "qsim_server_drain",
-    "qsim_server_request_info", "qsim_server_stats", "qsim_server_destroy",
+    "qsim_server_request_info", "qsim_server_stats", "qsim_server_destroy", "qsim_state_set_product",
 )
 
 
@@ -121,6 +121,7 @@ def _load() -> ctypes.CDLL:
         "qsim_server_request_info": (i32, [vp, ctypes.c_int64, vp]),
         "qsim_server_stats": (i32, [vp, vp, vp, vp, vp]),
         "qsim_server_destroy": (None, [vp]),
+        "qsim_state_set_product": (i32, [vp, vp, vp]),
         "qsim_state_profile_read": (i32, [vp, vp]),
     }
     for name, (res, args) in sig.items():
@@ -288,6 +289,13 @@ class State:
     def apply_packed(self, steps: np.ndarray, stream=None):
         _check(_lib.qsim_apply_steps(self._h, steps.ctypes.data if len(steps) else None, len(steps),
                                      ctypes.c_void_p(_stream_ptr(stream))))
+
+    def set_product(self, qubits: np.ndarray, stream=None):
+        """k1 = q_M (x) ... (x) q_1 from qubits[b-1] = (q_b(0), q_b(1)) (shape (M, 2))."""
+        q = np.ascontiguousarray(qubits, dtype=np_dtype(self.code))
+        if q.shape != (self.M, 2):
+            raise ValueError("qubits must have shape (M, 2)")
+        _check(_lib.qsim_state_set_product(self._h, q.ctypes.data, ctypes.c_void_p(_stream_ptr(stream))))
 
     def apply_tile_pass(self, tile_mask: int, target, cmask, stream=None):
         st = pack_steps(target, cmask)

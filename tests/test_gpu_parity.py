@@ -403,3 +403,49 @@ def test_server_small_budget_queues(q):
         assert inf["status"] == 0
         k = k1 if k1 is not None else W.alternating_state(M, np.complex64)
         assert q.digest_bytes(oracle.apply(M, k, tg, cm).tobytes()) == inf["digest"]
+
+
+# ------------------------------------------------------------------ product-state input
+
+@pytest.mark.parametrize("dt", [np.complex64, np.complex128])
+def test_product_state_matches_oracle(q, dt):
+    """qsim_state_set_product builds q_M x ... x q_1 (Appendix 1) bit-exactly
+    as the oracle does, for every M from 1 to 20; then a diagram applied to it
+    matches the oracle too."""
+    rng = np.random.default_rng(31)
+    code = "c64" if dt == np.complex64 else "c128"
+    for M in list(range(1, 21)):
+        qq = rng.standard_normal((M, 2)) + 1j * rng.standard_normal((M, 2))
+        qq = (qq / np.linalg.norm(qq, axis=1, keepdims=True)).astype(dt)
+        ref = oracle.product_state(M, qq)
+        say("product state", M, code)
+        with q.State(M, code) as s:
+            s.set_product(qq, stream=0)
+            assert_same(s.read(), ref, f"product state M={M}")
+            if M in (8, 17):
+                tg, cm = W.random_steps(rng, M, 50, (0, 3))
+                s.apply(tg, cm, stream=0)
+                assert_same(s.read(), oracle.apply(M, ref, tg, cm), f"product then apply M={M}")
+
+
+def test_product_state_m32_sampled(q):
+    """At M=32 (complex64): sampled rows against the oracle's product formula
+    evaluated for those rows, and the 2-norm of a unit-norm product."""
+    import torch
+    M = 32
+    rng = np.random.default_rng(32)
+    qq = rng.standard_normal((M, 2)) + 1j * rng.standard_normal((M, 2))
+    qq = (qq / np.linalg.norm(qq, axis=1, keepdims=True)).astype(np.complex64)
+    b0 = torch.empty(1 << M, dtype=torch.complex64, device="cuda")
+    b1 = torch.empty_like(b0)
+    s = q.State(M, "c64", buffers=(b0, b1))
+    say("product state m32")
+    s.set_product(qq)
+    torch.cuda.synchronize()
+    rows = np.concatenate([rng.integers(0, 1 << M, size=300, dtype=np.uint64), [0, 1, (1 << M) - 1]])
+    got = b0[torch.from_numpy(rows.astype(np.int64)).cuda()].cpu().numpy()
+    for r, g in zip(rows.tolist(), got):
+        assert g.tobytes() == oracle.product_entry(M, qq, r).tobytes(), f"row {r}"
+    nrm = float(torch.linalg.vector_norm(b0.view(torch.float32).double()))
+    assert abs(nrm - 1.0) < 1e-3
+    s.close()

@@ -333,3 +333,52 @@ def test_pins_accept_correct_loop():
 def test_pins_catch_planted_mistake(mutant):
     failed = _failing_pins(lambda M, v, tg, cm: _py_apply(M, v, tg, cm, mutant))
     assert failed, f"planted mistake {mutant} passed every pin"
+
+
+# ------------------------------------------------------------------ product-state input (Appendix 1)
+
+def test_product_state_appendix1_example():
+    """k1(5) = q3(1) q2(0) q1(1): with distinct primes as the qubit components
+    every product is exact and the whole vector equals the integer Kronecker
+    product q_M x ... x q_1 (bit order of Appendix 1)."""
+    primes = [2, 3, 5, 7, 11, 13, 17, 19]
+    for M, dt in ((3, np.complex128), (3, np.complex64), (4, np.complex128)):
+        q = np.array([[primes[2 * b], primes[2 * b + 1]] for b in range(M)], dtype=dt)
+        k1 = oracle.product_state(M, q)
+        kron = np.array([1], dtype=np.int64)
+        for b in range(M - 1, -1, -1):
+            kron = np.kron(kron, q[b].real.astype(np.int64))
+        np.testing.assert_array_equal(k1.real, kron)
+        np.testing.assert_array_equal(k1.imag, 0)
+        if M == 3:
+            assert k1[5] == q[2][1] * q[1][0] * q[0][1]
+
+
+def test_product_state_complex_and_norm():
+    """Complex components (exact small Gaussian integers) multiply as complex
+    numbers; unit-norm qubits give a unit-norm state (Sec. 2(b) normalisation)."""
+    q = np.array([[1 + 2j, 3 - 1j], [2 - 1j, 1j], [1 + 1j, -2 + 0j]], dtype=np.complex128)
+    k1 = oracle.product_state(3, q)
+    for i in range(8):
+        expect = q[2][(i >> 2) & 1] * q[1][(i >> 1) & 1] * q[0][i & 1]
+        assert k1[i] == expect
+    rng = np.random.default_rng(3)
+    for dt, tol in ((np.complex128, 1e-12), (np.complex64, 1e-5)):
+        qq = rng.standard_normal((12, 2)) + 1j * rng.standard_normal((12, 2))
+        qq /= np.linalg.norm(qq, axis=1, keepdims=True)
+        k = oracle.product_state(12, qq.astype(dt))
+        assert abs(np.linalg.norm(k.astype(np.complex128)) - 1.0) < tol
+        # the alternating input of Sec. 2(b) is the product of H|1> on the bottom qubit
+        # and H|0> on the others
+    s = 2 ** -0.5
+    qh = np.array([[s, -s]] + [[s, s]] * 9, dtype=np.complex128)
+    np.testing.assert_allclose(oracle.product_state(10, qh), W.alternating_state(10), rtol=0, atol=1e-15)
+
+
+def test_product_entry_matches_product_state():
+    rng = np.random.default_rng(4)
+    for dt in (np.complex64, np.complex128):
+        qq = (rng.standard_normal((11, 2)) + 1j * rng.standard_normal((11, 2))).astype(dt)
+        full = oracle.product_state(11, qq)
+        for i in (0, 1, 5, 777, 2047):
+            assert oracle.product_entry(11, qq, i).tobytes() == full[i].tobytes()
