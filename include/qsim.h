@@ -131,6 +131,22 @@ int qsim_state_set_product(qsim_state *state, const void *qubits, void *hip_stre
 int qsim_apply_steps(qsim_state *state, const qsim_step *steps, uint64_t L,
                      void *hip_stream);
 
+/* The row array x of a whole diagram (Sec. 2(h), Summary of Method): x(i)
+ * is the row of k1 that lands in row i of k2 = U_L ... U_1 k1, so that
+ * k2(i) = k1(x(i)) for every input (the information about the unitary
+ * matrix that the Conclusions propose to keep).  Built on the device by
+ * applying the diagram to the index vector (entry i = i) with the fused
+ * path; x_dev (device memory, 2^M uint32) receives it.  1 <= M <= 32.
+ * Allocates and frees a temporary state of 2 * 2^M * 8 bytes; returns when
+ * x_dev is written. */
+int qsim_rowmap_build(uint32_t M, const qsim_step *steps, uint64_t L,
+                      uint32_t *x_dev, void *hip_stream);
+
+/* current <- k1(x(i)) for the row array x_dev of qsim_rowmap_build: the
+ * same result as applying the diagram again, as one gather (a read of x,
+ * a read of the state at the rows x names, a write of the state). */
+int qsim_rowmap_apply(qsim_state *state, const uint32_t *x_dev, void *hip_stream);
+
 /* Same result as qsim_apply_steps, computed the plain way: one in-place
  * kernel launch per step that interchanges every pair of rows the step
  * toggles (the state is recalculated after each step, Sec. 2(h)).  A

@@ -995,6 +995,43 @@ int qsim_state_set_product(qsim_state *s, const void *qubits, void *hip_stream) 
     return QSIM_OK;
 }
 
+int qsim_rowmap_build(uint32_t M, const qsim_step *steps, uint64_t L, uint32_t *x_dev, void *hip_stream) {
+    if (M < 1 || M > 32) return fail(QSIM_ERR_INVALID, "qsim_rowmap_build needs 1 <= M <= 32");
+    if (!x_dev) return fail(QSIM_ERR_INVALID, "x_dev is NULL");
+    int rc = validate_steps(M, steps, L);
+    if (rc) return rc;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    qsim_state *tmp = qsim_state_create(M, QSIM_C64);
+    if (!tmp) return QSIM_ERR_NOMEM;
+    const uint64_t n = 1ull << M;
+    hipError_t e = launch_iota(static_cast<uint64_t *>(tmp->buf[0]), n, st);
+    if (e != hipSuccess) rc = device_fail(tmp, e, "rowmap iota");
+    if (!rc) rc = qsim_apply_steps(tmp, steps, L, st);
+    if (!rc) {
+        e = launch_narrow(static_cast<const uint64_t *>(tmp->buf[tmp->cur]), x_dev, n, st);
+        if (e != hipSuccess) rc = device_fail(tmp, e, "rowmap narrow");
+    }
+    if (!rc && (e = hipStreamSynchronize(st)) != hipSuccess) rc = device_fail(tmp, e, "rowmap synchronize");
+    const std::string msg = g_err;
+    qsim_state_destroy(tmp);
+    if (rc) g_err = msg;
+    return rc;
+}
+
+int qsim_rowmap_apply(qsim_state *s, const uint32_t *x_dev, void *hip_stream) {
+    int rc = check_state(s);
+    if (rc) return rc;
+    if (!x_dev) return fail(QSIM_ERR_INVALID, "x_dev is NULL");
+    if (s->M > 32) return fail(QSIM_ERR_INVALID, "row arrays hold 32-bit rows");
+    DeviceGuard g(s->device);
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    hipError_t e = launch_gather(s->elem, s->buf[s->cur], s->buf[s->cur ^ 1], x_dev, 1ull << s->M, st);
+    if (e != hipSuccess) return device_fail(s, e, "rowmap gather");
+    s->cur ^= 1;
+    s->last_stream = st;
+    return QSIM_OK;
+}
+
 int qsim_apply_steps(qsim_state *s, const qsim_step *steps, uint64_t L, void *hip_stream) {
     int rc = check_state(s);
     if (rc) return rc;

@@ -24,6 +24,7 @@
 //   * the planes are transposed back to 16-bit indices, entries are gathered
 //     from LDS and stored to the output tile with coalesced 16-byte stores.
 // One pass therefore costs one read and one write of the state.
+#include <algorithm>
 #include <cstring>
 
 #include "qsim_internal.h"
@@ -352,21 +353,22 @@ __global__ void __launch_bounds__(256) k_direct(const uint8_t *__restrict__ src,
 template <int ELEM>
 __global__ void __launch_bounds__(256) k_plain_step(uint8_t *__restrict__ buf, uint64_t half_n,
                                                     uint32_t t, uint64_t cm) {
-    const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= half_n) return;
     const uint64_t T = 1ull << t;
-    const uint64_t lo = ((q >> t) << (t + 1)) | (q & (T - 1));
-    if ((lo & cm) != cm) return;
-    if (ELEM == 8) {
-        uint64_t *b = reinterpret_cast<uint64_t *>(buf);
-        const uint64_t a0 = b[lo], a1 = b[lo | T];
-        b[lo] = a1;
-        b[lo | T] = a0;
-    } else {
-        vec16 *b = reinterpret_cast<vec16 *>(buf);
-        const vec16 a0 = b[lo], a1 = b[lo | T];
-        b[lo] = a1;
-        b[lo | T] = a0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < half_n; q += stride) {
+        const uint64_t lo = ((q >> t) << (t + 1)) | (q & (T - 1));
+        if ((lo & cm) != cm) continue;
+        if (ELEM == 8) {
+            uint64_t *b = reinterpret_cast<uint64_t *>(buf);
+            const uint64_t a0 = b[lo], a1 = b[lo | T];
+            b[lo] = a1;
+            b[lo | T] = a0;
+        } else {
+            vec16 *b = reinterpret_cast<vec16 *>(buf);
+            const vec16 a0 = b[lo], a1 = b[lo | T];
+            b[lo] = a1;
+            b[lo | T] = a0;
+        }
     }
 }
 
@@ -585,6 +587,44 @@ __global__ void __launch_bounds__(256) k_product(T *__restrict__ out, ProductArg
     }
 }
 
+// ------------------------------------------------------------ materialised row array
+
+// Index vector: entry i holds the integer i (8-byte entries).  Applying a
+// diagram to it leaves in row i the row of k1 that lands there, the row
+// array x(i) of the whole diagram.
+// One-entry-per-thread kernels use grid-stride loops: a launch may not
+// exceed 2^32 threads, and states reach 2^36 entries.
+__global__ void __launch_bounds__(256) k_iota(uint64_t *__restrict__ out, uint64_t n) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) out[i] = i;
+}
+
+__global__ void __launch_bounds__(256) k_narrow(const uint64_t *__restrict__ in, uint32_t *__restrict__ out,
+                                                uint64_t n) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        out[i] = (uint32_t)in[i];
+}
+
+// k2(i) = k1(x(i)) (Sec. 2(b) end, Summary of Method last bullet).
+template <int ELEM>
+__global__ void __launch_bounds__(256) k_gather(const uint8_t *__restrict__ src, uint8_t *__restrict__ dst,
+                                                const uint32_t *__restrict__ x, uint64_t n) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint64_t j = x[i] & (n - 1);   // n is a power of two: stays in the state
+        if (ELEM == 8)
+            reinterpret_cast<uint64_t *>(dst)[i] = reinterpret_cast<const uint64_t *>(src)[j];
+        else
+            reinterpret_cast<vec16 *>(dst)[i] = reinterpret_cast<const vec16 *>(src)[j];
+    }
+}
+
+uint32_t stride_grid(uint64_t n) {
+    const uint64_t g = (n + 255) / 256;
+    return (uint32_t)(g < (1ull << 20) ? g : (1ull << 20));
+}
+
 template <typename KernelT>
 hipError_t allow_lds(KernelT kernel, size_t bytes) {
     if (bytes <= 65536) return hipSuccess;
@@ -697,7 +737,7 @@ hipError_t launch_plain_step(uint32_t elem, void *buf, uint32_t M, uint32_t targ
                              uint64_t cmask, hipStream_t st) {
     const uint64_t half_n = 1ull << (M - 1);
     const uint32_t bs = 256;
-    const uint64_t grid = (half_n + bs - 1) / bs;
+    const uint64_t grid = std::min<uint64_t>((half_n + bs - 1) / bs, 1ull << 22);
     if (elem == 8)
         hipLaunchKernelGGL(k_plain_step<8>, dim3((uint32_t)grid), dim3(bs), 0, st, (uint8_t *)buf, half_n,
                            target, cmask);
@@ -751,6 +791,25 @@ hipError_t launch_product(uint32_t elem, void *out, uint32_t M, const void *qubi
         a.M = M;
         hipLaunchKernelGGL(k_product<double>, dim3((uint32_t)grid), dim3(bs), 0, st, (double *)out, a, n);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_iota(uint64_t *out, uint64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_iota, dim3(stride_grid(n)), dim3(256), 0, st, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_narrow(const uint64_t *in, uint32_t *out, uint64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_narrow, dim3(stride_grid(n)), dim3(256), 0, st, in, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(uint32_t elem, const void *src, void *dst, const uint32_t *x, uint64_t n, hipStream_t st) {
+    const dim3 grid(stride_grid(n));
+    if (elem == 8)
+        hipLaunchKernelGGL(k_gather<8>, grid, dim3(256), 0, st, (const uint8_t *)src, (uint8_t *)dst, x, n);
+    else
+        hipLaunchKernelGGL(k_gather<16>, grid, dim3(256), 0, st, (const uint8_t *)src, (uint8_t *)dst, x, n);
     return hipGetLastError();
 }
 

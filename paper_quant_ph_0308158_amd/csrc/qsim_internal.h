@@ -150,6 +150,9 @@ hipError_t launch_plain_step(uint32_t elem, void *buf, uint32_t M, uint32_t targ
                              uint64_t cmask, hipStream_t st);
 hipError_t launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t st);
 hipError_t launch_product(uint32_t elem, void *out, uint32_t M, const void *qubits, hipStream_t st);
+hipError_t launch_iota(uint64_t *out, uint64_t n, hipStream_t st);
+hipError_t launch_narrow(const uint64_t *in, uint32_t *out, uint64_t n, hipStream_t st);
+hipError_t launch_gather(uint32_t elem, const void *src, void *dst, const uint32_t *x, uint64_t n, hipStream_t st);
 hipError_t launch_batch(uint32_t elem, uint32_t tb, const BatchPass *passes, const BatchSmall *smalls,
                         const uint64_t *items, uint32_t n_items, uint32_t *counters, uint32_t n_rec_blocks,
                         uint32_t spin_limit, hipStream_t st);

@@ -188,11 +188,11 @@ namespace {
 // (the paper's example input, Sec. 2(b) and Sec. 4), written as raw words.
 __global__ void k_fill_alternating(uint64_t *w, uint64_t n, uint32_t words_per_entry, uint64_t pos,
                                    uint64_t neg) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint64_t v = (i & 1u) ? neg : pos;
-    w[i * words_per_entry] = v;
-    if (words_per_entry == 2) w[i * 2 + 1] = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        w[i * words_per_entry] = (i & 1u) ? neg : pos;
+        if (words_per_entry == 2) w[i * 2 + 1] = 0;
+    }
 }
 
 void alternating_words(uint32_t M, uint32_t elem, uint64_t *pos, uint64_t *neg) {
@@ -251,7 +251,8 @@ void qsim_server::worker_main(uint32_t slot) {
             if (r->k1.empty()) {
                 uint64_t pos, neg;
                 alternating_words(r->M, r->elem, &pos, &neg);
-                hipLaunchKernelGGL(k_fill_alternating, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st,
+                const uint64_t blocks = std::min<uint64_t>((n + 255) / 256, 1ull << 20);
+                hipLaunchKernelGGL(k_fill_alternating, dim3((uint32_t)blocks), dim3(256), 0, st,
                                    reinterpret_cast<uint64_t *>(b0), n, r->elem / 8u, pos, neg);
                 if (hipGetLastError() != hipSuccess) status = QSIM_ERR_DEVICE;
             } else if (hipMemcpyAsync(b0, r->k1.data(), r->k1.size(), hipMemcpyHostToDevice, st) != hipSuccess) {

@@ -37,6 +37,7 @@ EXPORTS = (
     "qsim_version", "qsim_state_profile", "qsim_state_profile_read", "qsim_apply_tile_pass",
     "qsim_batch_last_status", "qsim_server_create", "qsim_server_submit", "qsim_server_drain",
     "qsim_server_request_info", "qsim_server_stats", "qsim_server_destroy", "qsim_state_set_product",
+    "qsim_rowmap_build", "qsim_rowmap_apply",
 )
 
 
@@ -122,6 +123,8 @@ def _load() -> ctypes.CDLL:
         "qsim_server_stats": (i32, [vp, vp, vp, vp, vp]),
         "qsim_server_destroy": (None, [vp]),
         "qsim_state_set_product": (i32, [vp, vp, vp]),
+        "qsim_rowmap_build": (i32, [u32, vp, u64, vp, vp]),
+        "qsim_rowmap_apply": (i32, [vp, vp, vp]),
         "qsim_state_profile_read": (i32, [vp, vp]),
     }
     for name, (res, args) in sig.items():
@@ -297,6 +300,10 @@ class State:
             raise ValueError("qubits must have shape (M, 2)")
         _check(_lib.qsim_state_set_product(self._h, q.ctypes.data, ctypes.c_void_p(_stream_ptr(stream))))
 
+    def rowmap_apply(self, x_ptr: int, stream=None):
+        """current <- k1(x(i)) with a device row array from rowmap_build."""
+        _check(_lib.qsim_rowmap_apply(self._h, ctypes.c_void_p(_ptr(x_ptr)), ctypes.c_void_p(_stream_ptr(stream))))
+
     def apply_tile_pass(self, tile_mask: int, target, cmask, stream=None):
         st = pack_steps(target, cmask)
         _check(_lib.qsim_apply_tile_pass(self._h, int(tile_mask), st.ctypes.data if len(st) else None,
@@ -344,6 +351,14 @@ def apply_batch_packed(states: Sequence[State], packed: Sequence[np.ndarray], st
     ls = (ctypes.c_uint64 * n)(*[len(p) for p in packed])
     _check(_lib.qsim_apply_batch(ctypes.cast(hs, ctypes.c_void_p), ctypes.cast(ps, ctypes.c_void_p),
                                  ctypes.cast(ls, ctypes.c_void_p), n, ctypes.c_void_p(_stream_ptr(stream))))
+
+
+def rowmap_build(M: int, target, cmask, x_dev, stream=None):
+    """Write the row array x of the diagram (k2(i) = k1(x(i))) into x_dev: a
+    device buffer of 2^M uint32 (a torch tensor or a raw pointer)."""
+    st = pack_steps(target, cmask)
+    _check(_lib.qsim_rowmap_build(M, st.ctypes.data if len(st) else None, len(st), ctypes.c_void_p(_ptr(x_dev)),
+                                  ctypes.c_void_p(_stream_ptr(stream))))
 
 
 def batch_status():

@@ -449,3 +449,27 @@ def test_product_state_m32_sampled(q):
     nrm = float(torch.linalg.vector_norm(b0.view(torch.float32).double()))
     assert abs(nrm - 1.0) < 1e-3
     s.close()
+
+
+
+# ------------------------------------------------------------------ materialised row array
+
+def test_rowmap_build_and_apply(q):
+    """qsim_rowmap_build gives the paper's row array x of U_L...U_1 (the
+    oracle's sparse-matrix bookkeeping folded over the reversed list), and
+    qsim_rowmap_apply equals applying the diagram."""
+    import torch
+    rng = np.random.default_rng(41)
+    for M, dt in ((3, np.complex64), (12, np.complex128), (18, np.complex64), (20, np.complex128)):
+        tg, cm = W.random_steps(rng, M, 150, (0, 3))
+        x = torch.empty(1 << M, dtype=torch.int32, device="cuda")
+        say("rowmap", M)
+        q.rowmap_build(M, tg, cm, x)
+        torch.cuda.synchronize()
+        xr = oracle.rowmap(M, tg[::-1], cm[::-1])
+        np.testing.assert_array_equal(x.cpu().numpy().view(np.uint32).astype(np.uint64), xr)
+        k1 = W.gaussian_state(rng, M, dt)
+        with q.State(M, "c64" if dt == np.complex64 else "c128") as s:
+            s.write(k1)
+            s.rowmap_apply(x.data_ptr(), stream=0)
+            assert_same(s.read(), oracle.apply(M, k1, tg, cm), f"rowmap apply M={M}")
