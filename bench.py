@@ -202,6 +202,7 @@ def main():
     ap.add_argument("--no-modes", action="store_true",
                     help="skip the batched and served comparisons of the default run")
     ap.add_argument("--tuning", default=None, help="JSON dict of qsim_tuning fields")
+    ap.add_argument("--autotune", action="store_true", help="pick the tuning with qsim_autotune first")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -236,6 +237,12 @@ def main():
     if args.tuning:
         st.set_tuning(json.loads(args.tuning))
     tuning = json.loads(args.tuning) if args.tuning else None
+    autotune_s = None
+    if args.autotune:
+        t0 = time.perf_counter()
+        tuned = st.autotune(tg, cm)
+        autotune_s = round(time.perf_counter() - t0, 2)
+        tuning = {k: tuned[k] for k in ("tile_bits", "low_bits", "mid_low_bits", "kernel_variant", "rows_per_thread")}
     masks, lens, _ = qsim.plan_describe(M, dt, tg, cm, tuning)
 
     for _ in range(args.warmup):
@@ -321,7 +328,8 @@ def main():
         "dtype": "c64" if dt == "c64" else "c128",
         "data": "synthetic",
         "config": {"workload": wl["name"], "M": M, "L": L, "passes": int(len(masks)),
-                   "tile_bits": int(bin(int(masks[0])).count("1")) if len(masks) else M, **wl["desc"]},
+                   "tile_bits": int(bin(int(masks[0])).count("1")) if len(masks) else M, **wl["desc"],
+                   "tuning": tuning, "autotune_s": autotune_s},
         "roofline": roofline,
         "copy_probe_GBps": round(copy_gbps, 1),
         "cpu_baseline": cpu,

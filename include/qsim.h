@@ -301,6 +301,17 @@ int qsim_state_set_tuning(qsim_state *state, const qsim_tuning *tuning);
 int qsim_apply_tile_pass(qsim_state *state, uint64_t tile_mask,
                          const qsim_step *steps, uint64_t L, void *hip_stream);
 
+/* Choose the launch parameters of the fused path for this state and
+ * diagram by measurement: every candidate (tile size, kernel shape, forced
+ * low bits of the middle passes) applies the diagram once on the device,
+ * timed with events, then its reverse, which undoes it (each step matrix is
+ * its own inverse, Sec. 2(a)); the state's contents are unchanged on
+ * return.  The fastest candidate becomes the state's tuning and is copied
+ * to *out (may be NULL).  States small enough for one workgroup have
+ * nothing to choose.  Synchronous. */
+int qsim_autotune(qsim_state *state, const qsim_step *steps, uint64_t L,
+                  void *hip_stream, qsim_tuning *out);
+
 /* ---------------------------------------------------------------- planning */
 
 /* Describe the pass plan the fused path would use for a diagram (host

@@ -1148,6 +1148,84 @@ int qsim_batch_last_status(void) {
     return batch_status();
 }
 
+int qsim_autotune(qsim_state *s, const qsim_step *steps, uint64_t L, void *hip_stream, qsim_tuning *out) {
+    int rc = check_state(s);
+    if (rc) return rc;
+    if ((rc = validate_steps(s->M, steps, L))) return rc;
+    const Tuning keep = s->tune;
+    auto export_tuning = [&](const Tuning &t) {
+        if (!out) return;
+        std::memset(out, 0, sizeof(*out));
+        out->tile_bits = (uint32_t)t.tile_bits;
+        out->low_bits = (uint32_t)t.low_bits;
+        out->max_seg_steps = (uint32_t)t.max_seg_steps;
+        out->reorder = t.reorder ? 1u : 2u;
+        out->small_bits = (uint32_t)t.small_bits;
+        out->kernel_variant = t.variant + 1;
+        out->wg_per_cu = t.wg_per_cu;
+        out->outer_order = t.outer_order + 1;
+        out->remap = t.remap ? 1u : 2u;
+        out->mid_low_bits = (uint32_t)t.mid_low_bits;
+        out->min_overlap = (uint32_t)t.min_overlap;
+        out->rows_per_thread = 1u << t.rows_eb;
+    };
+    if (L == 0 || (int)s->M <= s->tune.small_bits) {   // one launch: nothing to choose
+        export_tuning(s->tune);
+        return QSIM_OK;
+    }
+    // Candidates around the measured defaults: tile size, kernel shape and
+    // the low bits of the middle passes.
+    struct Cand { int tile_bits; uint32_t variant; int mid_low; };
+    std::vector<Cand> cands;
+    if (s->elem == 8)
+        cands = {{13, 0, 2}, {13, 0, 3}, {13, 1, 2}, {14, 1, 2}, {14, 2, 2}, {12, 0, 2}};
+    else
+        cands = {{13, 1, 2}, {13, 0, 2}, {12, 0, 2}, {12, 1, 2}, {13, 1, 3}};
+    std::vector<qsim_step> rev(steps, steps + L);
+    std::reverse(rev.begin(), rev.end());
+    DeviceGuard g(s->device);
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return device_fail(s, hipErrorOutOfMemory, "autotune events");
+    // Each candidate applies the diagram (timed) and then its reverse, which
+    // undoes it (every step is its own inverse), so the state is unchanged.
+    float best_ms = 0.f;
+    Tuning best = keep;
+    bool first = true;
+    for (const Cand &c : cands) {
+        Tuning t = keep;
+        t.tile_bits = std::min(c.tile_bits, s->elem == 8 ? kMaxTileBits : kMaxTileBits - 1);
+        t.variant = c.variant;
+        t.mid_low_bits = std::min(c.mid_low, t.low_bits);
+        if ((uint32_t)t.tile_bits < t.rows_eb || (uint32_t)t.tile_bits - t.rows_eb > 10) continue;
+        s->tune = t;
+        if ((rc = qsim_apply_steps(s, rev.data(), L, st)) || (rc = qsim_apply_steps(s, steps, L, st))) break;
+        if (hipEventRecord(e0, st) != hipSuccess) { rc = device_fail(s, hipErrorUnknown, "autotune"); break; }
+        if ((rc = qsim_apply_steps(s, steps, L, st))) break;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            rc = device_fail(s, hipErrorUnknown, "autotune");
+            break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        // the state now holds U k1; applying the reversed list undoes it
+        if ((rc = qsim_apply_steps(s, rev.data(), L, st))) break;
+        if (first || ms < best_ms) {
+            best_ms = ms;
+            best = t;
+            first = false;
+        }
+    }
+    (void)hipStreamSynchronize(st);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    s->tune = rc ? keep : best;
+    if (rc) return rc;
+    export_tuning(best);
+    return QSIM_OK;
+}
+
 int qsim_state_set_tuning(qsim_state *s, const qsim_tuning *tuning) {
     int rc = check_state(s);
     if (rc) return rc;

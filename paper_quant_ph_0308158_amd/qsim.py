@@ -37,7 +37,7 @@ EXPORTS = (
     "qsim_version", "qsim_state_profile", "qsim_state_profile_read", "qsim_apply_tile_pass",
     "qsim_batch_last_status", "qsim_server_create", "qsim_server_submit", "qsim_server_drain",
     "qsim_server_request_info", "qsim_server_stats", "qsim_server_destroy", "qsim_state_set_product",
-    "qsim_rowmap_build", "qsim_rowmap_apply",
+    "qsim_rowmap_build", "qsim_rowmap_apply", "qsim_autotune",
 )
 
 
@@ -125,6 +125,7 @@ def _load() -> ctypes.CDLL:
         "qsim_state_set_product": (i32, [vp, vp, vp]),
         "qsim_rowmap_build": (i32, [u32, vp, u64, vp, vp]),
         "qsim_rowmap_apply": (i32, [vp, vp, vp]),
+        "qsim_autotune": (i32, [vp, vp, u64, vp, vp]),
         "qsim_state_profile_read": (i32, [vp, vp]),
     }
     for name, (res, args) in sig.items():
@@ -321,6 +322,15 @@ class State:
         p = Profile()
         _check(_lib.qsim_state_profile_read(self._h, ctypes.byref(p)))
         return p.as_dict()
+
+    def autotune(self, target, cmask, stream=None) -> dict:
+        """Measure candidate tunings for this diagram on this state (contents
+        unchanged) and keep the fastest; returns it."""
+        st = pack_steps(target, cmask)
+        t = Tuning()
+        _check(_lib.qsim_autotune(self._h, st.ctypes.data if len(st) else None, len(st),
+                                  ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(t)))
+        return {k: getattr(t, k) for k, _ in Tuning._fields_}
 
     def set_tuning(self, tuning: Optional[dict]):
         t = _tuning_struct(tuning)

@@ -473,3 +473,21 @@ def test_rowmap_build_and_apply(q):
             s.write(k1)
             s.rowmap_apply(x.data_ptr(), stream=0)
             assert_same(s.read(), oracle.apply(M, k1, tg, cm), f"rowmap apply M={M}")
+
+
+
+def test_autotune_keeps_state_and_result(q):
+    """qsim_autotune leaves the state's contents unchanged and the tuning it
+    picks gives the oracle's result."""
+    rng = np.random.default_rng(51)
+    for M, dt in ((17, np.complex64), (16, np.complex128)):
+        tg, cm = W.random_steps(rng, M, 200, (0, 3))
+        k1 = W.gaussian_state(rng, M, dt)
+        with q.State(M, "c64" if dt == np.complex64 else "c128") as s:
+            s.write(k1)
+            say("autotune", M)
+            t = s.autotune(tg, cm, stream=0)
+            assert t["tile_bits"] in (12, 13, 14)
+            assert_same(s.read(), k1, "state after autotune")
+            s.apply(tg, cm, stream=0)
+            assert_same(s.read(), oracle.apply(M, k1, tg, cm), "apply with the tuned parameters")
