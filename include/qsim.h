@@ -284,6 +284,10 @@ typedef struct {
     uint32_t rows_per_thread; /* tile rows per thread of the fused pass:
                               8, 16 or 32 (threads per tile = 2^tile_bits /
                               rows_per_thread, at most 1024)               */
+    uint32_t plan_search;  /* 1 = off, 2 = on: after the greedy scan builds a
+                              pass, swap single tile bits for outside bits
+                              while that admits more pending steps (fewer
+                              passes, more host time); 0 = on for M >= 30 */
 } qsim_tuning;
 
 /* Set (tuning != NULL) or reset to defaults (NULL) the parameters used by

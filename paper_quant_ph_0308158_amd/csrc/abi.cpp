@@ -75,6 +75,7 @@ struct Tuning {
     int mid_low_bits;     // forced low bits of the passes in between
     int min_overlap;      // tile bits shared by consecutive passes
     uint32_t rows_eb;     // log2 of the tile rows each thread owns
+    int plan_search;      // -1 = by size, 0 = off, 1 = on
 };
 
 Tuning default_tuning(uint32_t elem) {
@@ -91,6 +92,7 @@ Tuning default_tuning(uint32_t elem) {
     t.mid_low_bits = 2;
     t.min_overlap = 1;                   // no overlap requirement (measured best)
     t.rows_eb = 5;
+    t.plan_search = -1;
     return t;
 }
 
@@ -112,6 +114,10 @@ int tuning_from(const qsim_tuning *in, uint32_t elem, Tuning *out) {
             if (in->rows_per_thread != 8 && in->rows_per_thread != 16 && in->rows_per_thread != 32)
                 return fail(QSIM_ERR_INVALID, "rows_per_thread must be 8, 16 or 32");
             t.rows_eb = (uint32_t)__builtin_ctz(in->rows_per_thread);
+        }
+        if (in->plan_search) {
+            if (in->plan_search > 2) return fail(QSIM_ERR_INVALID, "plan_search out of range");
+            t.plan_search = in->plan_search == 2 ? 1 : 0;
         }
     }
     if (t.mid_low_bits < 1 || t.mid_low_bits > t.low_bits) t.mid_low_bits = t.low_bits;
@@ -138,6 +144,7 @@ PlanConfig plan_config(const Tuning &t) {
     c.min_overlap = t.remap ? t.min_overlap : 0;
     c.max_seg_steps = t.max_seg_steps;
     c.reorder = t.reorder;
+    c.search = t.plan_search;
     return c;
 }
 
@@ -384,7 +391,23 @@ int prepare_passes(uint32_t M, uint32_t elem, const std::vector<Pass> &passes,
         // by physical position in the written layout makes the lanes of one
         // wave store cover whole contiguous lines; bit 0 stays first (its
         // physical position is 0 in every layout, which the 8-byte pairs need).
+        // Kernel index bits: LO pair bit, then 6 lane bits, then the wave
+        // bits, then the per-thread row bits.
         std::sort(in_log, in_log + ni, [&](uint8_t x, uint8_t y) { return ld[x] < ld[y]; });
+        // The thread bits above the 64 lanes of a wave (the wave number)
+        // take the highest written positions and the per-thread rows the
+        // ones below, so that each wave's stores cover one compact block
+        // (measured faster than rows spread over the whole tile).
+        {
+            const uint32_t lanes = LO + 6, tb = K - eb;
+            if (tb > 6) {
+                const uint32_t nw = tb - 6;
+                uint8_t by_pos[16];
+                std::memcpy(by_pos, in_log, sizeof(by_pos));
+                for (uint32_t q = 0; q < nw; ++q) in_log[lanes + q] = by_pos[K - nw + q];
+                for (uint32_t q = 0; q < K - lanes - nw; ++q) in_log[lanes + nw + q] = by_pos[lanes + q];
+            }
+        }
         for (uint32_t j = 0; j < ni; ++j) jpos[in_log[j]] = (uint8_t)j;
         // Tiles may be enumerated in any order: outer_order picks which
         // outside bits (by physical position in the written layout) vary
@@ -1168,6 +1191,7 @@ int qsim_autotune(qsim_state *s, const qsim_step *steps, uint64_t L, void *hip_s
         out->mid_low_bits = (uint32_t)t.mid_low_bits;
         out->min_overlap = (uint32_t)t.min_overlap;
         out->rows_per_thread = 1u << t.rows_eb;
+        out->plan_search = t.plan_search < 0 ? 0u : (t.plan_search ? 2u : 1u);
     };
     if (L == 0 || (int)s->M <= s->tune.small_bits) {   // one launch: nothing to choose
         export_tuning(s->tune);

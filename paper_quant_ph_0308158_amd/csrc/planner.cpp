@@ -89,6 +89,52 @@ std::vector<Pass> plan_passes(uint32_t M, const uint32_t *target, const uint64_t
         return popc(allowed & ~I & ~U) >= K - popc(I);
     };
 
+    // Mask search: the greedy scan commits to tile bits in the order the
+    // pending steps ask for them.  Afterwards one tile bit (not one the
+    // pass must hold) is swapped for one outside bit while a scan with the
+    // fixed mask admits more pending steps; that scan keeps the same
+    // commutation blocking, so its steps form a valid pass.
+    const bool search = cfg.search > 0 || (cfg.search < 0 && M >= 30);
+    auto scan_fixed = [&](uint64_t I, std::vector<uint32_t> *take) {
+        uint64_t BT = 0, BC = 0;
+        bool any_blocked = false;
+        int n = 0;
+        for (uint32_t s : pending) {
+            const bool ready = n < cap &&
+                               (cfg.reorder ? !((cmask[s] & BT) || ((BC >> target[s]) & 1ull)) : !any_blocked);
+            if (ready && (((I >> target[s]) & 1ull) || !(cmask[s] & I))) {
+                ++n;
+                if (take) take->push_back(s);
+            } else {
+                BT |= 1ull << target[s];
+                BC |= cmask[s];
+                any_blocked = true;
+            }
+        }
+        return n;
+    };
+    auto climb = [&](uint64_t I, uint64_t keep) {
+        int best = scan_fixed(I, nullptr);
+        for (int round = 0; round < 4; ++round) {
+            uint64_t bestI = I;
+            for (uint32_t b = 0; b < M; ++b) {
+                if (!((I >> b) & 1ull) || ((keep >> b) & 1ull)) continue;
+                for (uint32_t c = 0; c < M; ++c) {
+                    if (((I >> c) & 1ull) || !((allowed >> c) & 1ull)) continue;
+                    const uint64_t J = (I & ~(1ull << b)) | (1ull << c);
+                    const int n = scan_fixed(J, nullptr);
+                    if (n > best) {
+                        best = n;
+                        bestI = J;
+                    }
+                }
+            }
+            if (bestI == I) break;
+            I = bestI;
+        }
+        return I;
+    };
+
     // One pass over the pending steps, starting from tile mask `start`.
     // A step may join the pass only if it commutes with every earlier
     // pending step left behind in this scan: with BT the targets and BC the
@@ -152,7 +198,17 @@ std::vector<Pass> plan_passes(uint32_t M, const uint32_t *target, const uint64_t
         }
         Pass p;
         p.tile_mask = I;
-        p.steps = taken;
+        if (search) {
+            // A fixed-mask scan admits every step the greedy scan took (the
+            // final mask only added bits no outer step is controlled by), so
+            // the climb can only add steps.
+            p.tile_mask = climb(I, start);
+            for (uint32_t s : pending) state[s] = 0;
+            scan_fixed(p.tile_mask, &p.steps);
+            for (uint32_t s : p.steps) state[s] = 2;
+        } else {
+            p.steps = taken;
+        }
         std::vector<uint32_t> next;
         next.reserve(pending.size());
         for (uint32_t s : pending) {

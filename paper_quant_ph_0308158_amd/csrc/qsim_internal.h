@@ -121,6 +121,7 @@ struct PlanConfig {
     int min_overlap = 0;    // tile bits a middle pass shares with the previous one
     int max_seg_steps = 1024;
     bool reorder = true;
+    int search = -1;        // tile-mask hill climb per pass: 1 on, 0 off, -1 on for M >= 30
 };
 
 // Split steps into passes (see planner.cpp).

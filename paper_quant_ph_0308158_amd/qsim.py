@@ -78,7 +78,8 @@ class Tuning(ctypes.Structure):
                 ("small_bits", ctypes.c_uint32), ("kernel_variant", ctypes.c_uint32),
                 ("wg_per_cu", ctypes.c_uint32), ("outer_order", ctypes.c_uint32),
                 ("remap", ctypes.c_uint32), ("mid_low_bits", ctypes.c_uint32),
-                ("min_overlap", ctypes.c_uint32), ("rows_per_thread", ctypes.c_uint32)]
+                ("min_overlap", ctypes.c_uint32), ("rows_per_thread", ctypes.c_uint32),
+                ("plan_search", ctypes.c_uint32)]
 
 
 def _load() -> ctypes.CDLL:

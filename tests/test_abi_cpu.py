@@ -107,6 +107,10 @@ def _check_plan(M, dtype, tg, cm, tuning):
     (4, 13, "c64", {"tile_bits": 5, "low_bits": 1}),
     (5, 13, "c64", {"tile_bits": 5, "low_bits": 1, "min_overlap": 5}),
     (6, 16, "c128", {"tile_bits": 8, "min_overlap": 4, "mid_low_bits": 1}),
+    (7, 14, "c64", {"tile_bits": 6, "low_bits": 2, "plan_search": 2}),
+    (8, 16, "c128", {"tile_bits": 8, "max_seg_steps": 9, "plan_search": 2}),
+    (9, 16, "c64", {"tile_bits": 8, "reorder": False, "plan_search": 2}),
+    (10, 13, "c64", {"tile_bits": 5, "low_bits": 1, "min_overlap": 5, "plan_search": 2}),
 ])
 def test_planner_reorder_is_exact(seed, M, dtype, tuning):
     """The planner's execution order has the same product as the original
@@ -127,6 +131,10 @@ def test_planner_on_benchmark_workloads():
     tg, cm = W.m32_config()
     masks, lens, order = _check_plan(32, "c64", tg, cm, {})
     assert len(masks) < 80
+    # The mask search (on by default at this size) takes at least the greedy
+    # scan's steps in each pass; on this workload that saves passes.
+    off, _, _ = _check_plan(32, "c64", tg, cm, {"plan_search": 1})
+    assert len(masks) <= len(off)
     tg, cm = W.m26_config()
     _check_plan(26, "c128", tg, cm, {})
 
