@@ -9,7 +9,8 @@ this module only marshals numpy arrays into it.  Steps are given as two
 arrays: ``target`` (address bit of the NOT, 0-based, bit b is the paper's
 a(b+1)) and ``cmask`` (bit mask of the controlling bits, all of which must be
 1 for the step to fire).  ``steps[0]`` acts first (Sec. 2(a): k2 = U_L k1 with
-U_L the product of the step matrices).
+U_L the product of the step matrices).  An optional ``kind`` array adds
+controlled phase -1 steps (kind 1) beside the controlled NOTs (kind 0).
 """
 from __future__ import annotations
 
@@ -64,6 +65,14 @@ def _load():
     lib.oracle_product_entry.restype = ctypes.c_int
     lib.oracle_product_entry.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint64,
                                          ctypes.c_void_p]
+    u8p = ctypes.POINTER(ctypes.c_uint8)
+    lib.oracle_apply_signed.restype = ctypes.c_int
+    lib.oracle_apply_signed.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p, u32p, u64p, u8p,
+                                        ctypes.c_uint64, ctypes.c_int]
+    lib.oracle_sample_rows_signed.restype = ctypes.c_int
+    lib.oracle_sample_rows_signed.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p, u32p, u64p,
+                                              u8p, ctypes.c_uint64, u64p, ctypes.c_uint64, ctypes.c_void_p,
+                                              ctypes.c_int]
     lib.oracle_max_threads.restype = ctypes.c_int
     lib.oracle_max_threads.argtypes = []
     _lib = lib
@@ -96,16 +105,33 @@ def _check(rc: int, what: str):
         raise ValueError(f"{what}: oracle rejected the arguments (code {rc})")
 
 
+def _kinds(kind, n):
+    k = np.ascontiguousarray(np.asarray(kind, dtype=np.uint8))
+    if k.shape != (n,):
+        raise ValueError("kind must be a 1-D array with one entry per step")
+    return k, k.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+
+
 def apply(M: int, state: np.ndarray, target, cmask, threads: int = 1,
-          method: str = "plain") -> np.ndarray:
+          method: str = "plain", kind=None) -> np.ndarray:
     """Return U_L ... U_1 state (a new array), by the plain pair-swap loop
-    (``method="plain"``) or by intelligent looping (``method="enum"``)."""
+    (``method="plain"``) or by intelligent looping (``method="enum"``).
+    ``kind`` (optional, one entry per step): 0 = controlled NOT, 1 =
+    controlled phase -1 on the rows whose target and control bits are all
+    1 (plain loop only)."""
     eb = _elem_bytes(state)
     if state.shape != (1 << M,):
         raise ValueError("state must hold 2^M entries")
     out = np.array(state, copy=True, order="C")
     t, c = _steps_arrays(target, cmask)
     tp, cp = _ptrs(t, c)
+    if kind is not None:
+        if method != "plain":
+            raise ValueError("signed steps use the plain loop")
+        k, kp = _kinds(kind, len(t))
+        _check(_load().oracle_apply_signed(M, eb, out.ctypes.data, tp, cp, kp, len(t), int(threads)),
+               "apply_signed")
+        return out
     fn = _load().oracle_apply if method == "plain" else _load().oracle_apply_enum
     _check(fn(M, eb, out.ctypes.data, tp, cp, len(t), int(threads)), "apply")
     return out
@@ -142,8 +168,9 @@ def source_index(M: int, target, cmask, i: int) -> int:
     return int(_load().oracle_source_index(M, tp, cp, len(t), int(i)))
 
 
-def sample_rows(M: int, k1: np.ndarray, target, cmask, idx, threads: int = 1) -> np.ndarray:
-    """k2 at the rows ``idx`` without forming the whole of k2."""
+def sample_rows(M: int, k1: np.ndarray, target, cmask, idx, threads: int = 1, kind=None) -> np.ndarray:
+    """k2 at the rows ``idx`` without forming the whole of k2 (``kind`` as
+    in apply)."""
     eb = _elem_bytes(k1)
     if k1.shape != (1 << M,) or not k1.flags.c_contiguous:
         raise ValueError("k1 must be a contiguous array of 2^M entries")
@@ -151,6 +178,12 @@ def sample_rows(M: int, k1: np.ndarray, target, cmask, idx, threads: int = 1) ->
     tp, cp = _ptrs(t, c)
     ix = np.ascontiguousarray(np.asarray(idx, dtype=np.uint64))
     out = np.empty(len(ix), dtype=k1.dtype)
+    if kind is not None:
+        k, kp = _kinds(kind, len(t))
+        _check(_load().oracle_sample_rows_signed(M, eb, k1.ctypes.data, tp, cp, kp, len(t),
+                                                 ix.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                                 len(ix), out.ctypes.data, int(threads)), "sample_rows_signed")
+        return out
     _check(_load().oracle_sample_rows(M, eb, k1.ctypes.data, tp, cp, len(t),
                                       ix.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
                                       len(ix), out.ctypes.data, int(threads)), "sample_rows")

@@ -15,6 +15,10 @@
  *   U_s has a 1 at (i, i with bit goto flipped) for every row i whose
  *   control bits are all 1, and a 1 on the diagonal elsewhere.
  *
+ * Signed steps (oracle_apply_signed, oracle_sample_rows_signed) add a
+ * second step kind, a controlled phase of -1, which reaches the signed
+ * permutation matrices such as the paper's first example (Sec. 2(a)).
+ *
  * Conventions (readings of the paper, each listed in the design notes):
  *   - Address bit b (0-based) is the paper's a(b+1); a(1) is the LSB
  *     (Sec. 2(b)).  Rows are counted top to bottom from 0 to 2^M - 1.
@@ -322,6 +326,117 @@ int oracle_product_entry(uint32_t M, uint32_t elem_bytes, const void *qubits, ui
         return 0;
     }
     return -1;
+}
+
+/*
+ * Signed steps (Sec. 2(a)).  The wiring-diagram class has only 0/1 step
+ * matrices; the paper's first example of a unitary matrix, however, is a
+ * permutation with one entry -1, which that class cannot reach.  A second
+ * kind of step closes the gap: kind[s] = 1 is a controlled phase of -1,
+ * the diagonal matrix with -1 in every row i whose bits t and C are all 1
+ * and +1 elsewhere (symmetric, its own inverse, like every NOT step).
+ * kind[s] = 0 is the controlled NOT above.  Products of both kinds are the
+ * signed permutations reachable from controlled NOTs.
+ *
+ * Negating an entry negates its real and imaginary parts; IEEE 754
+ * negation is the sign-bit flip, exact for every value (zeros, infinities
+ * and NaN payloads included), so entries stay opaque words: bit 63 of each
+ * 8-byte word for complex128, bits 31 and 63 of the one word for complex64.
+ */
+static int check_kinds(const uint8_t *kind, uint64_t L)
+{
+    if (L > 0 && kind == NULL) return -1;
+    for (uint64_t s = 0; s < L; ++s)
+        if (kind[s] > 1u) return -2;
+    return 0;
+}
+
+static inline void negate_entry(uint64_t *w, uint64_t i, uint32_t nw)
+{
+    if (nw == 1u) {
+        w[i] ^= (1ull << 31) | (1ull << 63);
+    } else {
+        w[2 * i] ^= 1ull << 63;
+        w[2 * i + 1] ^= 1ull << 63;
+    }
+}
+
+/* Plain loop over every row for every step, as oracle_apply, with phase
+ * steps negating the rows whose bits t and C are all 1. */
+int oracle_apply_signed(uint32_t M, uint32_t elem_bytes, void *buf,
+                        const uint32_t *target, const uint64_t *cmask,
+                        const uint8_t *kind, uint64_t L, int nthreads)
+{
+    int rc = check_args(M, elem_bytes, target, cmask, L);
+    if (rc) return rc;
+    if ((rc = check_kinds(kind, L))) return rc;
+    if (L > 0 && buf == NULL) return -1;
+    uint64_t *w = (uint64_t *)buf;
+    const uint32_t nw = elem_bytes / 8u;
+    const uint64_t n = 1ull << M;
+    for (uint64_t s = 0; s < L; ++s) {
+        const uint64_t T = 1ull << target[s];
+        const uint64_t C = cmask[s];
+        const int phase = kind[s] == 1u;
+        int64_t i;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) num_threads(nthreads > 0 ? nthreads : 1) if (nthreads > 1)
+#endif
+        for (i = 0; i < (int64_t)n; ++i) {
+            uint64_t u = (uint64_t)i;
+            if (phase) {
+                if ((u & (C | T)) == (C | T)) negate_entry(w, u, nw);
+            } else if ((u & T) == 0 && (u & C) == C) {
+                swap_words(w, u, u | T, nw);
+            }
+        }
+    }
+    (void)nthreads;
+    return 0;
+}
+
+/*
+ * k2 at sampled rows for signed steps.  Row i of U_L ... U_1 has its one
+ * nonzero entry in column x(i) with sign sigma(i): following row i through
+ * the product from the left, a NOT step U_s moves it to row y_s(i), and a
+ * phase step multiplies it by U_s's diagonal entry in the row it is in at
+ * that point.  out[r] = sigma(idx[r]) k1(x(idx[r])).
+ */
+int oracle_sample_rows_signed(uint32_t M, uint32_t elem_bytes, const void *k1,
+                              const uint32_t *target, const uint64_t *cmask,
+                              const uint8_t *kind, uint64_t L, const uint64_t *idx,
+                              uint64_t nsample, void *out, int nthreads)
+{
+    int rc = check_args(M, elem_bytes, target, cmask, L);
+    if (rc) return rc;
+    if ((rc = check_kinds(kind, L))) return rc;
+    if (nsample > 0 && (k1 == NULL || idx == NULL || out == NULL)) return -1;
+    const uint64_t n = 1ull << M;
+    for (uint64_t r = 0; r < nsample; ++r)
+        if (idx[r] >= n) return -3;
+    const uint32_t nw = elem_bytes / 8u;
+    const uint64_t *src = (const uint64_t *)k1;
+    uint64_t *dst = (uint64_t *)out;
+    int64_t r;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) num_threads(nthreads > 0 ? nthreads : 1) if (nthreads > 1)
+#endif
+    for (r = 0; r < (int64_t)nsample; ++r) {
+        uint64_t x = idx[r];
+        int neg = 0;
+        for (uint64_t s = L; s-- > 0;) {
+            const uint64_t T = 1ull << target[s];
+            if (kind[s] == 1u) {
+                if ((x & (cmask[s] | T)) == (cmask[s] | T)) neg ^= 1;
+            } else {
+                x = step_column(x, T, cmask[s]);
+            }
+        }
+        for (uint32_t q = 0; q < nw; ++q) dst[(uint64_t)r * nw + q] = src[x * nw + q];
+        if (neg) negate_entry(dst, (uint64_t)r, nw);
+    }
+    (void)nthreads;
+    return 0;
 }
 
 /* Number of threads an OpenMP region would use (1 without OpenMP). */

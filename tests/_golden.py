@@ -31,7 +31,10 @@ def load_examples(path: str = GOLDEN):
     out = {}
     for name, b in blocks.items():
         ex = {"name": name, "cite": b["cite"], "M": int(b["M"])}
-        ex["target"], ex["cmask"] = parse_steps(b["steps"])
+        ex["target"], ex["cmask"] = parse_steps(b.get("steps", ""))
+        if "matrix" in b:
+            ex["matrix"] = np.array([[int(x) for x in row.split()] for row in b["matrix"].split("/")],
+                                    dtype=np.int64)
         if "expect_sign" in b:
             ex["expect_sign"] = np.array([1.0 if s == "+" else -1.0 for s in b["expect_sign"].split()])
         if "expect_src" in b:

@@ -6,6 +6,9 @@
 * invariants: involution, conservation of the multiset of entries and of the
   norm, split associativity, commutation of non-interfering steps;
 * the closed form of the paper's own computational example (Sec. 4);
+* signed steps (controlled phase -1): the paper's printed signed example
+  matrix (Sec. 2(a)) reproduced by a four-step diagram, dense brute force
+  with signed step matrices, involution and sign-bit exactness;
 * mutation checks: plausible mistakes, planted in pure-Python variants of the
   oracle's loop, each fail at least one of the pins above.
 """
@@ -382,3 +385,178 @@ def test_product_entry_matches_product_state():
         full = oracle.product_state(11, qq)
         for i in (0, 1, 5, 777, 2047):
             assert oracle.product_entry(11, qq, i).tobytes() == full[i].tobytes()
+
+
+# ------------------------------------------------------------------ signed steps (Sec. 2(a) example matrix)
+
+NOT, PHASE = 0, 1
+
+
+def dense_phase(M, t, cmask):
+    """Controlled phase -1: I - 2 P, P projecting onto the rows whose bits t
+    and C are all 1 (a Kronecker product, bit M-1 leftmost)."""
+    I2 = np.eye(2, dtype=np.int64)
+    P1 = np.array([[0, 0], [0, 1]], dtype=np.int64)
+    m = cmask | (1 << t)
+    P = kron_all([P1 if (m >> b) & 1 else I2 for b in range(M - 1, -1, -1)])
+    return np.eye(1 << M, dtype=np.int64) - 2 * P
+
+
+def dense_signed(M, tg, cm, kd):
+    U = np.eye(1 << M, dtype=np.int64)
+    for s in range(len(tg)):
+        f = dense_phase if kd[s] == PHASE else dense_step
+        U = f(M, int(tg[s]), int(cm[s])) @ U
+    return U
+
+
+def int_state(M, dt):
+    """Small integers in both parts: exact under negation and under a 0/+-1
+    matrix product in float64."""
+    i = np.arange(1 << M)
+    return (i + 1 + 1j * (1000 + 3 * i)).astype(dt)
+
+
+def random_signed(rng, M, L, p_phase=0.35):
+    tg, cm = W.random_steps(rng, M, L, (0, 3))
+    kd = (rng.random(L) < p_phase).astype(np.uint8)
+    return tg, cm, kd
+
+
+# Construction (not printed in the paper): on two bits (b1 b0), the NOTs
+# [b0 controls b1, b1 controls b0, NOT b0] move the entry at (b1, b0) to
+# (b0 ^ b1, b1 ^ 1), i.e. k2(i) = k1(x(i)) with x = (3, 0, 2, 1); a phase
+# step on bit 0 controlled by bit 1 then negates row 3.
+SIGNED_EXAMPLE = (np.array([1, 0, 0, 0], dtype=np.uint32),
+                  np.array([0b01, 0b10, 0, 0b10], dtype=np.uint64),
+                  np.array([NOT, NOT, NOT, PHASE], dtype=np.uint8))
+
+
+def test_paper_signed_example_matrix():
+    ex = EXAMPLES["sec2a_signed_example"]
+    M, G = ex["M"], ex["matrix"]
+    tg, cm, kd = SIGNED_EXAMPLE
+    U = dense_signed(M, tg, cm, kd)
+    np.testing.assert_array_equal(U, G, err_msg=ex["cite"])
+    assert (G.T @ G == np.eye(4, dtype=np.int64)).all()        # unitary (Sec. 2(a))
+    for dt in (np.complex64, np.complex128):
+        k1 = int_state(M, dt)
+        k2 = oracle.apply(M, k1, tg, cm, kind=kd)
+        np.testing.assert_array_equal(k2, (G @ k1.astype(np.complex128)).astype(dt))
+        np.testing.assert_array_equal(oracle.sample_rows(M, k1, tg, cm, np.arange(4), kind=kd), k2)
+    # Without the phase step the same diagram is the 0/1 matrix |G|.
+    k2 = oracle.apply(M, int_state(M, np.complex128), tg[:3], cm[:3])
+    np.testing.assert_array_equal(k2, np.abs(G) @ int_state(M, np.complex128))
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_signed_dense_bruteforce(seed):
+    rng = np.random.default_rng(9000 + seed)
+    M = int(rng.integers(1, 8))
+    L = int(rng.integers(0, 26))
+    tg, cm, kd = random_signed(rng, M, L)
+    U = dense_signed(M, tg, cm, kd)
+    n = 1 << M
+    assert (U.T @ U == np.eye(n, dtype=np.int64)).all()
+    assert (np.abs(U).sum(axis=1) == 1).all()                   # a signed permutation
+    for dt in (np.complex64, np.complex128):
+        k1 = int_state(M, dt)
+        expect = (U @ k1.astype(np.complex128)).astype(dt)
+        got = oracle.apply(M, k1, tg, cm, kind=kd)
+        np.testing.assert_array_equal(got, expect)
+        idx = rng.integers(0, n, size=13)
+        np.testing.assert_array_equal(oracle.sample_rows(M, k1, tg, cm, idx, kind=kd), expect[idx])
+    # all-NOT kinds reduce to the unsigned oracle
+    k1 = W.gaussian_state(rng, M, np.complex64)
+    z = np.zeros(L, dtype=np.uint8)
+    assert oracle.apply(M, k1, tg, cm, kind=z).tobytes() == oracle.apply(M, k1, tg, cm).tobytes()
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_signed_involution_and_sign_bits(seed):
+    """Every signed step is its own inverse, negation flips only sign bits
+    (NaN payloads, zeros and infinities included), and the magnitudes are
+    only moved."""
+    rng = np.random.default_rng(9100 + seed)
+    M = int(rng.integers(2, 12))
+    tg, cm, kd = random_signed(rng, M, 80)
+    for dt in (np.complex64, np.complex128):
+        k1 = W.special_values_state(rng, M, dt)
+        k2 = oracle.apply(M, k1, tg, cm, kind=kd)
+        back = oracle.apply(M, k2, tg[::-1], cm[::-1], kind=kd[::-1])
+        assert back.tobytes() == k1.tobytes()
+        sign = np.uint64(0x8000000080000000) if dt == np.complex64 else np.uint64(1 << 63)
+        a = np.sort(k1.view(np.uint64) & ~sign)
+        b = np.sort(k2.view(np.uint64) & ~sign)
+        assert a.tobytes() == b.tobytes()
+    # one phase step on bit t, no controls: rows with bit t set flip both signs
+    t = int(rng.integers(0, M))
+    k1 = W.special_values_state(rng, M, np.complex64)
+    k2 = oracle.apply(M, k1, [t], [0], kind=[PHASE])
+    rows = (np.arange(1 << M) >> t) & 1
+    flip = np.where(rows == 1, np.uint64(0x8000000080000000), np.uint64(0))
+    np.testing.assert_array_equal(k2.view(np.uint64), k1.view(np.uint64) ^ flip)
+
+
+def test_signed_commutation():
+    """A phase step commutes with a NOT step exactly when the NOT's target is
+    not among the phase step's bits; phase steps always commute."""
+    rng = np.random.default_rng(9200)
+    M = 6
+    k1 = int_state(M, np.complex128)
+    seen = [0, 0]
+    for _ in range(300):
+        tg, cm, kd = random_signed(rng, M, 2, 0.5)
+        a = oracle.apply(M, k1, tg, cm, kind=kd)
+        b = oracle.apply(M, k1, tg[::-1], cm[::-1], kind=kd[::-1])
+        def tm(s): return 0 if kd[s] else 1 << int(tg[s])
+        def rm(s): return int(cm[s]) | ((1 << int(tg[s])) if kd[s] else 0)
+        commute = not (tm(0) & rm(1)) and not (tm(1) & rm(0))
+        seen[commute] += 1
+        assert (a.tobytes() == b.tobytes()) == commute
+    assert min(seen) > 30
+
+
+def _py_apply_signed(M, v, tg, cm, kd, mutant=None):
+    v = list(v)
+    for s in range(len(tg)):
+        t, C, T = int(tg[s]), int(cm[s]), 1 << int(tg[s])
+        if kd[s] == PHASE and mutant != "phase_as_not":
+            if mutant == "phase_ignored":
+                continue
+            m = C if mutant == "phase_controls_only" else C | T
+            for i in range(1 << M):
+                hit = (i & m) != 0 if mutant == "phase_or" else (i & m) == m
+                if hit:
+                    v[i] = -v[i]
+            continue
+        for i in range(1 << M):
+            if not i & T and (i & C) == C:
+                v[i], v[i | T] = v[i | T], v[i]
+    return v
+
+
+def _failing_signed_pins(apply_fn):
+    failed = set()
+    ex = EXAMPLES["sec2a_signed_example"]
+    tg, cm, kd = SIGNED_EXAMPLE
+    if list(apply_fn(2, [1, 2, 3, 4], tg, cm, kd)) != list(ex["matrix"] @ np.array([1, 2, 3, 4])):
+        failed.add("paper")
+    rng = np.random.default_rng(78)
+    for _ in range(8):
+        M = int(rng.integers(2, 6))
+        tg, cm, kd = random_signed(rng, M, 8, 0.5)
+        x = np.arange(1, (1 << M) + 1)
+        if list(apply_fn(M, list(x), tg, cm, kd)) != list(dense_signed(M, tg, cm, kd) @ x):
+            failed.add("dense")
+    return failed
+
+
+def test_signed_pins_accept_correct_loop():
+    assert _failing_signed_pins(lambda M, v, tg, cm, kd: _py_apply_signed(M, v, tg, cm, kd)) == set()
+
+
+@pytest.mark.parametrize("mutant", ["phase_as_not", "phase_ignored", "phase_controls_only", "phase_or"])
+def test_signed_pins_catch_planted_mistake(mutant):
+    failed = _failing_signed_pins(lambda M, v, tg, cm, kd: _py_apply_signed(M, v, tg, cm, kd, mutant))
+    assert failed, f"planted mistake {mutant} passed every pin"
