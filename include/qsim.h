@@ -21,6 +21,13 @@
  *    of them must be 1 for the NOT to fire (Sec. 2(g), generalised to any
  *    number of controls); control_mask == 0 is the unconditional NOT
  *    (Sec. 2(e)).
+ *  - Beyond the wiring-diagram class, a step may instead be a controlled
+ *    phase of -1 (kind QSIM_STEP_PHASE): the diagonal matrix that negates
+ *    every row whose target bit and control bits are all 1.  Diagrams
+ *    mixing both kinds give the signed permutation matrices, such as the
+ *    paper's first example of a unitary matrix (Sec. 2(a)).  Negation flips
+ *    the sign bit of both parts of an entry (IEEE 754 negate), so results
+ *    stay exact to the bit.
  *  - Entries are opaque words of 8 bytes (QSIM_C64: two float32) or 16
  *    bytes (QSIM_C128: two float64), stored contiguously in row order.  The
  *    library never reads them as floating point: NaN payloads, -0.0 and
@@ -61,14 +68,21 @@ typedef enum {
     QSIM_ERR_RANGE = -4    /* offset + count beyond 2^M                     */
 } qsim_status;
 
-/* One wiring-diagram step (16 bytes): a NOT on address bit `target`
- * (the paper's 'goto' minus one) that fires when every bit set in
- * `control_mask` is 1 in the row address (the paper's 'from', any number of
- * them).  Valid iff target < M, control_mask < 2^M and bit `target` of
- * control_mask is 0 (Sec. 2(b)-(g)).  reserved0 must be 0. */
+/* Kinds of step. */
+typedef enum {
+    QSIM_STEP_NOT = 0,   /* controlled NOT: the wiring-diagram step          */
+    QSIM_STEP_PHASE = 1  /* controlled phase -1 (signed steps, Sec. 2(a))    */
+} qsim_step_kind;
+
+/* One step (16 bytes).  QSIM_STEP_NOT: a NOT on address bit `target` (the
+ * paper's 'goto' minus one) that fires when every bit set in `control_mask`
+ * is 1 in the row address (the paper's 'from', any number of them),
+ * Sec. 2(b)-(g).  QSIM_STEP_PHASE: every row whose bit `target` and
+ * control bits are all 1 is negated.  Valid iff kind is one of the two,
+ * target < M, control_mask < 2^M and bit `target` of control_mask is 0. */
 typedef struct {
     uint32_t target;
-    uint32_t reserved0;
+    uint32_t kind;
     uint64_t control_mask;
 } qsim_step;
 
@@ -126,12 +140,14 @@ int qsim_state_set_product(qsim_state *state, const void *qubits, void *hip_stre
  * before the call returns.  Work is enqueued on `hip_stream` (a
  * hipStream_t; NULL = the default stream) and the call returns without
  * waiting for it.  L == 0 is a no-op.  QSIM_ERR_INVALID on any invalid step
- * (target >= M, control >= M, target among its controls, reserved0 != 0) or
+ * (target >= M, control >= M, target among its controls, unknown kind) or
  * steps == NULL with L > 0. */
 int qsim_apply_steps(qsim_state *state, const qsim_step *steps, uint64_t L,
                      void *hip_stream);
 
-/* The row array x of a whole diagram (Sec. 2(h), Summary of Method): x(i)
+/* The row array x of a whole diagram of QSIM_STEP_NOT steps (a row array
+ * holds no signs: phase steps are rejected with QSIM_ERR_INVALID)
+ * (Sec. 2(h), Summary of Method): x(i)
  * is the row of k1 that lands in row i of k2 = U_L ... U_1 k1, so that
  * k2(i) = k1(x(i)) for every input (the information about the unitary
  * matrix that the Conclusions propose to keep).  Built on the device by
@@ -149,7 +165,8 @@ int qsim_rowmap_apply(qsim_state *state, const uint32_t *x_dev, void *hip_stream
 
 /* Same result as qsim_apply_steps, computed the plain way: one in-place
  * kernel launch per step that interchanges every pair of rows the step
- * toggles (the state is recalculated after each step, Sec. 2(h)).  A
+ * toggles, or negates the rows a phase step selects (the state is
+ * recalculated after each step, Sec. 2(h)).  A
  * comparator for the fused path; not faster. */
 int qsim_apply_steps_plain(qsim_state *state, const qsim_step *steps,
                            uint64_t L, void *hip_stream);
@@ -296,8 +313,9 @@ int qsim_state_set_tuning(qsim_state *state, const qsim_tuning *tuning);
 
 /* Apply the steps, in the order given, as a single fused pass through
  * tiles whose address bits are `tile_mask` (for callers that plan passes
- * themselves, and for measuring one pass).  Every step must target a bit of
- * tile_mask or have no control in it (Sec. 2(i): steps processed together);
+ * themselves, and for measuring one pass).  Every NOT step must target a
+ * bit of tile_mask or have no control in it (Sec. 2(i): steps processed
+ * together; phase steps always qualify);
  * tile_mask must have 5..14 bits set (5..13 for QSIM_C128), all below bit
  * 32 and below M, and must contain bit 0 for QSIM_C64.  L may be 0: the pass
  * then moves every entry back to its own row.  QSIM_ERR_INVALID otherwise;

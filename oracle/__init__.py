@@ -73,6 +73,9 @@ def _load():
     lib.oracle_sample_rows_signed.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p, u32p, u64p,
                                               u8p, ctypes.c_uint64, u64p, ctypes.c_uint64, ctypes.c_void_p,
                                               ctypes.c_int]
+    lib.oracle_source_index_signed.restype = ctypes.c_uint64
+    lib.oracle_source_index_signed.argtypes = [ctypes.c_uint32, u32p, u64p, u8p, ctypes.c_uint64,
+                                               ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]
     lib.oracle_max_threads.restype = ctypes.c_int
     lib.oracle_max_threads.argtypes = []
     _lib = lib
@@ -166,6 +169,16 @@ def source_index(M: int, target, cmask, i: int) -> int:
     t, c = _steps_arrays(target, cmask)
     tp, cp = _ptrs(t, c)
     return int(_load().oracle_source_index(M, tp, cp, len(t), int(i)))
+
+
+def source_index_signed(M: int, target, cmask, kind, i: int):
+    """(x(i), negated) of U_L ... U_1 with signed steps: k2(i) = +-k1(x(i))."""
+    t, c = _steps_arrays(target, cmask)
+    tp, cp = _ptrs(t, c)
+    k, kp = _kinds(kind, len(t))
+    neg = ctypes.c_int(0)
+    x = _load().oracle_source_index_signed(M, tp, cp, kp, len(t), int(i), ctypes.byref(neg))
+    return int(x), bool(neg.value)
 
 
 def sample_rows(M: int, k1: np.ndarray, target, cmask, idx, threads: int = 1, kind=None) -> np.ndarray:

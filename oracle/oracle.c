@@ -396,6 +396,28 @@ int oracle_apply_signed(uint32_t M, uint32_t elem_bytes, void *buf,
 }
 
 /*
+ * Column x(i) and sign of row i of the signed product U_L ... U_1 (see
+ * below): *neg receives 1 when the entry is -1.  Returns x(i).
+ */
+uint64_t oracle_source_index_signed(uint32_t M, const uint32_t *target, const uint64_t *cmask,
+                                    const uint8_t *kind, uint64_t L, uint64_t i, int *neg)
+{
+    (void)M;
+    uint64_t x = i;
+    int n = 0;
+    for (uint64_t s = L; s-- > 0;) {
+        const uint64_t T = 1ull << target[s];
+        if (kind[s] == 1u) {
+            if ((x & (cmask[s] | T)) == (cmask[s] | T)) n ^= 1;
+        } else {
+            x = step_column(x, T, cmask[s]);
+        }
+    }
+    if (neg) *neg = n;
+    return x;
+}
+
+/*
  * k2 at sampled rows for signed steps.  Row i of U_L ... U_1 has its one
  * nonzero entry in column x(i) with sign sigma(i): following row i through
  * the product from the left, a NOT step U_s moves it to row y_s(i), and a

@@ -49,8 +49,8 @@ int validate_steps(uint32_t M, const qsim_step *steps, uint64_t L) {
     const uint64_t all = (M >= 64) ? ~0ull : ((1ull << M) - 1ull);
     for (uint64_t s = 0; s < L; ++s) {
         const qsim_step &st = steps[s];
-        if (st.reserved0 != 0)
-            return fail(QSIM_ERR_INVALID, "step " + std::to_string(s) + ": reserved0 must be 0");
+        if (st.kind != QSIM_STEP_NOT && st.kind != QSIM_STEP_PHASE)
+            return fail(QSIM_ERR_INVALID, "step " + std::to_string(s) + ": unknown kind " + std::to_string(st.kind));
         if (st.target >= M)
             return fail(QSIM_ERR_INVALID, "step " + std::to_string(s) + ": target " + std::to_string(st.target) +
                                               " >= M = " + std::to_string(M));
@@ -61,6 +61,32 @@ int validate_steps(uint32_t M, const qsim_step *steps, uint64_t L) {
     }
     return QSIM_OK;
 }
+
+// The steps as separate arrays (planner input).
+struct StepLists {
+    std::vector<uint32_t> tg;
+    std::vector<uint64_t> cm;
+    std::vector<uint8_t> kd;
+    bool any_phase = false;
+};
+
+StepLists split_steps(const qsim_step *steps, uint64_t L) {
+    StepLists o;
+    o.tg.resize(L);
+    o.cm.resize(L);
+    o.kd.resize(L);
+    for (uint64_t i = 0; i < L; ++i) {
+        o.tg[i] = steps[i].target;
+        o.cm[i] = steps[i].control_mask;
+        o.kd[i] = steps[i].kind == QSIM_STEP_PHASE ? kStepPhase : kStepNot;
+        o.any_phase |= o.kd[i] == kStepPhase;
+    }
+    return o;
+}
+
+// Bits a step reads at its place in the walk: the controls, plus the target
+// for a phase step (whose rows are those with target and controls all 1).
+inline uint64_t phase_mask(const qsim_step &st) { return st.control_mask | (1ull << st.target); }
 
 struct Tuning {
     int tile_bits;
@@ -296,12 +322,19 @@ size_t push_inner(std::vector<uint8_t> &blob, std::vector<uint32_t> inner) {
 // Small-state path: the whole state is one tile; every step is inner.
 void prepare_small(uint32_t M, uint32_t elem, const qsim_step *steps, uint64_t L, Prepared &pr) {
     std::vector<uint32_t> inner(L);
+    bool sign = false;
     for (uint64_t s = 0; s < L; ++s) {
         const qsim_step &st = steps[L - 1 - s];
-        inner[s] = pack_inner(st.target, (uint32_t)st.control_mask);
+        if (st.kind == QSIM_STEP_PHASE) {
+            inner[s] = pack_inner(kSignPlane, (uint32_t)phase_mask(st));
+            sign = true;
+        } else {
+            inner[s] = pack_inner(st.target, (uint32_t)st.control_mask);
+        }
     }
     Launch l;
     l.kind = Launch::SMALL;
+    l.ta.sign = sign ? 1u : 0u;
     l.inner_off = push_inner(pr.blob, inner);
     l.ta.n_inner = (uint32_t)L;
     l.ta.tb = M - 5;
@@ -319,9 +352,10 @@ void prepare_direct(const qsim_step *steps, uint64_t L, Prepared &pr) {
     std::vector<TmStep> rev(L);
     for (uint64_t s = 0; s < L; ++s) {
         const qsim_step &st = steps[L - 1 - s];
-        rev[s].cm = st.control_mask;
+        const bool ph = st.kind == QSIM_STEP_PHASE;
+        rev[s].cm = ph ? phase_mask(st) : st.control_mask;
         rev[s].tbit = st.target;
-        rev[s].inner = 0;
+        rev[s].inner = ph ? 1u : 0u;
     }
     Launch l;
     l.kind = Launch::DIRECT;
@@ -352,8 +386,8 @@ void make_layout(uint32_t M, uint32_t fixed, uint64_t A, uint64_t B, uint8_t *la
 }
 
 int prepare_passes(uint32_t M, uint32_t elem, const std::vector<Pass> &passes,
-                   const uint32_t *target, const uint64_t *cmask, uint32_t outer_order, bool remap,
-                   uint32_t eb, Prepared &pr) {
+                   const uint32_t *target, const uint64_t *cmask, const uint8_t *kind, uint32_t outer_order,
+                   bool remap, uint32_t eb, Prepared &pr) {
     const uint32_t LO = elem == 8 ? 1 : 0;
     const size_t P = passes.size();
     // Layouts at the pass boundaries; the state enters and leaves in the
@@ -428,24 +462,30 @@ int prepare_passes(uint32_t M, uint32_t elem, const std::vector<Pass> &passes,
 
         std::vector<TmStep> tm;
         std::vector<uint32_t> inner;
+        bool sign = false;
         tm.reserve(p.steps.size());
         for (size_t q = p.steps.size(); q-- > 0;) {
             const uint32_t s = p.steps[q];
             const uint64_t T = 1ull << target[s];
+            const bool ph = kind && kind[s] == kStepPhase;
+            // A phase step is an inner step on the sign plane: its tile
+            // bits select rows inside the tile, its outside bits the tiles.
+            const uint64_t rmask = ph ? (cmask[s] | T) : cmask[s];
             TmStep d;
-            d.cm = cmask[s] & ~I;
+            d.cm = rmask & ~I;
             d.tbit = target[s];
-            d.inner = (I & T) ? 1u : 0u;
+            d.inner = (ph || (I & T)) ? 1u : 0u;
             tm.push_back(d);
+            sign |= ph;
             if (d.inner) {
                 uint32_t icm = 0;
-                uint64_t ci = cmask[s] & I;
+                uint64_t ci = rmask & I;
                 while (ci) {
                     const uint32_t b = (uint32_t)__builtin_ctzll(ci);
                     ci &= ci - 1;
                     icm |= 1u << jpos[b];
                 }
-                inner.push_back(pack_inner(jpos[target[s]], icm));
+                inner.push_back(pack_inner(ph ? kSignPlane : jpos[target[s]], icm));
             }
         }
         const uint32_t n_inner = (uint32_t)inner.size();
@@ -474,6 +514,7 @@ int prepare_passes(uint32_t M, uint32_t elem, const std::vector<Pass> &passes,
         lt.ta.tb = K - eb;
         lt.ta.eb = eb;
         lt.ta.n_out = no;
+        lt.ta.sign = sign ? 1u : 0u;
         const uint32_t vpt = (1u << eb) >> LO;
         for (uint32_t r = 0; r < 32; ++r) {
             const uint64_t j = (uint64_t)r << (LO + lt.ta.tb);
@@ -497,20 +538,15 @@ int prepare(qsim_state *s, const qsim_step *steps, uint64_t L, Prepared &pr) {
         prepare_small(M, s->elem, steps, L, pr);
         return QSIM_OK;
     }
-    std::vector<uint32_t> tg(L);
-    std::vector<uint64_t> cm(L);
-    for (uint64_t i = 0; i < L; ++i) {
-        tg[i] = steps[i].target;
-        cm[i] = steps[i].control_mask;
-    }
+    const StepLists sl = split_steps(steps, L);
     std::vector<Pass> passes;
     try {
-        passes = plan_passes(M, tg.data(), cm.data(), L, plan_config(s->tune));
+        passes = plan_passes(M, sl.tg.data(), sl.cm.data(), sl.kd.data(), L, plan_config(s->tune));
     } catch (const std::exception &e) {
         return fail(QSIM_ERR_INVALID, std::string("planner: ") + e.what());
     }
-    return prepare_passes(M, s->elem, passes, tg.data(), cm.data(), s->tune.outer_order, s->tune.remap,
-                          s->tune.rows_eb, pr);
+    return prepare_passes(M, s->elem, passes, sl.tg.data(), sl.cm.data(), sl.kd.data(), s->tune.outer_order,
+                          s->tune.remap, s->tune.rows_eb, pr);
 }
 
 // Timing helpers: a launch of `kind` (0 tile, 1 map, 2 other) is bracketed
@@ -696,20 +732,15 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
             bp.small = true;
             prepare_small(s->M, elem, steps[c], L, bp.pr);
         } else {
-            std::vector<uint32_t> tg(L);
-            std::vector<uint64_t> cm(L);
-            for (uint64_t i = 0; i < L; ++i) {
-                tg[i] = steps[c][i].target;
-                cm[i] = steps[c][i].control_mask;
-            }
+            const StepLists sl = split_steps(steps[c], L);
             PlanConfig pc = plan_config(s->tune);
             pc.tile_bits = (int)Kb;
             pc.low_bits = std::min(pc.low_bits, (int)Kb);
             pc.mid_low_bits = std::min(pc.mid_low_bits, pc.low_bits);
             try {
-                std::vector<Pass> passes = plan_passes(s->M, tg.data(), cm.data(), L, pc);
-                bp.rc = prepare_passes(s->M, elem, passes, tg.data(), cm.data(), s->tune.outer_order, s->tune.remap,
-                                       5u, bp.pr);
+                std::vector<Pass> passes = plan_passes(s->M, sl.tg.data(), sl.cm.data(), sl.kd.data(), L, pc);
+                bp.rc = prepare_passes(s->M, elem, passes, sl.tg.data(), sl.cm.data(), sl.kd.data(),
+                                       s->tune.outer_order, s->tune.remap, 5u, bp.pr);
                 if (bp.rc) bp.err = g_err;
             } catch (const std::exception &e) {
                 bp.rc = QSIM_ERR_INVALID;
@@ -742,6 +773,7 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
     std::vector<size_t> circuit_blob_off(n, 0);
     size_t blob_size = 0, rec_words_total = 0;
     uint32_t max_level = 0;
+    bool any_sign = false;   // some tile or small item has phase steps
     for (uint32_t c = 0; c < n; ++c) {
         circuit_blob_off[c] = blob_size;
         blob_size += (plans[c].pr.blob.size() + 255) & ~size_t(255);
@@ -754,6 +786,7 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
             const Launch &l = bp.pr.launches[0];
             BatchSmall sm{};
             sm.ta = l.ta;
+            any_sign |= sm.ta.sign != 0;
             sm.src = s->buf[s->cur];
             sm.dst = s->buf[s->cur ^ 1];
             sm.L = l.n;
@@ -769,6 +802,7 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
             const Launch &lm = bp.pr.launches[i], &lt = bp.pr.launches[i + 1];
             BatchPass p{};
             p.ta = lt.ta;
+            any_sign |= p.ta.sign != 0;
             p.tm = lm.tm;
             p.src = s->buf[s->cur ^ (level & 1u)];
             p.dst = s->buf[s->cur ^ ((level + 1) & 1u)];
@@ -860,7 +894,7 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
     w.stage.pending = true;
     w.ctr_dev = reinterpret_cast<uint32_t *>(dev);
     if (!items.empty()) {
-        e = launch_batch(elem, tb, reinterpret_cast<const BatchPass *>(dev + pass_off),
+        e = launch_batch(elem, tb, any_sign, reinterpret_cast<const BatchPass *>(dev + pass_off),
                          reinterpret_cast<const BatchSmall *>(dev + small_off),
                          reinterpret_cast<const uint64_t *>(dev + items_off), (uint32_t)items.size(), w.ctr_dev,
                          n_rec_blocks, 1u << 24, st);
@@ -1023,6 +1057,9 @@ int qsim_rowmap_build(uint32_t M, const qsim_step *steps, uint64_t L, uint32_t *
     if (!x_dev) return fail(QSIM_ERR_INVALID, "x_dev is NULL");
     int rc = validate_steps(M, steps, L);
     if (rc) return rc;
+    for (uint64_t i = 0; i < L; ++i)
+        if (steps[i].kind == QSIM_STEP_PHASE)
+            return fail(QSIM_ERR_INVALID, "step " + std::to_string(i) + ": a row array holds no signs (phase step)");
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     qsim_state *tmp = qsim_state_create(M, QSIM_C64);
     if (!tmp) return QSIM_ERR_NOMEM;
@@ -1076,20 +1113,17 @@ int qsim_apply_tile_pass(qsim_state *s, uint64_t tile_mask, const qsim_step *ste
     const int kmax = s->elem == 8 ? kMaxTileBits : kMaxTileBits - 1;
     if ((tile_mask & ~all) || (tile_mask >> 32) || K < 5 || K > kmax || (s->elem == 8 && !(tile_mask & 1ull)))
         return fail(QSIM_ERR_INVALID, "tile_mask: 5..14 bits (13 for complex128) below min(M, 32), bit 0 for complex64");
-    std::vector<uint32_t> tg(L);
-    std::vector<uint64_t> cm(L);
+    const StepLists sl = split_steps(steps, L);
     Pass p;
     p.tile_mask = tile_mask;
     for (uint64_t i = 0; i < L; ++i) {
-        tg[i] = steps[i].target;
-        cm[i] = steps[i].control_mask;
-        if (!((tile_mask >> tg[i]) & 1ull) && (cm[i] & tile_mask))
+        if (sl.kd[i] == kStepNot && !((tile_mask >> sl.tg[i]) & 1ull) && (sl.cm[i] & tile_mask))
             return fail(QSIM_ERR_INVALID, "step " + std::to_string(i) + " has a control in the tile but its target outside");
         p.steps.push_back((uint32_t)i);
     }
     Prepared pr;
-    if ((rc = prepare_passes(s->M, s->elem, std::vector<Pass>{p}, tg.data(), cm.data(), s->tune.outer_order, false,
-                             s->tune.rows_eb, pr)))
+    if ((rc = prepare_passes(s->M, s->elem, std::vector<Pass>{p}, sl.tg.data(), sl.cm.data(), sl.kd.data(),
+                             s->tune.outer_order, false, s->tune.rows_eb, pr)))
         return rc;
     DeviceGuard g(s->device);
     if (!g.ok) return device_fail(s, hipErrorInvalidDevice, "set device");
@@ -1107,7 +1141,9 @@ int qsim_apply_steps_plain(qsim_state *s, const qsim_step *steps, uint64_t L, vo
         hipEvent_t ev_a = nullptr;
         hipError_t e = prof_begin(s, st, &ev_a);
         if (e == hipSuccess)
-            e = launch_plain_step(s->elem, s->buf[s->cur], s->M, steps[i].target, steps[i].control_mask, st);
+            e = steps[i].kind == QSIM_STEP_PHASE
+                    ? launch_plain_phase(s->elem, s->buf[s->cur], s->M, phase_mask(steps[i]), st)
+                    : launch_plain_step(s->elem, s->buf[s->cur], s->M, steps[i].target, steps[i].control_mask, st);
         if (e == hipSuccess) e = prof_end(s, st, 2, ev_a, 0);
         if (e != hipSuccess) return device_fail(s, e, "plain step launch");
     }
@@ -1269,15 +1305,10 @@ int qsim_plan_describe(uint32_t M, qsim_dtype dtype, const qsim_step *steps, uin
     if (rc) return rc;
     Tuning t;
     if ((rc = tuning_from(tuning, elem, &t))) return rc;
-    std::vector<uint32_t> tg(L);
-    std::vector<uint64_t> cm(L);
-    for (uint64_t i = 0; i < L; ++i) {
-        tg[i] = steps[i].target;
-        cm[i] = steps[i].control_mask;
-    }
+    const StepLists sl = split_steps(steps, L);
     std::vector<Pass> passes;
     try {
-        passes = plan_passes(M, tg.data(), cm.data(), L, plan_config(t));
+        passes = plan_passes(M, sl.tg.data(), sl.cm.data(), sl.kd.data(), L, plan_config(t));
     } catch (const std::exception &e) {
         return fail(QSIM_ERR_INVALID, std::string("planner: ") + e.what());
     }

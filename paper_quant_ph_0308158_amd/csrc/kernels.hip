@@ -197,13 +197,44 @@ __device__ __forceinline__ void tile_stage(const TileVecs<ELEM, EB> &v, uint32_t
     for (uint32_t r = 0; r < Shape<ELEM, EB>::VPT; ++r) lds[threadIdx.x | (r << tb)] = v[r];
 }
 
+// Sign of a transposed source index: bit kSignPlane (set by the phase
+// steps of the pass) moved to bit 31, the sign bit of a float32 word and of
+// the high word of a float64.
+__device__ __forceinline__ uint32_t sign_word(uint32_t v) { return (v >> kSignPlane) << 31; }
+
 // Gather the calling thread's output entries from the staged source tile
-// and store them with 16-byte stores.
-template <int ELEM, int EB>
+// and store them with 16-byte stores.  With phase steps in the pass, bit
+// kSignPlane of each source index says whether the entry is negated: both
+// its parts get their sign bit flipped.  SIGN is a template parameter so
+// that passes without phase steps run code with no trace of it.
+template <int ELEM, int EB, bool SIGN>
 __device__ __forceinline__ void tile_emit(const uint32_t (&w)[kPlanes], vec16 *__restrict__ dst, uint64_t dst_base,
                                           const TileArgs &a, const vec16 *lds) {
     constexpr uint32_t VPT = Shape<ELEM, EB>::VPT;
     constexpr uint32_t EPV = Shape<ELEM, EB>::EPV;
+    constexpr uint32_t kIndex = (1u << kSignPlane) - 1u;
+    if constexpr (SIGN) {
+        if (ELEM == 8) {
+            const uint2 *l2 = reinterpret_cast<const uint2 *>(lds);
+#pragma unroll
+            for (uint32_t r = 0; r < VPT; ++r) {
+                const uint32_t v0 = src_of(w, 2u * r), v1 = src_of(w, 2u * r + 1u);
+                const uint2 e0 = l2[v0 & kIndex];
+                const uint2 e1 = l2[v1 & kIndex];
+                const uint32_t m0 = sign_word(v0), m1 = sign_word(v1);
+                st_nt(dst + (dst_base + a.off_r_dst[r]) / EPV, make_uint4(e0.x ^ m0, e0.y ^ m0, e1.x ^ m1, e1.y ^ m1));
+            }
+        } else {
+#pragma unroll
+            for (uint32_t r = 0; r < VPT; ++r) {
+                const uint32_t v0 = src_of(w, r);
+                const vec16 e0 = lds[v0 & kIndex];
+                const uint32_t m0 = sign_word(v0);
+                st_nt(dst + (dst_base + a.off_r_dst[r]) / EPV, make_uint4(e0.x, e0.y ^ m0, e0.z, e0.w ^ m0));
+            }
+        }
+        return;
+    }
     if (ELEM == 8) {
         const uint2 *l2 = reinterpret_cast<const uint2 *>(lds);
 #pragma unroll
@@ -226,7 +257,7 @@ __device__ __forceinline__ void tile_emit(const uint32_t (&w)[kPlanes], vec16 *_
 // ~0 the loads of the next source tile are issued into `v` as soon as the
 // current one is in LDS, so they overlap the gather, the stores and the
 // next tile's walk.
-template <int ELEM, int EB, bool FLAGS>
+template <int ELEM, int EB, bool FLAGS, bool SIGN>
 __device__ __forceinline__ void tile_step(TileVecs<ELEM, EB> &v, const vec16 *__restrict__ src,
                                           vec16 *__restrict__ dst, uint64_t dst_base, uint64_t next_base,
                                           const TileArgs &a, const uint32_t *__restrict__ flags, vec16 *lds) {
@@ -235,7 +266,7 @@ __device__ __forceinline__ void tile_step(TileVecs<ELEM, EB> &v, const vec16 *__
     tile_stage<ELEM, EB>(v, a.tb, lds);
     __syncthreads();
     if (next_base != ~0ull) load_tile<ELEM, EB>(v, src, next_base, a);
-    tile_emit<ELEM, EB>(w, dst, dst_base, a, lds);
+    tile_emit<ELEM, EB, SIGN>(w, dst, dst_base, a, lds);
 }
 
 __device__ __forceinline__ uint64_t rec_base(const uint32_t *rec) {
@@ -247,7 +278,7 @@ __device__ __forceinline__ uint64_t rec_base(const uint32_t *rec) {
 // gridDim.x, ...; the loads of each tile are issued DEPTH tiles ahead, into
 // one of DEPTH register buffers, so they overlap the gathers, stores and
 // walks of the tiles in between.
-template <int ELEM, int DEPTH, int EB>
+template <int ELEM, int DEPTH, int EB, bool SIGN>
 __global__ void __launch_bounds__(EB == 5 ? 512 : 1024) k_tile(const vec16 *__restrict__ src,
                                                               vec16 *__restrict__ dst, TileArgs a,
                                                               uint64_t n_tiles) {
@@ -271,22 +302,22 @@ __global__ void __launch_bounds__(EB == 5 ? 512 : 1024) k_tile(const vec16 *__re
             const uint64_t next = tile + (uint64_t)NB * stride;
             const uint64_t next_base =
                 (DEPTH > 0 && next < n_tiles) ? rec_base(a.rec + next * a.rec_words) + off_src : ~0ull;
-            tile_step<ELEM, EB, true>(v[d], src, dst, outer_address(a, tile) + off_dst, next_base, a,
-                                      a.rec + tile * a.rec_words + 2, lds);
+            tile_step<ELEM, EB, true, SIGN>(v[d], src, dst, outer_address(a, tile) + off_dst, next_base, a,
+                                            a.rec + tile * a.rec_words + 2, lds);
             __syncthreads();
         }
     }
 }
 
 // Whole state in one workgroup's LDS: one tile, every step is inner.
-template <int ELEM>
+template <int ELEM, bool SIGN>
 __global__ void __launch_bounds__(512) k_small(const vec16 *__restrict__ src, vec16 *__restrict__ dst,
                                                TileArgs a) {
     extern __shared__ vec16 lds[];
     vec16 v[Shape<ELEM, 5>::VPT];
     load_tile<ELEM, 5>(v, src, thread_offset<ELEM>(a.pos_src, a.tb, threadIdx.x), a);
-    tile_step<ELEM, 5, false>(v, src, dst, thread_offset<ELEM>(a.pos_dst, a.tb, threadIdx.x), ~0ull, a, nullptr,
-                              lds);
+    tile_step<ELEM, 5, false, SIGN>(v, src, dst, thread_offset<ELEM>(a.pos_dst, a.tb, threadIdx.x), ~0ull, a,
+                                    nullptr, lds);
 }
 
 // Per-tile record of a pass: source tile address and the outside-control
@@ -329,6 +360,31 @@ __global__ void __launch_bounds__(256) k_tilemap(TileMapArgs a) {
     if (tile < a.n_tiles) tilemap_one(a, tile);
 }
 
+// One row of the direct gather: walk row i backwards through every step (a
+// NOT step moves it, a phase step flips its sign when all its bits are 1
+// at that point) and copy the entry it lands on, negated if the sign is
+// odd.
+template <int ELEM>
+__device__ __forceinline__ void direct_row(const void *src, void *dst, uint64_t i,
+                                           const TmStep *__restrict__ steps_rev, uint32_t L) {
+    uint64_t x = i;
+    uint32_t neg = 0;
+    for (uint32_t s = 0; s < L; ++s) {
+        const uint64_t cm = steps_rev[s].cm;
+        const bool hit = (x & cm) == cm;
+        if (steps_rev[s].inner) neg ^= hit ? 1u : 0u;
+        else if (hit) x ^= 1ull << steps_rev[s].tbit;
+    }
+    const uint32_t m = neg << 31;
+    if (ELEM == 8) {
+        const uint2 e = reinterpret_cast<const uint2 *>(src)[x];
+        reinterpret_cast<uint2 *>(dst)[i] = make_uint2(e.x ^ m, e.y ^ m);
+    } else {
+        const vec16 e = reinterpret_cast<const vec16 *>(src)[x];
+        reinterpret_cast<vec16 *>(dst)[i] = make_uint4(e.x, e.y ^ m, e.z, e.w ^ m);
+    }
+}
+
 // Direct gather: each thread walks its own row backwards through every step
 // and copies the entry it lands on.  Used for states of fewer than 64 rows.
 template <int ELEM>
@@ -336,16 +392,7 @@ __global__ void __launch_bounds__(256) k_direct(const uint8_t *__restrict__ src,
                                                 uint64_t n, const TmStep *__restrict__ steps_rev, uint32_t L) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    uint64_t x = i;
-    for (uint32_t s = 0; s < L; ++s) {
-        const uint64_t cm = steps_rev[s].cm;
-        if ((x & cm) == cm) x ^= 1ull << steps_rev[s].tbit;
-    }
-    if (ELEM == 8) {
-        reinterpret_cast<uint64_t *>(dst)[i] = reinterpret_cast<const uint64_t *>(src)[x];
-    } else {
-        reinterpret_cast<vec16 *>(dst)[i] = reinterpret_cast<const vec16 *>(src)[x];
-    }
+    direct_row<ELEM>(src, dst, i, steps_rev, L);
 }
 
 // Plain per-step update: one thread per row pair (i, i | 2^t) with bit t of
@@ -368,6 +415,32 @@ __global__ void __launch_bounds__(256) k_plain_step(uint8_t *__restrict__ buf, u
             const vec16 a0 = b[lo], a1 = b[lo | T];
             b[lo] = a1;
             b[lo | T] = a0;
+        }
+    }
+}
+
+// Plain phase step: every row whose bits in `mask` are all 1 is negated in
+// place (sign bits of both parts flipped).  One thread per row of the
+// 2^(M - |mask|) selected rows: the row counter is spread into the free bits.
+template <int ELEM>
+__global__ void __launch_bounds__(256) k_plain_phase(uint8_t *__restrict__ buf, uint64_t n_rows, uint64_t mask,
+                                                     uint32_t M) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n_rows; q += stride) {
+        uint64_t i = mask, c = q;
+        for (uint32_t b = 0; b < M && c; ++b) {
+            if ((mask >> b) & 1ull) continue;
+            i |= (c & 1ull) << b;
+            c >>= 1;
+        }
+        if (ELEM == 8) {
+            uint2 *b = reinterpret_cast<uint2 *>(buf);
+            const uint2 e = b[i];
+            b[i] = make_uint2(e.x ^ 0x80000000u, e.y ^ 0x80000000u);
+        } else {
+            vec16 *b = reinterpret_cast<vec16 *>(buf);
+            const vec16 e = b[i];
+            b[i] = make_uint4(e.x, e.y ^ 0x80000000u, e.z, e.w ^ 0x80000000u);
         }
     }
 }
@@ -423,22 +496,12 @@ __device__ __forceinline__ void wait_at_least(uint32_t *p, uint32_t target, uint
 // Whole small circuit (2^M entries in LDS, every step inner) with the
 // first 2^tb threads of the workgroup; states of fewer than 32 rows use a
 // direct walk per row.
-template <int ELEM>
+template <int ELEM, bool SIGN>
 __device__ __forceinline__ void small_item(const BatchSmall &sm, vec16 *lds) {
     constexpr uint32_t VPT = Shape<ELEM, 5>::VPT;
     const uint32_t tid = threadIdx.x;
     if (sm.direct) {
-        if (tid < (1u << sm.M)) {
-            uint64_t x = tid;
-            for (uint32_t s = 0; s < sm.L; ++s) {
-                const uint64_t cm = sm.steps_rev[s].cm;
-                if ((x & cm) == cm) x ^= 1ull << sm.steps_rev[s].tbit;
-            }
-            if (ELEM == 8)
-                reinterpret_cast<uint64_t *>(sm.dst)[tid] = reinterpret_cast<const uint64_t *>(sm.src)[x];
-            else
-                reinterpret_cast<vec16 *>(sm.dst)[tid] = reinterpret_cast<const vec16 *>(sm.src)[x];
-        }
+        if (tid < (1u << sm.M)) direct_row<ELEM>(sm.src, sm.dst, tid, sm.steps_rev, sm.L);
         return;
     }
     const TileArgs &a = sm.ta;
@@ -454,10 +517,10 @@ __device__ __forceinline__ void small_item(const BatchSmall &sm, vec16 *lds) {
         tile_stage<ELEM, 5>(v, a.tb, lds);
     }
     __syncthreads();
-    if (active) tile_emit<ELEM, 5>(w, dst, off, a, lds);
+    if (active) tile_emit<ELEM, 5, SIGN>(w, dst, off, a, lds);
 }
 
-template <int ELEM>
+template <int ELEM, bool SIGN>
 __global__ void __launch_bounds__(256) k_batch(const BatchPass *__restrict__ passes,
                                                const BatchSmall *__restrict__ smalls,
                                                const uint64_t *__restrict__ items, uint32_t n_items,
@@ -489,7 +552,7 @@ __global__ void __launch_bounds__(256) k_batch(const BatchPass *__restrict__ pas
             if (tile < bp.n_tiles) tilemap_one(bp.tm, tile);
             publish(&ctr[1], 1u);
         } else if (kind == kItemSmall) {
-            small_item<ELEM>(smalls[idx], lds);
+            small_item<ELEM, SIGN>(smalls[idx], lds);
         } else {
             const BatchPass &bp = passes[idx];
             if (tid == 0) {
@@ -513,8 +576,8 @@ __global__ void __launch_bounds__(256) k_batch(const BatchPass *__restrict__ pas
             for (uint64_t tile = t0; tile < t1; ++tile) {
                 const uint64_t next_base =
                     tile + 1 < t1 ? rec_base(a.rec + (tile + 1) * a.rec_words) + off_src : ~0ull;
-                tile_step<ELEM, 5, true>(v, src, dst, outer_address(a, tile) + off_dst, next_base, a,
-                                         a.rec + tile * a.rec_words + 2, lds);
+                tile_step<ELEM, 5, true, SIGN>(v, src, dst, outer_address(a, tile) + off_dst, next_base, a,
+                                               a.rec + tile * a.rec_words + 2, lds);
                 __syncthreads();
             }
             publish(&ctr[kBatchCtrHeader + bp.circuit], (uint32_t)(t1 - t0));
@@ -651,15 +714,14 @@ hipError_t launch_small(uint32_t elem, const void *src, void *dst, uint32_t M,
                         const TileArgs &a, hipStream_t st) {
     const size_t lds = (size_t)elem << M;
     const uint32_t threads = 1u << a.tb;
-    hipError_t e;
-    if (elem == 8) {
-        if ((e = allow_lds(k_small<8>, lds)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_small<8>, dim3(1), dim3(threads), lds, st, (const vec16 *)src, (vec16 *)dst, a);
-    } else {
-        if ((e = allow_lds(k_small<16>, lds)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_small<16>, dim3(1), dim3(threads), lds, st, (const vec16 *)src, (vec16 *)dst, a);
-    }
-    return hipGetLastError();
+    auto go = [&](auto kern) {
+        hipError_t e = allow_lds(kern, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3(1), dim3(threads), lds, st, (const vec16 *)src, (vec16 *)dst, a);
+        return hipGetLastError();
+    };
+    if (elem == 8) return a.sign ? go(k_small<8, true>) : go(k_small<8, false>);
+    return a.sign ? go(k_small<16, true>) : go(k_small<16, false>);
 }
 
 hipError_t launch_tilemap(const TileMapArgs &a, hipStream_t st) {
@@ -682,14 +744,14 @@ uint64_t resident_blocks(KernelT kernel, uint32_t threads, size_t lds) {
     return (uint64_t)cus * (uint64_t)(per_cu > 0 ? per_cu : 1);
 }
 
-template <int ELEM, int DEPTH, int EB>
+template <int ELEM, int DEPTH, int EB, bool SIGN>
 hipError_t launch_tile_t(const void *src, void *dst, uint64_t n_tiles, const TileArgs &a, uint32_t wg_per_cu,
                          hipStream_t st) {
     const size_t lds = (size_t)ELEM << (a.tb + EB);
     const uint32_t threads = 1u << a.tb;
     if (threads > (EB == 5 ? 512u : 1024u)) return hipErrorInvalidValue;
     hipError_t e;
-    if ((e = allow_lds(k_tile<ELEM, DEPTH, EB>, lds)) != hipSuccess) return e;
+    if ((e = allow_lds(k_tile<ELEM, DEPTH, EB, SIGN>, lds)) != hipSuccess) return e;
     uint64_t grid = n_tiles;
     if (DEPTH > 0) {
         uint64_t r = 0;
@@ -699,22 +761,29 @@ hipError_t launch_tile_t(const void *src, void *dst, uint64_t n_tiles, const Til
             if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
             r = (uint64_t)cus * wg_per_cu;
         } else {
-            r = resident_blocks(k_tile<ELEM, DEPTH, EB>, threads, lds);
+            r = resident_blocks(k_tile<ELEM, DEPTH, EB, SIGN>, threads, lds);
         }
         if (r > 0 && r < grid) grid = r;
     }
-    hipLaunchKernelGGL((k_tile<ELEM, DEPTH, EB>), dim3((uint32_t)grid), dim3(threads), lds, st,
+    hipLaunchKernelGGL((k_tile<ELEM, DEPTH, EB, SIGN>), dim3((uint32_t)grid), dim3(threads), lds, st,
                        (const vec16 *)src, (vec16 *)dst, a, n_tiles);
     return hipGetLastError();
+}
+
+template <int ELEM, int EB, bool SIGN>
+hipError_t launch_tile_s(const void *src, void *dst, uint64_t n_tiles, const TileArgs &a, uint32_t variant,
+                         uint32_t wg_per_cu, hipStream_t st) {
+    if constexpr (ELEM == 8)
+        if (variant == 2) return launch_tile_t<ELEM, 2, EB, SIGN>(src, dst, n_tiles, a, wg_per_cu, st);
+    if (variant >= 1) return launch_tile_t<ELEM, 1, EB, SIGN>(src, dst, n_tiles, a, wg_per_cu, st);
+    return launch_tile_t<ELEM, 0, EB, SIGN>(src, dst, n_tiles, a, wg_per_cu, st);
 }
 
 template <int ELEM, int EB>
 hipError_t launch_tile_e(const void *src, void *dst, uint64_t n_tiles, const TileArgs &a, uint32_t variant,
                          uint32_t wg_per_cu, hipStream_t st) {
-    if constexpr (ELEM == 8)
-        if (variant == 2) return launch_tile_t<ELEM, 2, EB>(src, dst, n_tiles, a, wg_per_cu, st);
-    if (variant >= 1) return launch_tile_t<ELEM, 1, EB>(src, dst, n_tiles, a, wg_per_cu, st);
-    return launch_tile_t<ELEM, 0, EB>(src, dst, n_tiles, a, wg_per_cu, st);
+    if (a.sign) return launch_tile_s<ELEM, EB, true>(src, dst, n_tiles, a, variant, wg_per_cu, st);
+    return launch_tile_s<ELEM, EB, false>(src, dst, n_tiles, a, variant, wg_per_cu, st);
 }
 
 // variant 0: one tile per workgroup; 1: persistent, loads one tile ahead;
@@ -747,31 +816,36 @@ hipError_t launch_plain_step(uint32_t elem, void *buf, uint32_t M, uint32_t targ
     return hipGetLastError();
 }
 
-hipError_t launch_batch(uint32_t elem, uint32_t tb, const BatchPass *passes, const BatchSmall *smalls,
+hipError_t launch_plain_phase(uint32_t elem, void *buf, uint32_t M, uint64_t mask, hipStream_t st) {
+    const uint64_t n_rows = 1ull << (M - (uint32_t)__builtin_popcountll(mask));
+    const uint32_t bs = 256;
+    const uint64_t grid = std::min<uint64_t>((n_rows + bs - 1) / bs, 1ull << 22);
+    if (elem == 8)
+        hipLaunchKernelGGL(k_plain_phase<8>, dim3((uint32_t)grid), dim3(bs), 0, st, (uint8_t *)buf, n_rows, mask, M);
+    else
+        hipLaunchKernelGGL(k_plain_phase<16>, dim3((uint32_t)grid), dim3(bs), 0, st, (uint8_t *)buf, n_rows, mask, M);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(uint32_t elem, uint32_t tb, bool sign, const BatchPass *passes, const BatchSmall *smalls,
                         const uint64_t *items, uint32_t n_items, uint32_t *counters, uint32_t n_rec_blocks,
                         uint32_t spin_limit, hipStream_t st) {
     const uint32_t threads = 1u << tb;
     const size_t lds = (size_t)elem << (tb + 5);
     if (threads > 256) return hipErrorInvalidValue;
-    hipError_t e;
-    uint64_t grid = 0;
-    if (elem == 8) {
-        if ((e = allow_lds(k_batch<8>, lds)) != hipSuccess) return e;
-        grid = resident_blocks(k_batch<8>, threads, lds);
-    } else {
-        if ((e = allow_lds(k_batch<16>, lds)) != hipSuccess) return e;
-        grid = resident_blocks(k_batch<16>, threads, lds);
-    }
-    if (grid == 0) grid = 256;
-    if (grid > n_items) grid = n_items;
-    if (grid == 0) return hipSuccess;
-    if (elem == 8)
-        hipLaunchKernelGGL(k_batch<8>, dim3((uint32_t)grid), dim3(threads), lds, st, passes, smalls, items,
-                           n_items, counters, n_rec_blocks, spin_limit);
-    else
-        hipLaunchKernelGGL(k_batch<16>, dim3((uint32_t)grid), dim3(threads), lds, st, passes, smalls, items,
-                           n_items, counters, n_rec_blocks, spin_limit);
-    return hipGetLastError();
+    auto go = [&](auto kern) {
+        hipError_t e = allow_lds(kern, lds);
+        if (e != hipSuccess) return e;
+        uint64_t grid = resident_blocks(kern, threads, lds);
+        if (grid == 0) grid = 256;
+        if (grid > n_items) grid = n_items;
+        if (grid == 0) return hipSuccess;
+        hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(threads), lds, st, passes, smalls, items, n_items,
+                           counters, n_rec_blocks, spin_limit);
+        return hipGetLastError();
+    };
+    if (elem == 8) return sign ? go(k_batch<8, true>) : go(k_batch<8, false>);
+    return sign ? go(k_batch<16, true>) : go(k_batch<16, false>);
 }
 
 hipError_t launch_product(uint32_t elem, void *out, uint32_t M, const void *qubits, hipStream_t st) {

@@ -17,6 +17,16 @@
 // Sec. 2(i)).  The scan below keeps every step behind each earlier step it
 // does not commute with, so the product of the reordered list is the
 // product of the original one.
+//
+// A phase step (a diagonal matrix: -1 on the rows whose bits t and C are
+// all 1) moves nothing, so it joins any pass: inside a tile it flips the
+// sign of the rows its tile bits select, for the tiles its outside bits
+// select.  In terms of commutation it writes no address bit and reads all
+// of C and t: it commutes with a NOT step unless that step's target is one
+// of its bits, and with every other phase step.  With write mask W (the
+// NOT's target bit, none for a phase step) and read mask R (the controls,
+// plus the target for a phase step), two steps commute iff neither writes
+// a bit the other reads.
 #include <algorithm>
 #include <stdexcept>
 
@@ -28,19 +38,18 @@ namespace {
 
 inline int popc(uint64_t x) { return __builtin_popcountll(x); }
 
-inline bool commute(uint32_t t1, uint64_t c1, uint32_t t2, uint64_t c2) {
-    return !((c2 >> t1) & 1ull) && !((c1 >> t2) & 1ull);
-}
+inline bool is_phase(const uint8_t *kind, uint32_t s) { return kind && kind[s] == kStepPhase; }
 
 // Smallest mask containing `I` under which every step of `taken` (plus the
 // candidate step, if any) is admissible; returns 0 if that needs more than
 // `K` bits or a bit outside `allowed`.
 uint64_t close_mask(uint64_t I, const std::vector<uint32_t> &taken, int cand, const uint32_t *target,
-                    const uint64_t *cmask, int K, uint64_t allowed) {
+                    const uint64_t *cmask, const uint8_t *kind, int K, uint64_t allowed) {
     bool changed = true;
     while (changed) {
         changed = false;
         auto visit = [&](uint32_t q) {
+            if (is_phase(kind, q)) return;
             const uint64_t T = 1ull << target[q];
             if (!(I & T) && (cmask[q] & I)) {
                 I |= T;
@@ -56,8 +65,8 @@ uint64_t close_mask(uint64_t I, const std::vector<uint32_t> &taken, int cand, co
 
 }  // namespace
 
-std::vector<Pass> plan_passes(uint32_t M, const uint32_t *target, const uint64_t *cmask, uint64_t L,
-                              const PlanConfig &cfg) {
+std::vector<Pass> plan_passes(uint32_t M, const uint32_t *target, const uint64_t *cmask, const uint8_t *kind,
+                              uint64_t L, const PlanConfig &cfg) {
     std::vector<Pass> passes;
     if (L == 0) return passes;
     const int K = std::min<int>(cfg.tile_bits, (int)M);
@@ -74,13 +83,20 @@ std::vector<Pass> plan_passes(uint32_t M, const uint32_t *target, const uint64_t
     pending.reserve(L);
     for (uint64_t s = 0; s < L; ++s) pending.push_back((uint32_t)s);
 
-    // Controls of the taken steps whose target lies outside mask I: bits that
-    // cannot join the tile any more without pulling those targets in.
+    // Write and read masks (see the top of the file).
+    auto WM = [&](uint32_t s) { return is_phase(kind, s) ? 0ull : 1ull << target[s]; };
+    auto RM = [&](uint32_t s) { return is_phase(kind, s) ? (cmask[s] | (1ull << target[s])) : cmask[s]; };
+    // Admissible in a pass with tile mask I.
+    auto admissible = [&](uint32_t s, uint64_t I) {
+        return is_phase(kind, s) || ((I >> target[s]) & 1ull) || !(cmask[s] & I);
+    };
+    // Controls of the taken NOT steps whose target lies outside mask I: bits
+    // that cannot join the tile any more without pulling those targets in.
     auto outer_controls = [&](const std::vector<uint32_t> &taken, int cand, uint64_t I) {
         uint64_t U = 0;
         for (uint32_t q : taken)
-            if (!((I >> target[q]) & 1ull)) U |= cmask[q];
-        if (cand >= 0 && !((I >> target[cand]) & 1ull)) U |= cmask[cand];
+            if (!is_phase(kind, q) && !((I >> target[q]) & 1ull)) U |= cmask[q];
+        if (cand >= 0 && !is_phase(kind, (uint32_t)cand) && !((I >> target[cand]) & 1ull)) U |= cmask[cand];
         return U;
     };
     // A pass must still be able to grow its tile to K bits with bits that no
@@ -100,14 +116,13 @@ std::vector<Pass> plan_passes(uint32_t M, const uint32_t *target, const uint64_t
         bool any_blocked = false;
         int n = 0;
         for (uint32_t s : pending) {
-            const bool ready = n < cap &&
-                               (cfg.reorder ? !((cmask[s] & BT) || ((BC >> target[s]) & 1ull)) : !any_blocked);
-            if (ready && (((I >> target[s]) & 1ull) || !(cmask[s] & I))) {
+            const bool ready = n < cap && (cfg.reorder ? !((RM(s) & BT) || (WM(s) & BC)) : !any_blocked);
+            if (ready && admissible(s, I)) {
                 ++n;
                 if (take) take->push_back(s);
             } else {
-                BT |= 1ull << target[s];
-                BC |= cmask[s];
+                BT |= WM(s);
+                BC |= RM(s);
                 any_blocked = true;
             }
         }
@@ -148,24 +163,26 @@ std::vector<Pass> plan_passes(uint32_t M, const uint32_t *target, const uint64_t
         std::vector<uint32_t> taken;
         for (uint32_t s : pending) {
             if ((int)taken.size() >= cap) break;
-            const bool ready = cfg.reorder ? !((cmask[s] & BT) || ((BC >> target[s]) & 1ull)) : !any_blocked;
+            const bool ready = cfg.reorder ? !((RM(s) & BT) || (WM(s) & BC)) : !any_blocked;
             if (!ready) {
                 state[s] = 3;
-                BT |= 1ull << target[s];
-                BC |= cmask[s];
+                BT |= WM(s);
+                BC |= RM(s);
                 any_blocked = true;
                 continue;
             }
             const uint64_t T = 1ull << target[s];
             bool took = false;
-            if (I & T) {
+            if (is_phase(kind, s)) {
+                took = true;                       // moves nothing: any tile
+            } else if (I & T) {
                 took = true;                       // inner step: U unchanged
             } else if (!(cmask[s] & I) && completable(I, U | cmask[s])) {
                 U |= cmask[s];                     // outer step
                 took = true;
             } else {
                 // make it an inner step by adding its target (and the closure)
-                const uint64_t J = close_mask(I | T, taken, (int)s, target, cmask, K, allowed);
+                const uint64_t J = close_mask(I | T, taken, (int)s, target, cmask, kind, K, allowed);
                 if (J) {
                     const uint64_t UJ = outer_controls(taken, (int)s, J);
                     if (completable(J, UJ)) {
@@ -180,8 +197,8 @@ std::vector<Pass> plan_passes(uint32_t M, const uint32_t *target, const uint64_t
                 state[s] = 2;
             } else {
                 state[s] = 3;
-                BT |= 1ull << target[s];
-                BC |= cmask[s];
+                BT |= WM(s);
+                BC |= RM(s);
                 any_blocked = true;
             }
         }
@@ -236,6 +253,7 @@ std::vector<Pass> plan_passes(uint32_t M, const uint32_t *target, const uint64_t
         uint64_t I = mid_base;
         for (uint32_t s : pending) {
             if (popc(I & prev) >= min_ov) break;
+            if (is_phase(kind, s)) continue;
             const uint64_t T = 1ull << target[s];
             if ((prev & T) && (allowed & T)) I |= T;
         }

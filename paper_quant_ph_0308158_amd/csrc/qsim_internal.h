@@ -18,10 +18,22 @@ constexpr int kMaxTileBits = 14;   // 2^14 entries * 8 B = 128 KiB of LDS
 constexpr int kMaxOuterBits = 48;
 constexpr uint32_t kMaxQubits = 36;    // largest M of a state
 
+// Step kinds as the library stores them (the public qsim_step_kind values).
+constexpr uint8_t kStepNot = 0;
+constexpr uint8_t kStepPhase = 1;
+
+// Bit-plane that carries the sign of each row during the inner walk: tile
+// indices have at most kMaxTileBits bits, so plane 15 is free.  A phase
+// step is an inner step that targets it.
+constexpr uint32_t kSignPlane = 15;
+
 // A step as the tile-map kernel sees it (16 bytes).  `cm` is the part of the
 // control mask outside the tile; `tbit` is the address bit of the target;
 // `inner` is 1 when the target is a tile bit (the step moves entries inside
-// a tile and the tile-map only records whether its outside controls hold).
+// a tile and the tile-map only records whether its outside controls hold)
+// and for every phase step (outside part of its mask, target included).
+// In the direct per-row walk `inner` = 1 marks a phase step and `cm` is
+// its whole mask.
 struct TmStep {
     uint64_t cm;
     uint32_t tbit;
@@ -50,7 +62,7 @@ struct TileArgs {
     uint32_t tb;            // log2(threads per workgroup); tile bits = tb + eb
     uint32_t n_out;         // outer bits (M - tile bits)
     uint32_t eb;            // log2(tile rows per thread): 3, 4 or 5
-    uint32_t pad;
+    uint32_t sign;          // 1 when the pass has phase steps (sign plane in use)
     uint32_t off_r_src[32]; // element offset of the tile-index bits above the thread bits, per r (read)
     uint32_t off_r_dst[32]; // same for the write layout
     uint8_t pos_src[16];    // physical bit of tile-index bit b in the read layout
@@ -125,7 +137,8 @@ struct PlanConfig {
 };
 
 // Split steps into passes (see planner.cpp).
-std::vector<Pass> plan_passes(uint32_t M, const uint32_t *target, const uint64_t *cmask,
+// kind may be null (every step a controlled NOT).
+std::vector<Pass> plan_passes(uint32_t M, const uint32_t *target, const uint64_t *cmask, const uint8_t *kind,
                               uint64_t L, const PlanConfig &cfg);
 
 }  // namespace qsim
@@ -149,12 +162,13 @@ hipError_t launch_tile(uint32_t elem, const void *src, void *dst, uint64_t n_til
                        uint32_t variant, uint32_t wg_per_cu, hipStream_t st);
 hipError_t launch_plain_step(uint32_t elem, void *buf, uint32_t M, uint32_t target,
                              uint64_t cmask, hipStream_t st);
+hipError_t launch_plain_phase(uint32_t elem, void *buf, uint32_t M, uint64_t mask, hipStream_t st);
 hipError_t launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t st);
 hipError_t launch_product(uint32_t elem, void *out, uint32_t M, const void *qubits, hipStream_t st);
 hipError_t launch_iota(uint64_t *out, uint64_t n, hipStream_t st);
 hipError_t launch_narrow(const uint64_t *in, uint32_t *out, uint64_t n, hipStream_t st);
 hipError_t launch_gather(uint32_t elem, const void *src, void *dst, const uint32_t *x, uint64_t n, hipStream_t st);
-hipError_t launch_batch(uint32_t elem, uint32_t tb, const BatchPass *passes, const BatchSmall *smalls,
+hipError_t launch_batch(uint32_t elem, uint32_t tb, bool sign, const BatchPass *passes, const BatchSmall *smalls,
                         const uint64_t *items, uint32_t n_items, uint32_t *counters, uint32_t n_rec_blocks,
                         uint32_t spin_limit, hipStream_t st);
 

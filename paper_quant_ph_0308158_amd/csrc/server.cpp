@@ -339,7 +339,7 @@ int64_t qsim_server_submit(qsim_server *srv, uint32_t M, qsim_dtype dtype, const
     if (L > 0 && !steps) return QSIM_ERR_INVALID;
     const uint64_t all = (1ull << M) - 1ull;
     for (uint64_t i = 0; i < L; ++i)
-        if (steps[i].reserved0 || steps[i].target >= M || (steps[i].control_mask & ~all) ||
+        if (steps[i].kind > QSIM_STEP_PHASE || steps[i].target >= M || (steps[i].control_mask & ~all) ||
             ((steps[i].control_mask >> steps[i].target) & 1ull))
             return QSIM_ERR_INVALID;
     auto r = std::make_shared<Request>();

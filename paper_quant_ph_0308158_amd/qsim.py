@@ -26,7 +26,8 @@ QSIM_C128 = 1
 OK, ERR_INVALID, ERR_NOMEM, ERR_DEVICE, ERR_RANGE = 0, -1, -2, -3, -4
 MAX_M = 36
 
-STEP_DTYPE = np.dtype([("target", "<u4"), ("reserved0", "<u4"), ("control_mask", "<u8")])
+STEP_DTYPE = np.dtype([("target", "<u4"), ("kind", "<u4"), ("control_mask", "<u8")])
+STEP_NOT, STEP_PHASE = 0, 1   # qsim_step_kind
 
 # Every symbol declared in include/qsim.h.
 EXPORTS = (
@@ -176,7 +177,9 @@ def np_dtype(code: int):
     return np.complex64 if code == QSIM_C64 else np.complex128
 
 
-def pack_steps(target, cmask) -> np.ndarray:
+def pack_steps(target, cmask, kind=None) -> np.ndarray:
+    """qsim_step array; ``kind`` (optional, per step): STEP_NOT (controlled
+    NOT, the default) or STEP_PHASE (controlled phase -1)."""
     t = np.asarray(target, dtype=np.uint32).ravel()
     c = np.asarray(cmask, dtype=np.uint64).ravel()
     if t.shape != c.shape:
@@ -184,6 +187,11 @@ def pack_steps(target, cmask) -> np.ndarray:
     st = np.zeros(len(t), dtype=STEP_DTYPE)
     st["target"] = t
     st["control_mask"] = c
+    if kind is not None:
+        k = np.asarray(kind, dtype=np.uint32).ravel()
+        if k.shape != t.shape:
+            raise ValueError("kind and target differ in length")
+        st["kind"] = k
     return st
 
 
@@ -286,8 +294,8 @@ class State:
                                             ctypes.c_void_p(_stream_ptr(stream))))
 
     # -- compute
-    def apply(self, target, cmask, stream=None):
-        st = pack_steps(target, cmask)
+    def apply(self, target, cmask, stream=None, kind=None):
+        st = pack_steps(target, cmask, kind)
         _check(_lib.qsim_apply_steps(self._h, st.ctypes.data if len(st) else None, len(st),
                                      ctypes.c_void_p(_stream_ptr(stream))))
 
@@ -306,13 +314,13 @@ class State:
         """current <- k1(x(i)) with a device row array from rowmap_build."""
         _check(_lib.qsim_rowmap_apply(self._h, ctypes.c_void_p(_ptr(x_ptr)), ctypes.c_void_p(_stream_ptr(stream))))
 
-    def apply_tile_pass(self, tile_mask: int, target, cmask, stream=None):
-        st = pack_steps(target, cmask)
+    def apply_tile_pass(self, tile_mask: int, target, cmask, stream=None, kind=None):
+        st = pack_steps(target, cmask, kind)
         _check(_lib.qsim_apply_tile_pass(self._h, int(tile_mask), st.ctypes.data if len(st) else None,
                                          len(st), ctypes.c_void_p(_stream_ptr(stream))))
 
-    def apply_plain(self, target, cmask, stream=None):
-        st = pack_steps(target, cmask)
+    def apply_plain(self, target, cmask, stream=None, kind=None):
+        st = pack_steps(target, cmask, kind)
         _check(_lib.qsim_apply_steps_plain(self._h, st.ctypes.data if len(st) else None, len(st),
                                            ctypes.c_void_p(_stream_ptr(stream))))
 
@@ -324,10 +332,10 @@ class State:
         _check(_lib.qsim_state_profile_read(self._h, ctypes.byref(p)))
         return p.as_dict()
 
-    def autotune(self, target, cmask, stream=None) -> dict:
+    def autotune(self, target, cmask, stream=None, kind=None) -> dict:
         """Measure candidate tunings for this diagram on this state (contents
         unchanged) and keep the fastest; returns it."""
-        st = pack_steps(target, cmask)
+        st = pack_steps(target, cmask, kind)
         t = Tuning()
         _check(_lib.qsim_autotune(self._h, st.ctypes.data if len(st) else None, len(st),
                                   ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(t)))
@@ -344,9 +352,10 @@ def _ptr(buf) -> int:
     return int(buf.data_ptr())
 
 
-def apply_batch(states: Sequence[State], steps: Sequence[Tuple[np.ndarray, np.ndarray]], stream=None):
+def apply_batch(states: Sequence[State], steps: Sequence[Tuple], stream=None):
+    """steps[c] = (target, cmask) or (target, cmask, kind) for circuit c."""
     n = len(states)
-    packed = [pack_steps(t, c) for t, c in steps]
+    packed = [pack_steps(*sc) for sc in steps]
     hs = (ctypes.c_void_p * n)(*[s.handle.value for s in states])
     ps = (ctypes.c_void_p * n)(*[p.ctypes.data if len(p) else None for p in packed])
     ls = (ctypes.c_uint64 * n)(*[len(p) for p in packed])
@@ -364,10 +373,11 @@ def apply_batch_packed(states: Sequence[State], packed: Sequence[np.ndarray], st
                                  ctypes.cast(ls, ctypes.c_void_p), n, ctypes.c_void_p(_stream_ptr(stream))))
 
 
-def rowmap_build(M: int, target, cmask, x_dev, stream=None):
+def rowmap_build(M: int, target, cmask, x_dev, stream=None, kind=None):
     """Write the row array x of the diagram (k2(i) = k1(x(i))) into x_dev: a
-    device buffer of 2^M uint32 (a torch tensor or a raw pointer)."""
-    st = pack_steps(target, cmask)
+    device buffer of 2^M uint32 (a torch tensor or a raw pointer).  Phase
+    steps are rejected: a row array holds no signs."""
+    st = pack_steps(target, cmask, kind)
     _check(_lib.qsim_rowmap_build(M, st.ctypes.data if len(st) else None, len(st), ctypes.c_void_p(_ptr(x_dev)),
                                   ctypes.c_void_p(_stream_ptr(stream))))
 
@@ -377,9 +387,9 @@ def batch_status():
     _check(_lib.qsim_batch_last_status())
 
 
-def plan_describe(M: int, dtype, target, cmask, tuning: Optional[dict] = None):
+def plan_describe(M: int, dtype, target, cmask, tuning: Optional[dict] = None, kind=None):
     """Host-only pass plan: (masks, lens, order)."""
-    st = pack_steps(target, cmask)
+    st = pack_steps(target, cmask, kind)
     L = len(st)
     n_passes = ctypes.c_uint32(0)
     t = _tuning_struct(tuning)
@@ -417,8 +427,8 @@ class Server:
             raise QsimError(ERR_NOMEM, "qsim_server_create failed")
         self._h = ctypes.c_void_p(h)
 
-    def submit(self, M: int, dtype, target, cmask, k1: Optional[np.ndarray] = None) -> int:
-        st = pack_steps(target, cmask)
+    def submit(self, M: int, dtype, target, cmask, k1: Optional[np.ndarray] = None, kind=None) -> int:
+        st = pack_steps(target, cmask, kind)
         ptr = None
         if k1 is not None:
             k1 = np.ascontiguousarray(k1)

@@ -58,13 +58,17 @@ def test_invalid_m_and_dtype():
         qsim.plan_describe(8, "c64", [0], [0], tuning={"tile_bits": 20})
 
 
-def test_reserved_field_must_be_zero():
-    st = qsim.pack_steps([1], [0])
-    st["reserved0"] = 7
+def test_unknown_step_kind_rejected():
+    st = qsim.pack_steps([1, 2], [0, 1], kind=[qsim.STEP_NOT, qsim.STEP_PHASE])
     n = qsim.ctypes.c_uint32(0)
-    rc = qsim.lib().qsim_plan_describe(8, 0, st.ctypes.data, 1, None, qsim.ctypes.byref(n),
+    rc = qsim.lib().qsim_plan_describe(8, 0, st.ctypes.data, 2, None, qsim.ctypes.byref(n),
+                                       None, None, 0, None)
+    assert rc == 0
+    st["kind"][1] = 7
+    rc = qsim.lib().qsim_plan_describe(8, 0, st.ctypes.data, 2, None, qsim.ctypes.byref(n),
                                        None, None, 0, None)
     assert rc == qsim.ERR_INVALID
+    assert "kind" in qsim.last_error()
 
 
 def test_create_without_device_fails_cleanly():
@@ -75,8 +79,8 @@ def test_create_without_device_fails_cleanly():
         qsim.State(10, "c64")
 
 
-def _check_plan(M, dtype, tg, cm, tuning):
-    masks, lens, order = qsim.plan_describe(M, dtype, tg, cm, tuning)
+def _check_plan(M, dtype, tg, cm, tuning, kd=None):
+    masks, lens, order = qsim.plan_describe(M, dtype, tg, cm, tuning, kind=kd)
     L = len(tg)
     assert sorted(order.tolist()) == list(range(L))
     assert int(lens.sum()) == L
@@ -94,6 +98,8 @@ def _check_plan(M, dtype, tg, cm, tuning):
         assert 1 <= n <= cap
         for s in order[pos:pos + n]:
             t, c = int(tg[s]), int(cm[s])
+            if kd is not None and kd[s] == qsim.STEP_PHASE:
+                continue                      # moves nothing: fits any tile
             assert (I >> t) & 1 or not (c & I), f"step {s} splits tiles of pass {p}"
         pos += n
     return masks, lens, order
@@ -149,3 +155,30 @@ def test_planner_same_target_run_is_one_pass():
                   dtype=np.uint64)
     masks, lens, order = _check_plan(M, "c64", tg, cm, {})
     assert len(masks) == 1
+
+
+@pytest.mark.parametrize("seed,M,dtype,tuning", [
+    (20, 12, "c64", {"tile_bits": 6, "low_bits": 2}),
+    (21, 14, "c128", {"tile_bits": 7, "low_bits": 3, "plan_search": 2}),
+    (22, 16, "c64", {"tile_bits": 8, "max_seg_steps": 9}),
+    (23, 13, "c64", {"tile_bits": 5, "low_bits": 1, "min_overlap": 5}),
+])
+def test_planner_reorder_is_exact_with_phase_steps(seed, M, dtype, tuning):
+    """Phase steps join any pass and move only past steps they commute with
+    (no NOT of theirs targets one of their bits): the reordered list has the
+    same signed product (oracle on integer-valued entries)."""
+    rng = np.random.default_rng(seed)
+    tg, cm = W.random_steps(rng, M, 150, (0, 3))
+    kd = (rng.random(150) < 0.4).astype(np.uint8)
+    masks, lens, order = _check_plan(M, dtype, tg, cm, tuning, kd)
+    assert len(masks) > 1
+    k1 = (np.arange(1 << M) + 1j * np.arange(1 << M)[::-1]).astype(np.complex128)
+    a = oracle.apply(M, k1, tg, cm, kind=kd)
+    b = oracle.apply(M, k1, tg[order], cm[order], kind=kd[order])
+    assert a.tobytes() == b.tobytes()
+
+
+def test_rowmap_rejects_phase_steps():
+    with pytest.raises(qsim.QsimError) as ei:
+        qsim.rowmap_build(8, [1], [0], 0, kind=[qsim.STEP_PHASE])
+    assert ei.value.code == qsim.ERR_INVALID

@@ -466,6 +466,9 @@ def test_signed_dense_bruteforce(seed):
         np.testing.assert_array_equal(got, expect)
         idx = rng.integers(0, n, size=13)
         np.testing.assert_array_equal(oracle.sample_rows(M, k1, tg, cm, idx, kind=kd), expect[idx])
+    for i in range(n):
+        x, neg = oracle.source_index_signed(M, tg, cm, kd, i)
+        assert U[i, x] == (-1 if neg else 1)
     # all-NOT kinds reduce to the unsigned oracle
     k1 = W.gaussian_state(rng, M, np.complex64)
     z = np.zeros(L, dtype=np.uint8)
