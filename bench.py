@@ -295,11 +295,26 @@ def main():
 
     modes = None
     if not args.no_modes and args.workload == "m32":
+        # Signed diagram: the same steps with every fourth one a controlled
+        # phase -1 instead of a NOT (phase steps join any pass).
+        kd = (np.arange(L) % 4 == 3).astype(np.uint8)
+        s_masks = qsim.plan_describe(M, dt, tg, cm, tuning, kind=kd)[0]
+        st.apply(tg, cm, kind=kd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(2):
+            st.apply(tg, cm, kind=kd)
+        torch.cuda.synchronize()
+        s_ms = (time.perf_counter() - t0) / 2 * 1e3
+        signed = {"ms_per_step": round(s_ms, 3), "passes": int(len(s_masks)),
+                  "value": float(1 << M) * L / (s_ms * 1e-3), "phase_steps": int(kd.sum()),
+                  "vs_unsigned": round(ms_per_step / s_ms, 4)}
         st.close()
         del k1, other
         torch.cuda.empty_cache()
         k1 = other = None
-        modes = {"batched": bench_batched(2), "served": bench_served(args.requests, W.SERVED_RATE)}
+        modes = {"batched": bench_batched(2), "served": bench_served(args.requests, W.SERVED_RATE),
+                 "signed": signed}
         torch.cuda.empty_cache()
 
     cpu = None

@@ -421,26 +421,47 @@ int prepare_passes(uint32_t M, uint32_t elem, const std::vector<Pass> &passes,
             if ((I >> b) & 1ull) in_log[ni++] = (uint8_t)b;
             else out_log[no++] = (uint8_t)b;
         }
-        // Tile-index bit j of the kernel is tile bit in_log[j].  Ordering them
-        // by physical position in the written layout makes the lanes of one
-        // wave store cover whole contiguous lines; bit 0 stays first (its
-        // physical position is 0 in every layout, which the 8-byte pairs need).
-        // Kernel index bits: LO pair bit, then 6 lane bits, then the wave
-        // bits, then the per-thread row bits.
-        std::sort(in_log, in_log + ni, [&](uint8_t x, uint8_t y) { return ld[x] < ld[y]; });
-        // The thread bits above the 64 lanes of a wave (the wave number)
-        // take the highest written positions and the per-thread rows the
-        // ones below, so that each wave's stores cover one compact block
+        // Tile-index bit j of the kernel is tile bit in_log[j].  Kernel index
+        // bits: the LO pair bit and 6 lane bits (one wave instruction moves
+        // these 2^(LO+6) rows), then the wave bits, then the per-thread row
+        // bits.  The lane bits hold the tile bits at the lowest physical
+        // positions of both layouts (the bits inside one 128-byte line), so
+        // every load and every store instruction covers whole lines: a line
+        // split across instructions can leave L2 before its last part is
+        // read, and is then fetched twice.  The rest of the lanes, and the
+        // order within them, follow the written layout so a wave store
+        // covers contiguous lines; bit 0 stays first (its physical position
+        // is 0 in every layout, which the 8-byte pairs need).  The wave bits
+        // take the highest written positions and the row bits the ones
+        // between, so that each wave's stores cover one compact block
         // (measured faster than rows spread over the whole tile).
+        std::sort(in_log, in_log + ni, [&](uint8_t x, uint8_t y) { return ld[x] < ld[y]; });
         {
-            const uint32_t lanes = LO + 6, tb = K - eb;
-            if (tb > 6) {
-                const uint32_t nw = tb - 6;
-                uint8_t by_pos[16];
-                std::memcpy(by_pos, in_log, sizeof(by_pos));
-                for (uint32_t q = 0; q < nw; ++q) in_log[lanes + q] = by_pos[K - nw + q];
-                for (uint32_t q = 0; q < K - lanes - nw; ++q) in_log[lanes + nw + q] = by_pos[lanes + q];
-            }
+            const uint32_t lanes = std::min<uint32_t>(LO + 6, K), tb = K - eb;
+            const uint32_t line_bits = elem == 8 ? 4u : 3u;
+            uint8_t by_pos[16];
+            std::memcpy(by_pos, in_log, sizeof(by_pos));
+            bool lane[16] = {false};
+            uint32_t nl = 0;
+            // written-side line bits first, then read-side ones, then the
+            // lowest remaining written positions
+            for (int pass = 0; pass < 3; ++pass)
+                for (uint32_t q = 0; q < K && nl < lanes; ++q) {
+                    const uint8_t b = by_pos[q];
+                    if (lane[q]) continue;
+                    const bool take = pass == 0 ? ld[b] < line_bits : (pass == 1 ? ls[b] < line_bits : true);
+                    if (take) { lane[q] = true; ++nl; }
+                }
+            uint32_t k = 0;
+            for (uint32_t q = 0; q < K; ++q)
+                if (lane[q]) in_log[k++] = by_pos[q];
+            uint8_t rest[16];
+            uint32_t nr = 0;
+            for (uint32_t q = 0; q < K; ++q)
+                if (!lane[q]) rest[nr++] = by_pos[q];
+            const uint32_t nw = tb > 6 ? tb - 6 : 0;
+            for (uint32_t q = 0; q < nw; ++q) in_log[k++] = rest[nr - nw + q];
+            for (uint32_t q = 0; q + nw < nr; ++q) in_log[k++] = rest[q];
         }
         for (uint32_t j = 0; j < ni; ++j) jpos[in_log[j]] = (uint8_t)j;
         // Tiles may be enumerated in any order: outer_order picks which
