@@ -31,12 +31,18 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBPS = 8000.0   # MI355X published HBM3E bandwidth
 PROFILES = os.path.join(ROOT, "profiles")
-KERNEL_SRC = os.path.join(ROOT, "paper_quant_ph_0308158_amd", "csrc", "kernels.hip")
+# Sources that decide the tile kernel's memory traffic: the kernels, and the
+# host code that plans passes and lays out the state between them.
+TRAFFIC_SRC = [os.path.join(ROOT, "paper_quant_ph_0308158_amd", "csrc", f)
+               for f in ("kernels.hip", "qsim_internal.h", "abi.cpp", "planner.cpp")]
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in TRAFFIC_SRC:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def workload(name: str):

@@ -305,6 +305,10 @@ typedef struct {
                               pass, swap single tile bits for outside bits
                               while that admits more pending steps (fewer
                               passes, more host time); 0 = on for M >= 30 */
+    uint32_t xcd_swizzle;  /* 1 = off, 2 = on (default): the one-tile-per-
+                              workgroup kernel maps 64 consecutive tiles to
+                              one XCD (workgroups are dealt to the 8 XCDs in
+                              turn), so neighbouring tiles share an L2    */
 } qsim_tuning;
 
 /* Set (tuning != NULL) or reset to defaults (NULL) the parameters used by

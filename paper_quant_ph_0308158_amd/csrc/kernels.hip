@@ -269,6 +269,15 @@ __device__ __forceinline__ void tile_step(TileVecs<ELEM, EB> &v, const vec16 *__
     tile_emit<ELEM, EB, SIGN>(w, dst, dst_base, a, lds);
 }
 
+// Tile of workgroup b when consecutive workgroups go to the 8 XCDs in turn:
+// 2^g consecutive tiles run on one XCD, so tiles that write parts of the
+// same lines share that XCD's L2.  g = 0: tile b.
+__device__ __forceinline__ uint64_t xcd_tile(uint64_t b, uint32_t g) {
+    if (!g) return b;
+    const uint64_t lo = (b >> 3) & ((1ull << g) - 1ull);
+    return lo | ((b & 7ull) << g) | ((b >> (3 + g)) << (g + 3));
+}
+
 __device__ __forceinline__ uint64_t rec_base(const uint32_t *rec) {
     return (uint64_t)uni(rec[0]) | ((uint64_t)uni(rec[1]) << 32);
 }
@@ -288,13 +297,14 @@ __global__ void __launch_bounds__(EB == 5 ? 512 : 1024) k_tile(const vec16 *__re
     const uint32_t off_src = thread_offset<ELEM>(a.pos_src, a.tb, threadIdx.x);
     const uint32_t off_dst = thread_offset<ELEM>(a.pos_dst, a.tb, threadIdx.x);
     const uint64_t stride = DEPTH > 0 ? gridDim.x : n_tiles;
+    const uint64_t b0 = DEPTH > 0 ? (uint64_t)blockIdx.x : xcd_tile(blockIdx.x, a.xcd);
     vec16 v[NB][VPT];
 #pragma unroll
     for (int d = 0; d < NB; ++d) {
-        const uint64_t t = blockIdx.x + (uint64_t)d * stride;
+        const uint64_t t = b0 + (uint64_t)d * stride;
         if (t < n_tiles) load_tile<ELEM, EB>(v[d], src, rec_base(a.rec + t * a.rec_words) + off_src, a);
     }
-    for (uint64_t first = blockIdx.x;; first += (uint64_t)NB * stride) {
+    for (uint64_t first = b0;; first += (uint64_t)NB * stride) {
 #pragma unroll
         for (int d = 0; d < NB; ++d) {
             const uint64_t tile = first + (uint64_t)d * stride;
@@ -445,25 +455,15 @@ __global__ void __launch_bounds__(256) k_plain_phase(uint8_t *__restrict__ buf, 
     }
 }
 
-// Plain streaming copy: each thread moves four 16-byte vectors per
-// iteration with all four loads in flight before the stores.
+// Plain streaming copy (the achievable-bandwidth reference): one 16-byte
+// vector per thread and a grid covering the whole buffer, so each
+// workgroup moves one 4 KiB block (the fastest copy shape measured on
+// MI355X, ahead of grid-stride loops with several vectors per thread).
 __global__ void __launch_bounds__(256) k_copy(const vec16 *__restrict__ src, vec16 *__restrict__ dst,
                                               uint64_t nvec) {
-    const uint64_t chunk = (uint64_t)blockDim.x * 4u;
-    const uint64_t stride = (uint64_t)gridDim.x * chunk;
-    for (uint64_t base = (uint64_t)blockIdx.x * chunk; base < nvec; base += stride) {
-        vec16 v[4];
-#pragma unroll
-        for (uint32_t k = 0; k < 4u; ++k) {
-            const uint64_t i = base + threadIdx.x + (uint64_t)k * blockDim.x;
-            if (i < nvec) v[k] = ld_nt(src + i);
-        }
-#pragma unroll
-        for (uint32_t k = 0; k < 4u; ++k) {
-            const uint64_t i = base + threadIdx.x + (uint64_t)k * blockDim.x;
-            if (i < nvec) st_nt(dst + i, v[k]);
-        }
-    }
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;   // loops only past 2^31 vectors
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvec; i += stride)
+        st_nt(dst + i, ld_nt(src + i));
 }
 
 // ------------------------------------------------------------ batched mode
@@ -891,11 +891,7 @@ hipError_t launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t s
     const uint64_t nvec = bytes / 16;
     if (nvec == 0) return hipSuccess;
     const uint32_t bs = 256;
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    uint64_t grid = (nvec + bs * 4 - 1) / (bs * 4);
-    const uint64_t cap = (uint64_t)cus * 8;
-    if (grid > cap) grid = cap;
+    const uint64_t grid = std::min<uint64_t>((nvec + bs - 1) / bs, 1ull << 23);   // at most 2^31 threads
     hipLaunchKernelGGL(k_copy, dim3((uint32_t)grid), dim3(bs), 0, st, (const vec16 *)src, (vec16 *)dst, nvec);
     return hipGetLastError();
 }

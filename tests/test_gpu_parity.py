@@ -104,6 +104,8 @@ def test_sizes_default_tuning(q, M, dt):
     (17, 19, np.complex128, {"tile_bits": 13, "rows_per_thread": 16, "kernel_variant": 2}),
     (18, 18, np.complex64, {"tile_bits": 9, "rows_per_thread": 8, "kernel_variant": 3, "small_bits": 5}),
     (10, 17, np.complex128, {"tile_bits": 11, "kernel_variant": 2, "wg_per_cu": 1, "remap": False}),
+    (19, 20, np.complex64, {"tile_bits": 10, "xcd_swizzle": 1, "small_bits": 5}),
+    (20, 21, np.complex128, {"tile_bits": 9, "xcd_swizzle": 2, "small_bits": 5}),
 ])
 def test_many_passes(q, seed, M, dt, tuning):
     """Small tiles force many passes, outer steps and tile relabelling."""
@@ -491,3 +493,19 @@ def test_autotune_keeps_state_and_result(q):
             assert_same(s.read(), k1, "state after autotune")
             s.apply(tg, cm, stream=0)
             assert_same(s.read(), oracle.apply(M, k1, tg, cm), "apply with the tuned parameters")
+
+
+def test_copy_bytes(q):
+    """qsim_copy_bytes (the achievable-bandwidth reference of the benchmark)
+    copies every byte, for sizes that leave a partial last workgroup."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(99)
+    for nbytes in (16, 4096 + 48, (1 << 24) + 16 * 37):
+        src = torch.randint(0, 256, (nbytes,), dtype=torch.uint8, device="cuda", generator=g)
+        dst = torch.zeros(nbytes + 64, dtype=torch.uint8, device="cuda")
+        say("copy", nbytes)
+        q.copy_bytes(dst.data_ptr(), src.data_ptr(), nbytes)
+        torch.cuda.synchronize()
+        assert torch.equal(dst[:nbytes], src)
+        assert int(dst[nbytes:].count_nonzero()) == 0
