@@ -118,6 +118,7 @@ def bench_batched(reps: int = 3):
         states.append(qsim.State(c.M, "c64", buffers=(k1, torch.empty_like(k1))))
     steps = [(c.target, c.cmask) for c in circuits]
     packed = [qsim.pack_steps(t, cm) for t, cm in steps]
+    batch = qsim.PackedBatch(steps)
     updates = float(sum((1 << c.M) * c.L for c in circuits))
     torch.cuda.synchronize()
 
@@ -126,7 +127,7 @@ def bench_batched(reps: int = 3):
             st.apply_packed(pk)
 
     def batched():
-        qsim.apply_batch_packed(states, packed)
+        qsim.apply_batch_packed(states, batch)
 
     out = {}
     for name, fn in (("plain", plain), ("batched", batched)):
@@ -319,7 +320,7 @@ def main():
         del k1, other
         torch.cuda.empty_cache()
         k1 = other = None
-        modes = {"batched": bench_batched(2), "served": bench_served(args.requests, W.SERVED_RATE),
+        modes = {"batched": bench_batched(5), "served": bench_served(args.requests, W.SERVED_RATE),
                  "signed": signed}
         torch.cuda.empty_cache()
 

@@ -703,17 +703,27 @@ namespace {
 
 // ------------------------------------------------------------ batched mode
 
-// Process-wide workspace of the batched launch (one batch in flight at a
-// time; a new batch waits for the previous one to finish with its buffers).
-struct BatchWorkspace {
-    std::mutex mu;
+// Process-wide workspace of the batched launch, in two slots used in turn:
+// while one batch's kernel runs, the next batch's plan is uploaded into the
+// other slot on a side stream, ordered by events (the upload waits until
+// the slot's previous kernel is done; the kernel waits for its upload).
+struct BatchSlot {
     DevBuf ws;          // counters, items, pass and circuit descriptors, step arrays
     DevBuf rec;         // tile-map records of every pass
-    HostStage stage;
-    hipEvent_t done = nullptr;
+    HostStage stage;    // pinned staging of the upload
+    uint32_t *hdr = nullptr;          // pinned copy of the counter header, written after the kernel
+    hipEvent_t uploaded = nullptr;    // upload finished
+    hipEvent_t done = nullptr;        // kernel and header copy finished
     bool pending = false;
-    uint32_t *ctr_dev = nullptr;
-    int last_status = QSIM_OK;
+};
+
+struct BatchWorkspace {
+    std::mutex mu;
+    BatchSlot slot[2];
+    int next = 0;                     // slot of the next batch
+    hipStream_t upload = nullptr;     // side stream for plan uploads (default priority)
+    int device = -1;                  // device the streams and buffers belong to
+    int status = QSIM_OK;             // first failure since the last status query
 };
 
 BatchWorkspace &batch_ws() {
@@ -721,23 +731,26 @@ BatchWorkspace &batch_ws() {
     return w;
 }
 
-// Wait for the last batched launch and read its error flag.
-int batch_collect(BatchWorkspace &w) {
-    if (!w.pending) return w.last_status;
-    w.pending = false;
-    hipError_t e = hipEventSynchronize(w.done);
-    if (e != hipSuccess) return w.last_status = fail(QSIM_ERR_DEVICE, std::string("batch: ") + hipGetErrorString(e));
-    uint32_t hdr[kBatchCtrHeader];
-    e = hipMemcpy(hdr, w.ctr_dev, sizeof(hdr), hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return w.last_status = fail(QSIM_ERR_DEVICE, std::string("batch: ") + hipGetErrorString(e));
-    if (hdr[2]) return w.last_status = fail(QSIM_ERR_DEVICE, "batch: a dependency wait timed out; results are invalid");
-    return w.last_status = QSIM_OK;
+// Wait for a slot's launch and fold its error flag into the sticky status.
+void batch_collect(BatchWorkspace &w, BatchSlot &b) {
+    if (!b.pending) return;
+    b.pending = false;
+    hipError_t e = hipEventSynchronize(b.done);
+    int rc = QSIM_OK;
+    if (e != hipSuccess) rc = fail(QSIM_ERR_DEVICE, std::string("batch: ") + hipGetErrorString(e));
+    else if (b.hdr[2]) rc = fail(QSIM_ERR_DEVICE, "batch: a dependency wait timed out; results are invalid");
+    if (rc != QSIM_OK && w.status == QSIM_OK) w.status = rc;
 }
 
+// Wait for every batch in flight; report (and clear) the first failure.
 int batch_status() {
     BatchWorkspace &w = batch_ws();
     std::lock_guard<std::mutex> lk(w.mu);
-    return batch_collect(w);
+    batch_collect(w, w.slot[w.next ^ 1]);
+    batch_collect(w, w.slot[w.next]);
+    const int rc = w.status;
+    w.status = QSIM_OK;
+    return rc;
 }
 
 // Per-circuit host preparation (run in parallel over circuits).
@@ -766,12 +779,17 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
         t_prev = t;
     };
 
-    // 1. plan every circuit (host threads)
+    // 1. validate and plan every circuit (host threads); nothing is
+    // enqueued unless every circuit passes
     std::vector<BatchCircuitPlan> plans(n);
     auto plan_one = [&](uint32_t c) {
         qsim_state *s = states[c];
         const uint64_t L = Ls[c];
         BatchCircuitPlan &bp = plans[c];
+        if ((bp.rc = validate_steps(s->M, steps[c], L))) {
+            bp.err = g_err;
+            return;
+        }
         if (L == 0) return;
         if (s->M <= 4) {
             bp.direct = true;
@@ -904,16 +922,41 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
 
     BatchWorkspace &w = batch_ws();
     std::lock_guard<std::mutex> lk(w.mu);
-    (void)batch_collect(w);
     hipError_t e;
-    if ((e = w.ws.ensure(total)) != hipSuccess) return fail(QSIM_ERR_NOMEM, "batch workspace");
-    if (rec_words_total && (e = w.rec.ensure(rec_words_total * 4)) != hipSuccess)
-        return fail(QSIM_ERR_NOMEM, "batch tile records");
-    if ((e = w.stage.ensure(total)) != hipSuccess) return fail(QSIM_ERR_DEVICE, "batch staging");
-    if (!w.done && (e = hipEventCreateWithFlags(&w.done, hipEventDisableTiming)) != hipSuccess)
+    if (w.device != states[0]->device) {
+        // the workspace moves to this device: finish and free what it held
+        for (BatchSlot &b : w.slot) {
+            batch_collect(w, b);
+            b.ws.release();
+            b.rec.release();
+            b.stage.release();
+            if (b.hdr) (void)hipHostFree(b.hdr);
+            if (b.uploaded) (void)hipEventDestroy(b.uploaded);
+            if (b.done) (void)hipEventDestroy(b.done);
+            b = BatchSlot{};
+        }
+        if (w.upload) (void)hipStreamDestroy(w.upload);
+        w.upload = nullptr;
+        w.device = states[0]->device;
+    }
+    if (!w.upload && (e = hipStreamCreateWithFlags(&w.upload, hipStreamNonBlocking)) != hipSuccess)
+        return fail(QSIM_ERR_DEVICE, "batch upload stream");
+    BatchSlot &b = w.slot[w.next];
+    // The slot's previous batch (two launches ago) must be done with its
+    // buffers: its status is read, its device buffers are then reused.
+    batch_collect(w, b);
+    if (!b.hdr && (e = hipHostMalloc((void **)&b.hdr, kBatchCtrHeader * 4, hipHostMallocDefault)) != hipSuccess)
+        return fail(QSIM_ERR_DEVICE, "batch status buffer");
+    if (!b.uploaded && (e = hipEventCreateWithFlags(&b.uploaded, hipEventDisableTiming)) != hipSuccess)
         return fail(QSIM_ERR_DEVICE, "batch event");
-    uint8_t *dev = static_cast<uint8_t *>(w.ws.p);
-    uint32_t *rec_dev = static_cast<uint32_t *>(w.rec.p);
+    if (!b.done && (e = hipEventCreateWithFlags(&b.done, hipEventDisableTiming)) != hipSuccess)
+        return fail(QSIM_ERR_DEVICE, "batch event");
+    if ((e = b.ws.ensure(total)) != hipSuccess) return fail(QSIM_ERR_NOMEM, "batch workspace");
+    if (rec_words_total && (e = b.rec.ensure(rec_words_total * 4)) != hipSuccess)
+        return fail(QSIM_ERR_NOMEM, "batch tile records");
+    if ((e = b.stage.ensure(total)) != hipSuccess) return fail(QSIM_ERR_DEVICE, "batch staging");
+    uint8_t *dev = static_cast<uint8_t *>(b.ws.p);
+    uint32_t *rec_dev = static_cast<uint32_t *>(b.rec.p);
     // device pointers inside the descriptors
     for (size_t g = 0; g < bpass.size(); ++g) {
         const size_t cb = blob_off + pass_blob_off[g];
@@ -927,7 +970,7 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
         if (bsmall[k].direct) bsmall[k].steps_rev = reinterpret_cast<const TmStep *>(p);
         else bsmall[k].ta.inner = reinterpret_cast<const uint32_t *>(p);
     }
-    uint8_t *h = static_cast<uint8_t *>(w.stage.p);
+    uint8_t *h = static_cast<uint8_t *>(b.stage.p);
     std::memset(h, 0, ctr_bytes);
     std::memcpy(h + items_off, items.data(), items.size() * 8);
     if (!bpass.empty()) std::memcpy(h + pass_off, bpass.data(), bpass.size() * sizeof(BatchPass));
@@ -936,23 +979,32 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
         if (!plans[c].pr.blob.empty())
             std::memcpy(h + blob_off + circuit_blob_off[c], plans[c].pr.blob.data(), plans[c].pr.blob.size());
     lap("stage");
-    if ((e = hipMemcpyAsync(dev, h, total, hipMemcpyHostToDevice, st)) != hipSuccess)
+    // Upload on the side stream (after the slot's previous kernel, which
+    // the collect above has already waited for), then the kernel on the
+    // caller's stream after the upload; the counter header is copied back
+    // behind the kernel so the status can be read without another copy.
+    if ((e = hipMemcpyAsync(dev, h, total, hipMemcpyHostToDevice, w.upload)) != hipSuccess)
         return fail(QSIM_ERR_DEVICE, std::string("batch upload: ") + hipGetErrorString(e));
-    if ((e = hipEventRecord(w.stage.ev, st)) != hipSuccess) return fail(QSIM_ERR_DEVICE, "batch event");
-    w.stage.pending = true;
-    w.ctr_dev = reinterpret_cast<uint32_t *>(dev);
+    if ((e = hipEventRecord(b.stage.ev, w.upload)) != hipSuccess) return fail(QSIM_ERR_DEVICE, "batch event");
+    b.stage.pending = true;
+    if ((e = hipEventRecord(b.uploaded, w.upload)) != hipSuccess) return fail(QSIM_ERR_DEVICE, "batch event");
+    if ((e = hipStreamWaitEvent(st, b.uploaded, 0)) != hipSuccess) return fail(QSIM_ERR_DEVICE, "batch event");
+    uint32_t *ctr_dev = reinterpret_cast<uint32_t *>(dev);
     if (!items.empty()) {
         e = launch_batch(elem, tb, any_sign, reinterpret_cast<const BatchPass *>(dev + pass_off),
                          reinterpret_cast<const BatchSmall *>(dev + small_off),
-                         reinterpret_cast<const uint64_t *>(dev + items_off), (uint32_t)items.size(), w.ctr_dev,
+                         reinterpret_cast<const uint64_t *>(dev + items_off), (uint32_t)items.size(), ctr_dev,
                          n_rec_blocks, 1u << 24, st);
         if (e != hipSuccess) {
             for (uint32_t c = 0; c < n; ++c) states[c]->poisoned = true;
             return fail(QSIM_ERR_DEVICE, std::string("batch launch: ") + hipGetErrorString(e));
         }
     }
-    if ((e = hipEventRecord(w.done, st)) != hipSuccess) return fail(QSIM_ERR_DEVICE, "batch event");
-    w.pending = true;
+    if ((e = hipMemcpyAsync(b.hdr, ctr_dev, kBatchCtrHeader * 4, hipMemcpyDeviceToHost, st)) != hipSuccess)
+        return fail(QSIM_ERR_DEVICE, std::string("batch status copy: ") + hipGetErrorString(e));
+    if ((e = hipEventRecord(b.done, st)) != hipSuccess) return fail(QSIM_ERR_DEVICE, "batch event");
+    b.pending = true;
+    w.next ^= 1;
     lap("launch");
     // every circuit's result sits in the buffer its last pass wrote
     std::vector<uint32_t> flips(n, 0);
@@ -1238,14 +1290,16 @@ int qsim_apply_batch(qsim_state *const *states, const qsim_step *const *steps, c
     if (n == 0) return QSIM_OK;
     if (!states || !steps || !Ls) return fail(QSIM_ERR_INVALID, "NULL array");
     std::unordered_set<const qsim_state *> seen;
+    seen.reserve(2 * (size_t)n);
     for (uint32_t c = 0; c < n; ++c) {
         int rc = check_state(states[c]);
         if (rc) return rc;
         if (states[c]->dtype != states[0]->dtype) return fail(QSIM_ERR_INVALID, "states differ in dtype");
         if (states[c]->device != states[0]->device) return fail(QSIM_ERR_INVALID, "states differ in device");
-        if ((rc = validate_steps(states[c]->M, steps[c], Ls[c]))) return rc;
+        if (Ls[c] > 0 && !steps[c]) return fail(QSIM_ERR_INVALID, "circuit " + std::to_string(c) + ": steps is NULL");
         if (!seen.insert(states[c]).second) return fail(QSIM_ERR_INVALID, "a state appears twice in the batch");
     }
+    // (the steps themselves are validated by the planning threads)
     DeviceGuard g(states[0]->device);
     if (!g.ok) return fail(QSIM_ERR_DEVICE, "set device");
     return batch_enqueue(states, steps, Ls, n, static_cast<hipStream_t>(hip_stream));

@@ -363,14 +363,45 @@ def apply_batch(states: Sequence[State], steps: Sequence[Tuple], stream=None):
                                  ctypes.cast(ls, ctypes.c_void_p), n, ctypes.c_void_p(_stream_ptr(stream))))
 
 
-def apply_batch_packed(states: Sequence[State], packed: Sequence[np.ndarray], stream=None):
-    """apply_batch with step arrays already packed by pack_steps."""
+class PackedBatch:
+    """The step lists of a batch in one contiguous qsim_step buffer, with the
+    per-circuit pointer and length arrays qsim_apply_batch takes, so a
+    batched call marshals three arrays instead of one object per circuit.
+    steps[c] = (target, cmask) or (target, cmask, kind)."""
+
+    def __init__(self, steps: Sequence[Tuple]):
+        parts = [pack_steps(*sc) for sc in steps]
+        self.lens = np.array([len(p) for p in parts], dtype=np.uint64)
+        self.buf = np.concatenate(parts) if parts else np.zeros(0, dtype=STEP_DTYPE)
+        if len(self.buf) == 0:
+            self.buf = np.zeros(1, dtype=STEP_DTYPE)     # a valid base address
+        offsets = np.concatenate([[0], np.cumsum(self.lens)[:-1]]).astype(np.uint64) if parts else self.lens
+        self.ptrs = np.uint64(self.buf.ctypes.data) + offsets * np.uint64(STEP_DTYPE.itemsize)
+
+    def __len__(self):
+        return len(self.lens)
+
+
+def _handles(states: Sequence[State]) -> np.ndarray:
+    return np.fromiter((s._h.value for s in states), dtype=np.uint64, count=len(states))
+
+
+def apply_batch_packed(states: Sequence[State], packed, stream=None):
+    """apply_batch with the steps already packed: a PackedBatch, or a list of
+    arrays from pack_steps."""
     n = len(states)
-    hs = (ctypes.c_void_p * n)(*[s.handle.value for s in states])
-    ps = (ctypes.c_void_p * n)(*[p.ctypes.data if len(p) else None for p in packed])
-    ls = (ctypes.c_uint64 * n)(*[len(p) for p in packed])
-    _check(_lib.qsim_apply_batch(ctypes.cast(hs, ctypes.c_void_p), ctypes.cast(ps, ctypes.c_void_p),
-                                 ctypes.cast(ls, ctypes.c_void_p), n, ctypes.c_void_p(_stream_ptr(stream))))
+    if not isinstance(packed, PackedBatch):
+        hs = (ctypes.c_void_p * n)(*[s.handle.value for s in states])
+        ps = (ctypes.c_void_p * n)(*[p.ctypes.data if len(p) else None for p in packed])
+        ls = (ctypes.c_uint64 * n)(*[len(p) for p in packed])
+        _check(_lib.qsim_apply_batch(ctypes.cast(hs, ctypes.c_void_p), ctypes.cast(ps, ctypes.c_void_p),
+                                     ctypes.cast(ls, ctypes.c_void_p), n, ctypes.c_void_p(_stream_ptr(stream))))
+        return
+    if len(packed) != n:
+        raise ValueError("one step list per state")
+    hs = _handles(states)
+    _check(_lib.qsim_apply_batch(ctypes.c_void_p(hs.ctypes.data), ctypes.c_void_p(packed.ptrs.ctypes.data),
+                                 ctypes.c_void_p(packed.lens.ctypes.data), n, ctypes.c_void_p(_stream_ptr(stream))))
 
 
 def rowmap_build(M: int, target, cmask, x_dev, stream=None, kind=None):

@@ -182,3 +182,22 @@ def test_rowmap_rejects_phase_steps():
     with pytest.raises(qsim.QsimError) as ei:
         qsim.rowmap_build(8, [1], [0], 0, kind=[qsim.STEP_PHASE])
     assert ei.value.code == qsim.ERR_INVALID
+
+
+def test_packed_batch_layout():
+    """PackedBatch: circuit c's pointer addresses its own steps, packed as
+    pack_steps would pack them, with its length; empty circuits included."""
+    import ctypes
+    rng = np.random.default_rng(40)
+    steps = []
+    for i in range(30):
+        M = int(rng.integers(1, 12))
+        L = 0 if i % 7 == 3 else int(rng.integers(1, 40))
+        tg, cm = W.random_steps(rng, M, L, (0, 3))
+        steps.append((tg, cm, (rng.random(L) < 0.3).astype(np.uint8)) if i % 2 else (tg, cm))
+    pb = qsim.PackedBatch(steps)
+    assert len(pb) == 30 and pb.ptrs.dtype == np.uint64 and pb.lens.dtype == np.uint64
+    for i, sc in enumerate(steps):
+        ref = qsim.pack_steps(*sc)
+        assert int(pb.lens[i]) == len(ref)
+        assert ctypes.string_at(int(pb.ptrs[i]), 16 * len(ref)) == ref.tobytes()

@@ -509,3 +509,59 @@ def test_copy_bytes(q):
         torch.cuda.synchronize()
         assert torch.equal(dst[:nbytes], src)
         assert int(dst[nbytes:].count_nonzero()) == 0
+
+
+def test_batches_back_to_back(q):
+    """Batched launches queued one after another without waiting (the plan
+    upload of one overlaps the kernel of the previous): batch 2 applies the
+    reversed diagrams of batch 1, so every state returns to its input;
+    batch 3 applies the diagrams again and must equal the oracle."""
+    rng = np.random.default_rng(130)
+    circuits = W.batched_config(n=60, seed=131, m_range=(3, 18), l_range=(0, 160))
+    states, ins = [], []
+    for c in circuits:
+        k1 = W.gaussian_state(rng, c.M, np.complex64)
+        s = q.State(c.M, "c64")
+        s.write(k1)
+        states.append(s)
+        ins.append(k1)
+    fwd = [(c.target, c.cmask) for c in circuits]
+    rev = [(c.target[::-1].copy(), c.cmask[::-1].copy()) for c in circuits]
+    say("batches back to back")
+    q.apply_batch(states, fwd, stream=0)
+    q.apply_batch_packed(states, q.PackedBatch(rev), stream=0)
+    q.apply_batch(states, fwd, stream=0)
+    q.batch_status()
+    for c, s, k1 in zip(circuits, states, ins):
+        assert_same(s.read(), oracle.apply(c.M, k1, c.target, c.cmask), f"third batch M={c.M} L={c.L}")
+    q.apply_batch(states, rev, stream=0)
+    q.batch_status()
+    for c, s, k1 in zip(circuits, states, ins):
+        assert_same(s.read(), k1, f"fourth batch undoes the third M={c.M} L={c.L}")
+        s.close()
+
+
+def test_batch_invalid_step_runs_nothing(q):
+    """A bad step in any circuit rejects the whole batch before anything is
+    enqueued: every state keeps its contents."""
+    rng = np.random.default_rng(140)
+    circuits = W.batched_config(n=20, seed=141, m_range=(5, 16), l_range=(1, 80))
+    states, ins = [], []
+    for c in circuits:
+        k1 = W.gaussian_state(rng, c.M, np.complex64)
+        s = q.State(c.M, "c64")
+        s.write(k1)
+        states.append(s)
+        ins.append(k1)
+    steps = [(c.target, c.cmask) for c in circuits]
+    bad_t = steps[13][0].copy()
+    bad_t[-1] = circuits[13].M          # target beyond the address bits
+    steps[13] = (bad_t, steps[13][1])
+    say("batch with an invalid step")
+    with pytest.raises(q.QsimError) as ei:
+        q.apply_batch(states, steps, stream=0)
+    assert ei.value.code == q.ERR_INVALID and "circuit 13" in q.last_error()
+    q.batch_status()
+    for s, k1 in zip(states, ins):
+        assert_same(s.read(), k1, "state after a rejected batch")
+        s.close()
