@@ -195,10 +195,13 @@ int qsim_read_portion_async(const qsim_state *state, uint64_t offset,
 int qsim_apply_batch(qsim_state *const *states, const qsim_step *const *steps,
                      const uint64_t *Ls, uint32_t n, void *hip_stream);
 
-/* Wait for the last qsim_apply_batch launch of the process and report
- * whether it completed cleanly: QSIM_OK, or QSIM_ERR_DEVICE if a HIP error
- * occurred or a tile's wait for the previous pass of its circuit ran out
- * (the results of that batch are then invalid). */
+/* Wait for every qsim_apply_batch launch of the process still in flight
+ * and report whether all launches since the previous call completed
+ * cleanly: QSIM_OK, or QSIM_ERR_DEVICE if a HIP error occurred or a tile's
+ * wait for the previous pass of its circuit ran out in one of them (the
+ * results of that batch are then invalid).  Batches may be enqueued back to
+ * back without calling this in between: the library keeps two workspaces
+ * and uploads one batch's plan while the previous batch runs. */
 int qsim_batch_last_status(void);
 
 /* ---------------------------------------------------------------- serving */
