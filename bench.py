@@ -92,14 +92,20 @@ def cpu_baseline(wl, k1_host, seconds: float):
     t0 = time.perf_counter()
     oracle.apply_inplace(M, buf, tg[:1], cm[:1], threads=threads)
     t1 = time.perf_counter() - t0
-    n = int(max(1, min(len(tg) - 1, seconds / max(t1, 1e-6))))
+    n = int(max(1, min(len(tg) - 2, seconds / max(t1, 1e-6))))
     t0 = time.perf_counter()
     oracle.apply_inplace(M, buf, tg[1:1 + n], cm[1:1 + n], threads=threads)
     dt = time.perf_counter() - t0
+    # one more step on a single thread
+    t0 = time.perf_counter()
+    oracle.apply_inplace(M, buf, tg[1 + n:2 + n], cm[1 + n:2 + n], threads=1)
+    d1 = time.perf_counter() - t0
     return {"value": float((1 << M) * n / dt), "unit": "amplitude-step updates/s", "cores": threads,
             "kind": "oracle",
             "sample": f"steps 2..{n + 1} of the same {len(tg)}-step diagram on the full 2^{M}-entry "
-                      f"input (plain pair-swap loop, OpenMP over rows, {dt:.1f} s)"}
+                      f"input (plain pair-swap loop, OpenMP over rows, {dt:.1f} s)",
+            "single_thread": {"value": float((1 << M) / d1), "cores": 1,
+                              "sample": f"step {n + 2} of the same diagram on one thread ({d1:.1f} s)"}}
 
 
 def bench_batched(reps: int = 3):
@@ -316,12 +322,25 @@ def main():
         signed = {"ms_per_step": round(s_ms, 3), "passes": int(len(s_masks)),
                   "value": float(1 << M) * L / (s_ms * 1e-3), "phase_steps": int(kd.sum()),
                   "vs_unsigned": round(ms_per_step / s_ms, 4)}
+        # Blocked halves: the same kind of draws with the 500 low-target steps
+        # first and the 500 high-target steps after them.
+        tb_, cb_ = W.m32_config(blocked=True)
+        b_masks = qsim.plan_describe(M, dt, tb_, cb_, tuning)[0]
+        st.apply(tb_, cb_)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(2):
+            st.apply(tb_, cb_)
+        torch.cuda.synchronize()
+        b_ms = (time.perf_counter() - t0) / 2 * 1e3
+        blocked = {"ms_per_step": round(b_ms, 3), "passes": int(len(b_masks)),
+                   "value": float(1 << M) * L / (b_ms * 1e-3)}
         st.close()
         del k1, other
         torch.cuda.empty_cache()
         k1 = other = None
         modes = {"batched": bench_batched(5), "served": bench_served(args.requests, W.SERVED_RATE),
-                 "signed": signed}
+                 "signed": signed, "blocked_halves": blocked}
         torch.cuda.empty_cache()
 
     cpu = None

@@ -150,13 +150,17 @@ def m26_config(seed: int = SEED_M26, M: int = 26, L: int = 200) -> Steps:
     return random_steps(np.random.default_rng(seed), M, L, (0, 4))
 
 
-def m32_config(seed: int = SEED_M32, M: int = 32, L: int = 1000, n_low_bits: int = 8) -> Steps:
+def m32_config(seed: int = SEED_M32, M: int = 32, L: int = 1000, n_low_bits: int = 8,
+               blocked: bool = False) -> Steps:
     """Half the steps target bits [0, n_low_bits), the rest [n_low_bits, M),
-    interleaved in a seeded random order; 1..3 controls."""
+    interleaved in a seeded random order; 1..3 controls.  blocked=True: the
+    same draws with the low-target half first, then the high-target half."""
     rng = np.random.default_rng(seed)
     half = L // 2
     kinds = np.array([0] * half + [1] * (L - half))
     rng.shuffle(kinds)
+    if blocked:
+        kinds = np.sort(kinds, kind="stable")
     targets = [int(rng.integers(0, n_low_bits)) if k == 0 else int(rng.integers(n_low_bits, M))
                for k in kinds]
     return random_steps(rng, M, L, (1, 3), targets=targets)
