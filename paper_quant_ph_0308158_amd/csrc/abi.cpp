@@ -177,6 +177,7 @@ PlanConfig plan_config(const Tuning &t) {
     c.max_seg_steps = t.max_seg_steps;
     c.reorder = t.reorder;
     c.search = t.plan_search;
+    c.remap = t.remap;
     return c;
 }
 
@@ -432,7 +433,7 @@ int prepare_passes(uint32_t M, uint32_t elem, const std::vector<Pass> &passes,
         // tile offsets below 2^32 and, for 8-byte entries, address bit 0 in
         // the tile (entries travel in adjacent pairs).
         if (K < eb || K - eb > 10 || K > (uint32_t)kMaxTileBits || (M - K) > (uint32_t)kMaxOuterBits ||
-            (I >> 32) != 0 || (elem == 8 && !(I & 1ull)) || (elem == 16 && K > (uint32_t)kMaxTileBits - 1))
+            (elem == 8 && !(I & 1ull)) || (elem == 16 && K > (uint32_t)kMaxTileBits - 1))
             return fail(QSIM_ERR_INVALID, "planner produced a tile the kernel cannot run");
         const uint8_t *ls = lam[pi].data(), *ld = lam[pi + 1].data();
         uint8_t in_log[16] = {0}, out_log[kMaxOuterBits] = {0};
@@ -533,6 +534,8 @@ int prepare_passes(uint32_t M, uint32_t elem, const std::vector<Pass> &passes,
         const uint32_t n_inner = (uint32_t)inner.size();
         const uint32_t rec_words = 2u + (n_inner + 31u) / 32u;
         const uint64_t n_tiles = 1ull << (M - K);
+        if (n_tiles > 0x7FFFFFFFull)
+            return fail(QSIM_ERR_INVALID, "more than 2^31 - 1 tiles in a pass: raise tile_bits");
 
         Launch lm;
         lm.kind = Launch::TILEMAP;

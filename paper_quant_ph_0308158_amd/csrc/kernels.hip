@@ -634,19 +634,23 @@ __global__ void __launch_bounds__(256) k_product(T *__restrict__ out, ProductArg
         out[2 * i + 1] = im;
         return;
     }
-    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t lane = (uint32_t)(t & 63u);
-    const uint64_t base = (t >> 6) << 10;
-    if (base >= n) return;
-    const uint32_t vtop = (uint32_t)((base >> (M - 1)) & 1u);
-    T pre_re = a.q[2 * (2 * (M - 1) + vtop)], pre_im = a.q[2 * (2 * (M - 1) + vtop) + 1];
-    fold_bits(a, base, M - 1, 11, pre_re, pre_im);
-    for (uint32_t k = 0; k < 16u; ++k) {
-        const uint64_t i = base + (uint64_t)k * 64u + lane;
-        T re = pre_re, im = pre_im;
-        fold_bits(a, i, 10, 1, re, im);
-        out[2 * i] = re;
-        out[2 * i + 1] = im;
+    // grid-stride over 1024-entry blocks (the stride is a multiple of 64,
+    // so a thread keeps its lane)
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;; t += stride) {
+        const uint32_t lane = (uint32_t)(t & 63u);
+        const uint64_t base = (t >> 6) << 10;
+        if (base >= n) return;
+        const uint32_t vtop = (uint32_t)((base >> (M - 1)) & 1u);
+        T pre_re = a.q[2 * (2 * (M - 1) + vtop)], pre_im = a.q[2 * (2 * (M - 1) + vtop) + 1];
+        fold_bits(a, base, M - 1, 11, pre_re, pre_im);
+        for (uint32_t k = 0; k < 16u; ++k) {
+            const uint64_t i = base + (uint64_t)k * 64u + lane;
+            T re = pre_re, im = pre_im;
+            fold_bits(a, i, 10, 1, re, im);
+            out[2 * i] = re;
+            out[2 * i + 1] = im;
+        }
     }
 }
 
@@ -852,7 +856,7 @@ hipError_t launch_product(uint32_t elem, void *out, uint32_t M, const void *qubi
     const uint64_t n = 1ull << M;
     const uint32_t bs = 256;
     const uint64_t threads = M < 11 ? n : n / 16;
-    const uint64_t grid = (threads + bs - 1) / bs;
+    const uint64_t grid = std::min<uint64_t>((threads + bs - 1) / bs, 1ull << 22);
     if (M < 1 || M > kMaxQubits) return hipErrorInvalidValue;
     if (elem == 8) {
         ProductArgs<float> a{};

@@ -71,8 +71,15 @@ std::vector<Pass> plan_passes(uint32_t M, const uint32_t *target, const uint64_t
     if (L == 0) return passes;
     const int K = std::min<int>(cfg.tile_bits, (int)M);
     const uint64_t all = (M >= 64) ? ~0ull : ((1ull << M) - 1ull);
-    // Tile bits address entries inside a tile with 32-bit offsets.
-    const uint64_t allowed = all & 0xFFFFFFFFull;
+    // Tile bits address entries inside a tile with 32-bit offsets, so their
+    // physical positions lie below 32.  The first pass reads and the last
+    // pass writes the natural layout (physical = logical), so their tile
+    // bits are logical bits below 32; with permuted layouts between passes
+    // a middle pass's tile bits sit at the bottom of both its layouts, so
+    // any bit will do (this lets steps on bits 32 and up become inner).
+    const uint64_t low32 = all & 0xFFFFFFFFull;
+    uint64_t allowed = low32;
+    auto set_allowed = [&](bool natural) { allowed = (natural || !cfg.remap) ? low32 : all; };
     const int low = std::min<int>(std::max(cfg.low_bits, 1), K);
     const uint64_t base = (1ull << low) - 1ull;
     const int cap = std::max(cfg.max_seg_steps, 1);
@@ -269,16 +276,40 @@ std::vector<Pass> plan_passes(uint32_t M, const uint32_t *target, const uint64_t
         if (p.steps.empty()) throw std::logic_error("planner made no progress");
         return p;
     };
-    while (!pending.empty())
+    while (!pending.empty()) {
+        set_allowed(passes.empty());
         passes.push_back(passes.empty() ? next_pass(base, base)
                                         : next_pass(seed_from(passes.back().tile_mask), mid_base));
-    if ((passes.back().tile_mask & base) != base) {
-        // Re-plan the last pass's steps from the full base.
-        Pass last = passes.back();
+    }
+    if ((passes.back().tile_mask & base) != base || (passes.back().tile_mask & ~low32)) {
+        // The last pass writes the natural layout: re-plan its steps from
+        // the full base with tile bits below 32.  Should that leave a step
+        // no such tile admits (a target above bit 31 with a control among
+        // the base bits), keep the pass and end with a pass without steps
+        // that only moves the state back to the natural layout.
+        const Pass last = passes.back();
         passes.pop_back();
         for (uint32_t s : last.steps) state[s] = 0;
         pending = last.steps;
-        while (!pending.empty()) passes.push_back(next_pass(base, base));
+        set_allowed(true);
+        std::vector<Pass> redo;
+        bool ok = true;
+        while (!pending.empty() && ok) {
+            Pass p = build_pass(base);
+            if (p.steps.empty()) ok = false;
+            else redo.push_back(std::move(p));
+        }
+        if (ok) {
+            for (Pass &p : redo) passes.push_back(std::move(p));
+        } else {
+            for (uint32_t s : last.steps) state[s] = 1;
+            pending.clear();
+            passes.push_back(last);
+            Pass tail;
+            tail.tile_mask = base;
+            for (uint32_t b = 0; b < 32 && b < M && popc(tail.tile_mask) < K; ++b) tail.tile_mask |= 1ull << b;
+            passes.push_back(tail);
+        }
     }
     return passes;
 }

@@ -136,6 +136,7 @@ struct PlanConfig {
     int max_seg_steps = 1024;
     bool reorder = true;
     int search = -1;        // tile-mask hill climb per pass: 1 on, 0 off, -1 on for M >= 30
+    bool remap = true;      // permuted layouts between passes (middle tiles may use bits >= 32)
 };
 
 // Split steps into passes (see planner.cpp).

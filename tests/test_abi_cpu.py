@@ -95,7 +95,8 @@ def _check_plan(M, dtype, tg, cm, tuning, kd=None):
         need = low if p in (0, len(masks) - 1) else mid
         assert I & ((1 << need) - 1) == (1 << need) - 1, "tile must hold the low address bits"
         assert I < (1 << M)
-        assert 1 <= n <= cap
+        # only a final pass that restores the natural layout may be empty
+        assert (1 <= n or p == len(masks) - 1) and n <= cap
         for s in order[pos:pos + n]:
             t, c = int(tg[s]), int(cm[s])
             if kd is not None and kd[s] == qsim.STEP_PHASE:
@@ -201,3 +202,46 @@ def test_packed_batch_layout():
         ref = qsim.pack_steps(*sc)
         assert int(pb.lens[i]) == len(ref)
         assert ctypes.string_at(int(pb.ptrs[i]), 16 * len(ref)) == ref.tobytes()
+
+
+def _order_commutes(tg, cm, kd, order):
+    """Every pair of steps whose relative order the plan swapped commutes:
+    neither writes a bit the other reads (a NOT writes its target; reads its
+    controls, a phase step reads its target and controls)."""
+    pos = np.empty(len(order), dtype=np.int64)
+    pos[np.asarray(order, dtype=np.int64)] = np.arange(len(order))
+    kd = np.zeros(len(tg), dtype=np.uint8) if kd is None else kd
+    W_ = [0 if kd[s] else 1 << int(tg[s]) for s in range(len(tg))]
+    R_ = [int(cm[s]) | ((1 << int(tg[s])) if kd[s] else 0) for s in range(len(tg))]
+    for i in range(len(tg)):
+        for j in range(i + 1, len(tg)):
+            if pos[j] < pos[i]:
+                assert not (W_[i] & R_[j]) and not (W_[j] & R_[i]), f"steps {i} and {j} swapped but do not commute"
+
+
+@pytest.mark.parametrize("M", [33, 34, 35, 36])
+def test_planner_beyond_32_address_bits(M):
+    """Tile offsets are 32-bit: the first and last pass (natural layout) keep
+    their tile bits below bit 32, middle passes may hold higher bits (their
+    layouts put the tile at the bottom); steps on bits 32 and up still find a
+    pass, and the plan's reordering only swaps commuting steps."""
+    tg, cm = W.m32_config(M=M, seed=M)
+    kd = (np.arange(len(tg)) % 5 == 4).astype(np.uint8)
+    for kind in (None, kd):
+        masks, lens, order = _check_plan(M, "c64", tg, cm, {}, kind)
+        m = [int(x) for x in masks]
+        assert m[0] < (1 << 32) and m[-1] < (1 << 32)
+        assert any(x >= (1 << 32) for x in m[1:-1]), "no middle pass used a high bit"
+        _order_commutes(tg, cm, kind, order)
+
+
+def test_planner_high_target_with_low_control_needs_tail_pass():
+    """A step targeting bit 33 controlled by bit 0 (always in the tile) can
+    only run in a middle pass; the plan then ends with a step-free pass that
+    restores the natural layout."""
+    M = 34
+    tg = np.array([33, 3, 40 - 7], dtype=np.uint32)
+    cm = np.array([0b1, 0, 1 << 20], dtype=np.uint64)
+    masks, lens, order = _check_plan(M, "c64", tg, cm, {})
+    assert int(lens[-1]) == 0 and int(masks[-1]) < (1 << 32)
+    assert any(int(x) >> 33 & 1 for x in masks)

@@ -565,3 +565,42 @@ def test_batch_invalid_step_runs_nothing(q):
     for s, k1 in zip(states, ins):
         assert_same(s.read(), k1, "state after a rejected batch")
         s.close()
+
+
+def test_m33_sampled_beyond_2_32_rows(q):
+    """M=33 complex64 (2^33 rows, 64 GiB per buffer): row addresses and
+    outer tile bits above bit 32.  Sampled rows (including the first and
+    last) against the oracle's source rows, then the involution."""
+    import torch
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()          # 128 GiB of buffers: return what earlier tests cached
+    M = 33
+    tg, cm = W.m32_config(M=33, seed=33)
+    say("m33: generate")
+    k1_dev = W.gaussian_state_torch(M, "c64", seed=33)
+    rng = np.random.default_rng(3333)
+    rows = np.concatenate([rng.integers(0, 1 << M, size=1500, dtype=np.uint64),
+                           np.arange(32, dtype=np.uint64), (1 << M) - 1 - np.arange(32, dtype=np.uint64),
+                           (1 << 32) + np.arange(-16, 16, dtype=np.int64).astype(np.uint64)])
+    src_rows = np.array([oracle.source_index(M, tg, cm, int(i)) for i in rows], dtype=np.int64)
+    assert (src_rows >= (1 << 32)).any() and (src_rows < (1 << 32)).any()
+    expect = k1_dev.view(torch.int64)[torch.from_numpy(src_rows).cuda()].cpu().numpy()
+    b1 = torch.empty_like(k1_dev)
+    s = q.State(M, "c64", buffers=(k1_dev, b1))
+    say("m33: apply")
+    s.apply(tg, cm)
+    torch.cuda.synchronize()
+    cur = k1_dev if s.current_ptr() == k1_dev.data_ptr() else b1
+    got = cur.view(torch.int64)[torch.from_numpy(rows.astype(np.int64)).cuda()].cpu().numpy()
+    np.testing.assert_array_equal(got, expect)
+    say("m33: involution")
+    s.apply(tg[::-1].copy(), cm[::-1].copy())
+    torch.cuda.synchronize()
+    cur = k1_dev if s.current_ptr() == k1_dev.data_ptr() else b1
+    s.close()
+    del b1
+    k1_again = W.gaussian_state_torch(M, "c64", seed=33)
+    same = torch.equal(cur.view(torch.int64), k1_again.view(torch.int64))
+    del k1_again, cur, k1_dev
+    torch.cuda.empty_cache()
+    assert same
