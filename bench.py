@@ -52,6 +52,11 @@ def workload(name: str):
         return dict(name="m32_c64_L1000", M=32, dtype="c64", seed=W.SEED_M32, target=tg, cmask=cm,
                     desc=dict(controls="1-3", targets="500 in bits 0-7, 500 in bits 8-31",
                               input="unit-norm complex Gaussian"))
+    if name == "m34":
+        tg, cm = W.m32_config(M=34, seed=34)
+        return dict(name="m34_c64_L1000", M=34, dtype="c64", seed=34, target=tg, cmask=cm,
+                    desc=dict(controls="1-3", targets="500 in bits 0-7, 500 in bits 8-33",
+                              input="unit-norm complex Gaussian"))
     if name == "m26":
         tg, cm = W.m26_config()
         return dict(name="m26_c128_L200", M=26, dtype="c128", seed=W.SEED_M26, target=tg, cmask=cm,
@@ -206,7 +211,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="m32", choices=["m32", "m26", "small", "batched", "served"])
+    ap.add_argument("--workload", default="m32", choices=["m32", "m34", "m26", "small", "batched", "served"])
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--rate", type=float, default=None, help="served: arrivals per second")
     ap.add_argument("--calibrate", action="store_true", help="served: all requests arrive at once")
