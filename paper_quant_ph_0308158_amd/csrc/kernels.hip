@@ -736,7 +736,7 @@ hipError_t launch_tilemap(const TileMapArgs &a, hipStream_t st) {
 }
 
 // Resident workgroups of a kernel on the current device (for the persistent
-// grid), cached per kernel and LDS size.
+// grid), from the runtime's occupancy query.
 template <typename KernelT>
 uint64_t resident_blocks(KernelT kernel, uint32_t threads, size_t lds) {
     int dev = 0, cus = 0, per_cu = 0;
