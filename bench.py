@@ -345,6 +345,7 @@ def main():
         torch.cuda.empty_cache()
         k1 = other = None
         modes = {"batched": bench_batched(5), "served": bench_served(args.requests, W.SERVED_RATE),
+                 "served_capacity": bench_served(args.requests, W.SERVED_RATE, calibrate=True),
                  "signed": signed, "blocked_halves": blocked}
         torch.cuda.empty_cache()
 
