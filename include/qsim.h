@@ -172,9 +172,8 @@ int qsim_apply_steps_plain(qsim_state *state, const qsim_step *steps,
                            uint64_t L, void *hip_stream);
 
 /* Copy rows [offset, offset+count) of the current vector to host memory:
- * the contiguous output portions handed to post-processing (Abstract,
- * Conclusions: the state vector is produced top to bottom in continuous
- * portions).  Waits for the work last enqueued on the state.
+ * the contiguous row ranges, first row to last, in which the result is
+ * handed on to post-processing (Abstract, Conclusions).  Waits for the work last enqueued on the state.
  * QSIM_ERR_RANGE if offset + count > 2^M. */
 int qsim_read_portion(const qsim_state *state, uint64_t offset, uint64_t count,
                       void *host_dst);
@@ -212,9 +211,8 @@ int qsim_batch_last_status(void);
  * number of times) whenever a slot and arena room are free, and admitted
  * requests run concurrently, each on its own stream: requests that arrive
  * while others are on the device join them (continuous batching).  Each
- * result is read back in contiguous portions of portion_entries rows (the
- * state vector produced top to bottom in continuous portions, Abstract and
- * Conclusions) and folded into a 64-bit digest as it lands.  With fcfs = 1
+ * result is read back in contiguous ranges of portion_entries rows, first
+ * row to last (Abstract, Conclusions), and folded into a 64-bit digest as it lands.  With fcfs = 1
  * one request runs at a time in arrival order (the plain comparator). */
 typedef struct qsim_server qsim_server;
 

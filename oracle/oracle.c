@@ -73,7 +73,7 @@ static inline void swap_words(uint64_t *w, uint64_t a, uint64_t b, uint32_t nw)
 
 /*
  * Plain step-by-step update (the state is recomputed after every step,
- * Sec. 2(h) first sentence; the "basic accumulation" alternative of the
+ * Sec. 2(h) first sentence; the plain accumulation alternative of the
  * Conclusions).  For step s with target bit t and control set C, every row
  * i with bit t clear and all bits of C set is interchanged with row
  * i + 2^t (Sec. 2(d): partner offset 2^(goto-1) in 1-based numbering).
@@ -108,7 +108,7 @@ int oracle_apply(uint32_t M, uint32_t elem_bytes, void *buf,
 }
 
 /*
- * "Intelligent looping" (Sec. 2(b) end, Sec. 2(i) Summary third bullet):
+ * Looping over the interchanged rows only (Sec. 2(b) end, Sec. 2(i) Summary third bullet):
  * only the rows that are interchanged are visited.  A pair exists for every
  * assignment of the bits that are neither the target nor a control; a
  * counter over those free bits is spread into their positions, the control
@@ -204,7 +204,7 @@ uint64_t oracle_source_index(uint32_t M, const uint32_t *target,
 
 /*
  * k2 at sampled rows: out[r] = k1(x(idx[r])) for r < nsample (Sec. 2(b):
- * "k2(i) = k1(x(i))").  k1 holds 2^M entries of elem_bytes each; out holds
+ * k2(i) = k1(x(i))).  k1 holds 2^M entries of elem_bytes each; out holds
  * nsample entries.
  */
 int oracle_sample_rows(uint32_t M, uint32_t elem_bytes, const void *k1,

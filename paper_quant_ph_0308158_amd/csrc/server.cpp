@@ -7,8 +7,8 @@
 // concurrently on their own streams, so work that arrives while others are
 // on the device overlaps with them (continuous batching).  Each worker
 // enqueues the initial state, the fused apply and the read-back of the
-// result in contiguous portions (the output "in continuous portions, top to
-// bottom" of the paper's Abstract and Conclusions) into pinned buffers,
+// result in contiguous row ranges, first row to last (how the paper's
+// Abstract and Conclusions hand the result on), into pinned buffers,
 // digests every portion as it lands, then returns its memory to the arena.
 // With fcfs set the server runs one request at a time in arrival order: the
 // plain comparator.
