@@ -140,6 +140,10 @@ def bench_batched(reps: int = 3):
     def batched():
         qsim.apply_batch_packed(states, batch)
 
+    # the batch autotuner picks the tiles per queue item (states unchanged)
+    t0 = time.perf_counter()
+    tiles = qsim.batch_autotune(states, batch)
+    tune_s = time.perf_counter() - t0
     out = {}
     for name, fn in (("plain", plain), ("batched", batched)):
         fn()
@@ -155,6 +159,7 @@ def bench_batched(reps: int = 3):
         st.close()
     return {"workload": "batched_4096_M8-20_L10-500_c64", "circuits": len(circuits),
             "amplitude_step_updates": updates, "plain": out["plain"], "batched": out["batched"],
+            "autotune": {"tiles_per_item": tiles, "seconds": round(tune_s, 2)},
             "speedup_vs_plain": round(out["plain"]["ms"] / out["batched"]["ms"], 2)}
 
 

@@ -203,6 +203,25 @@ int qsim_apply_batch(qsim_state *const *states, const qsim_step *const *steps,
  * and uploads one batch's plan while the previous batch runs. */
 int qsim_batch_last_status(void);
 
+/* Tiles of one pass that a queue item of the batched kernel covers (1..256;
+ * 0 restores the default, 16).  Larger items mean fewer completion
+ * handshakes, smaller ones a shorter tail at the end of each pass.
+ * Process-wide; applies to later qsim_apply_batch calls.  QSIM_ERR_INVALID
+ * above 256. */
+int qsim_batch_set_tiles_per_item(uint32_t tiles);
+uint32_t qsim_batch_tiles_per_item(void);
+
+/* Choose the tiles per queue item for a batch by measurement: for each
+ * candidate (4, 8, 16, 32, 64) the batch is applied, then the batch of
+ * reversed diagrams, which undoes it (every step is its own inverse,
+ * Sec. 2(a)), and the pair is timed; the fastest becomes the process-wide
+ * setting and is stored to *tiles_out (may be NULL).  Arguments as for
+ * qsim_apply_batch; the states' contents are unchanged on return.
+ * Synchronous. */
+int qsim_batch_autotune(qsim_state *const *states, const qsim_step *const *steps,
+                        const uint64_t *Ls, uint32_t n, void *hip_stream,
+                        uint32_t *tiles_out);
+
 /* ---------------------------------------------------------------- serving */
 
 /* A request server: wiring diagrams submitted over time run on one device

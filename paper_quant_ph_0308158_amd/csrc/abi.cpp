@@ -722,6 +722,7 @@ struct BatchSlot {
 
 struct BatchWorkspace {
     std::mutex mu;
+    std::atomic<uint32_t> tiles_per_item{kBatchTiles};   // qsim_batch_set_tiles_per_item / qsim_batch_autotune
     BatchSlot slot[2];
     int next = 0;                     // slot of the next batch
     hipStream_t upload = nullptr;     // side stream for plan uploads (default priority)
@@ -901,13 +902,14 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
     }
     std::vector<std::vector<uint32_t>> by_level(max_level);
     for (size_t g = 0; g < bpass.size(); ++g) by_level[bpass[g].level].push_back((uint32_t)g);
+    const uint32_t tpi = batch_ws().tiles_per_item.load();
     const size_t n_small = bsmall.size();
     size_t small_next = 0;
     const size_t levels = std::max<size_t>(max_level, 1);
     for (size_t lv = 0; lv < levels; ++lv) {
         if (lv < by_level.size())
             for (uint32_t g : by_level[lv])
-                for (uint64_t t = 0; t * kBatchTiles < bpass[g].n_tiles; ++t)
+                for (uint64_t t = 0; t * tpi < bpass[g].n_tiles; ++t)
                     items.push_back(batch_item(kItemTile, g, (uint32_t)t));
         const size_t upto = n_small * (lv + 1) / levels;
         for (; small_next < upto; ++small_next) items.push_back(batch_item(kItemSmall, (uint32_t)small_next, 0));
@@ -997,7 +999,7 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
         e = launch_batch(elem, tb, any_sign, reinterpret_cast<const BatchPass *>(dev + pass_off),
                          reinterpret_cast<const BatchSmall *>(dev + small_off),
                          reinterpret_cast<const uint64_t *>(dev + items_off), (uint32_t)items.size(), ctr_dev,
-                         n_rec_blocks, 1u << 24, st);
+                         n_rec_blocks, 1u << 24, tpi, st);
         if (e != hipSuccess) {
             for (uint32_t c = 0; c < n; ++c) states[c]->poisoned = true;
             return fail(QSIM_ERR_DEVICE, std::string("batch launch: ") + hipGetErrorString(e));
@@ -1310,6 +1312,62 @@ int qsim_apply_batch(qsim_state *const *states, const qsim_step *const *steps, c
 
 int qsim_batch_last_status(void) {
     return batch_status();
+}
+
+int qsim_batch_set_tiles_per_item(uint32_t tiles) {
+    if (tiles == 0) tiles = kBatchTiles;
+    if (tiles > kBatchTilesMax) return fail(QSIM_ERR_INVALID, "tiles_per_item above 256");
+    batch_ws().tiles_per_item.store(tiles);
+    return QSIM_OK;
+}
+
+uint32_t qsim_batch_tiles_per_item(void) { return batch_ws().tiles_per_item.load(); }
+
+int qsim_batch_autotune(qsim_state *const *states, const qsim_step *const *steps, const uint64_t *Ls, uint32_t n,
+                        void *hip_stream, uint32_t *tiles_out) {
+    if (n == 0) {
+        if (tiles_out) *tiles_out = qsim_batch_tiles_per_item();
+        return QSIM_OK;
+    }
+    if (!states || !steps || !Ls) return fail(QSIM_ERR_INVALID, "NULL array");
+    // Each trial applies the batch and then the batch of reversed diagrams,
+    // which undoes it (every step is its own inverse), so the states end as
+    // they began.
+    std::vector<std::vector<qsim_step>> rev(n);
+    std::vector<const qsim_step *> rev_ptr(n);
+    for (uint32_t c = 0; c < n; ++c) {
+        if (Ls[c] > 0 && !steps[c]) return fail(QSIM_ERR_INVALID, "circuit " + std::to_string(c) + ": steps is NULL");
+        rev[c].assign(steps[c], steps[c] + Ls[c]);
+        std::reverse(rev[c].begin(), rev[c].end());
+        rev_ptr[c] = rev[c].data();
+    }
+    const uint32_t keep = qsim_batch_tiles_per_item();
+    const uint32_t cands[] = {4, 8, 16, 32, 64};
+    auto trial = [&](double *ms) {
+        const auto t0 = std::chrono::steady_clock::now();
+        int rc = qsim_apply_batch(states, steps, Ls, n, hip_stream);
+        if (!rc) rc = qsim_apply_batch(states, rev_ptr.data(), Ls, n, hip_stream);
+        if (!rc) rc = batch_status();
+        if (ms) *ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        return rc;
+    };
+    int rc = trial(nullptr);   // warm the workspace and the caches of the first candidate's shapes
+    double best_ms = 1e300;
+    uint32_t best = keep;
+    for (uint32_t c : cands) {
+        if (rc) break;
+        batch_ws().tiles_per_item.store(c);
+        double ms = 0;
+        if ((rc = trial(&ms))) break;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    }
+    batch_ws().tiles_per_item.store(rc ? keep : best);
+    if (rc) return rc;
+    if (tiles_out) *tiles_out = best;
+    return QSIM_OK;
 }
 
 int qsim_autotune(qsim_state *s, const qsim_step *steps, uint64_t L, void *hip_stream, qsim_tuning *out) {

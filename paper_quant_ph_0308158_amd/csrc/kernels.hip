@@ -524,7 +524,8 @@ template <int ELEM, bool SIGN>
 __global__ void __launch_bounds__(256) k_batch(const BatchPass *__restrict__ passes,
                                                const BatchSmall *__restrict__ smalls,
                                                const uint64_t *__restrict__ items, uint32_t n_items,
-                                               uint32_t *ctr, uint32_t n_rec_blocks, uint32_t spin_limit) {
+                                               uint32_t *ctr, uint32_t n_rec_blocks, uint32_t spin_limit,
+                                               uint32_t tiles_per_item) {
     extern __shared__ vec16 lds[];
     __shared__ uint32_t s_item;
     constexpr uint32_t VPT = Shape<ELEM, 5>::VPT;
@@ -562,11 +563,11 @@ __global__ void __launch_bounds__(256) k_batch(const BatchPass *__restrict__ pas
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
             __syncthreads();
-            // a block of up to kBatchTiles tiles of one pass, the loads of
+            // a block of up to tiles_per_item tiles of one pass, the loads of
             // each tile issued while the previous one is gathered and stored
             const TileArgs &a = bp.ta;
-            const uint64_t t0 = (uint64_t)sub * kBatchTiles;
-            const uint64_t t1 = t0 + kBatchTiles < bp.n_tiles ? t0 + kBatchTiles : bp.n_tiles;
+            const uint64_t t0 = (uint64_t)sub * tiles_per_item;
+            const uint64_t t1 = t0 + tiles_per_item < bp.n_tiles ? t0 + tiles_per_item : bp.n_tiles;
             const vec16 *src = static_cast<const vec16 *>(bp.src);
             vec16 *dst = static_cast<vec16 *>(bp.dst);
             const uint32_t off_src = thread_offset<ELEM>(a.pos_src, a.tb, tid);
@@ -833,7 +834,7 @@ hipError_t launch_plain_phase(uint32_t elem, void *buf, uint32_t M, uint64_t mas
 
 hipError_t launch_batch(uint32_t elem, uint32_t tb, bool sign, const BatchPass *passes, const BatchSmall *smalls,
                         const uint64_t *items, uint32_t n_items, uint32_t *counters, uint32_t n_rec_blocks,
-                        uint32_t spin_limit, hipStream_t st) {
+                        uint32_t spin_limit, uint32_t tiles_per_item, hipStream_t st) {
     const uint32_t threads = 1u << tb;
     const size_t lds = (size_t)elem << (tb + 5);
     if (threads > 256) return hipErrorInvalidValue;
@@ -845,7 +846,7 @@ hipError_t launch_batch(uint32_t elem, uint32_t tb, bool sign, const BatchPass *
         if (grid > n_items) grid = n_items;
         if (grid == 0) return hipSuccess;
         hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(threads), lds, st, passes, smalls, items, n_items,
-                           counters, n_rec_blocks, spin_limit);
+                           counters, n_rec_blocks, spin_limit, tiles_per_item);
         return hipGetLastError();
     };
     if (elem == 8) return sign ? go(k_batch<8, true>) : go(k_batch<8, false>);

@@ -120,7 +120,9 @@ __host__ __device__ inline uint64_t batch_item(uint32_t kind, uint32_t index, ui
 // [4 + c] finished tiles of circuit c.
 constexpr uint32_t kBatchCtrHeader = 4;
 constexpr uint32_t kBatchGroup = 4;   // queue items taken per atomic
-constexpr uint32_t kBatchTiles = 16;  // tiles of one pass per tile item (4: 24.4 ms, 8: 19.8, 16: 18.7, 32: 20.3 for the 4096-circuit batch)
+constexpr uint32_t kBatchTiles = 16;  // default tiles of one pass per tile item (4: 24.4 ms, 8: 19.8, 16: 18.7,
+                                      // 32: 20.3 for 4096 circuits of M 8..20)
+constexpr uint32_t kBatchTilesMax = 256;
 
 // Host-side plan of the fused path.
 struct Pass {
@@ -173,6 +175,6 @@ hipError_t launch_narrow(const uint64_t *in, uint32_t *out, uint64_t n, hipStrea
 hipError_t launch_gather(uint32_t elem, const void *src, void *dst, const uint32_t *x, uint64_t n, hipStream_t st);
 hipError_t launch_batch(uint32_t elem, uint32_t tb, bool sign, const BatchPass *passes, const BatchSmall *smalls,
                         const uint64_t *items, uint32_t n_items, uint32_t *counters, uint32_t n_rec_blocks,
-                        uint32_t spin_limit, hipStream_t st);
+                        uint32_t spin_limit, uint32_t tiles_per_item, hipStream_t st);
 
 }  // namespace qsim

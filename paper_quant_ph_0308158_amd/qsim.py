@@ -38,7 +38,8 @@ EXPORTS = (
     "qsim_version", "qsim_state_profile", "qsim_state_profile_read", "qsim_apply_tile_pass",
     "qsim_batch_last_status", "qsim_server_create", "qsim_server_submit", "qsim_server_drain",
     "qsim_server_request_info", "qsim_server_stats", "qsim_server_destroy", "qsim_state_set_product",
-    "qsim_rowmap_build", "qsim_rowmap_apply", "qsim_autotune",
+    "qsim_rowmap_build", "qsim_rowmap_apply", "qsim_autotune", "qsim_batch_set_tiles_per_item",
+    "qsim_batch_tiles_per_item", "qsim_batch_autotune",
 )
 
 
@@ -129,6 +130,9 @@ def _load() -> ctypes.CDLL:
         "qsim_rowmap_apply": (i32, [vp, vp, vp]),
         "qsim_autotune": (i32, [vp, vp, u64, vp, vp]),
         "qsim_state_profile_read": (i32, [vp, vp]),
+        "qsim_batch_set_tiles_per_item": (i32, [u32]),
+        "qsim_batch_tiles_per_item": (u32, []),
+        "qsim_batch_autotune": (i32, [vp, vp, vp, u32, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -411,6 +415,31 @@ def rowmap_build(M: int, target, cmask, x_dev, stream=None, kind=None):
     st = pack_steps(target, cmask, kind)
     _check(_lib.qsim_rowmap_build(M, st.ctypes.data if len(st) else None, len(st), ctypes.c_void_p(_ptr(x_dev)),
                                   ctypes.c_void_p(_stream_ptr(stream))))
+
+
+def batch_set_tiles_per_item(tiles: int):
+    """Tiles of one pass per queue item of the batched kernel (0 = default)."""
+    _check(_lib.qsim_batch_set_tiles_per_item(int(tiles)))
+
+
+def batch_tiles_per_item() -> int:
+    return int(_lib.qsim_batch_tiles_per_item())
+
+
+def batch_autotune(states: Sequence[State], steps, stream=None) -> int:
+    """Pick the tiles per queue item for this batch by measurement (the
+    states' contents are unchanged); returns the chosen value.  steps: a
+    PackedBatch or a list of (target, cmask[, kind])."""
+    n = len(states)
+    pb = steps if isinstance(steps, PackedBatch) else PackedBatch(steps)
+    if len(pb) != n:
+        raise ValueError("one step list per state")
+    hs = _handles(states)
+    out = ctypes.c_uint32(0)
+    _check(_lib.qsim_batch_autotune(ctypes.c_void_p(hs.ctypes.data), ctypes.c_void_p(pb.ptrs.ctypes.data),
+                                    ctypes.c_void_p(pb.lens.ctypes.data), n, ctypes.c_void_p(_stream_ptr(stream)),
+                                    ctypes.byref(out)))
+    return int(out.value)
 
 
 def batch_status():

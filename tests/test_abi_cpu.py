@@ -245,3 +245,18 @@ def test_planner_high_target_with_low_control_needs_tail_pass():
     masks, lens, order = _check_plan(M, "c64", tg, cm, {})
     assert int(lens[-1]) == 0 and int(masks[-1]) < (1 << 32)
     assert any(int(x) >> 33 & 1 for x in masks)
+
+
+def test_batch_tiles_per_item_setting():
+    """The batched kernel's tiles per queue item: validated, process-wide,
+    0 restores the default (host only, no device work)."""
+    default = qsim.batch_tiles_per_item()
+    assert default == 16
+    qsim.batch_set_tiles_per_item(32)
+    assert qsim.batch_tiles_per_item() == 32
+    with pytest.raises(qsim.QsimError) as ei:
+        qsim.batch_set_tiles_per_item(257)
+    assert ei.value.code == qsim.ERR_INVALID
+    assert qsim.batch_tiles_per_item() == 32
+    qsim.batch_set_tiles_per_item(0)
+    assert qsim.batch_tiles_per_item() == default

@@ -604,3 +604,33 @@ def test_m33_sampled_beyond_2_32_rows(q):
     del k1_again, cur, k1_dev
     torch.cuda.empty_cache()
     assert same
+
+
+def test_batch_autotune_keeps_states(q):
+    """qsim_batch_autotune times candidate item sizes with forward and
+    reversed batches: the states are unchanged, the choice is one of the
+    candidates and a batch with it equals the oracle."""
+    rng = np.random.default_rng(150)
+    circuits = W.batched_config(n=48, seed=151, m_range=(6, 17), l_range=(0, 120))
+    states, ins = [], []
+    for c in circuits:
+        k1 = W.gaussian_state(rng, c.M, np.complex64)
+        s = q.State(c.M, "c64")
+        s.write(k1)
+        states.append(s)
+        ins.append(k1)
+    steps = [(c.target, c.cmask) for c in circuits]
+    say("batch autotune")
+    try:
+        t = q.batch_autotune(states, steps, stream=0)
+        assert t in (4, 8, 16, 32, 64) and q.batch_tiles_per_item() == t
+        for s, k1 in zip(states, ins):
+            assert_same(s.read(), k1, "state after batch autotune")
+        q.apply_batch(states, steps, stream=0)
+        q.batch_status()
+        for c, s, k1 in zip(circuits, states, ins):
+            assert_same(s.read(), oracle.apply(c.M, k1, c.target, c.cmask), f"tuned batch M={c.M} L={c.L}")
+    finally:
+        q.batch_set_tiles_per_item(0)
+        for s in states:
+            s.close()
