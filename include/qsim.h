@@ -321,10 +321,18 @@ typedef struct {
     uint32_t rows_per_thread; /* tile rows per thread of the fused pass:
                               8, 16 or 32 (threads per tile = 2^tile_bits /
                               rows_per_thread, at most 1024)               */
-    uint32_t plan_search;  /* 1 = off, 2 = on: after the greedy scan builds a
-                              pass, swap single tile bits for outside bits
-                              while that admits more pending steps (fewer
-                              passes, more host time); 0 = on for M >= 30 */
+    uint32_t plan_search;  /* 1 = off, 2 = climb: after the greedy scan
+                              builds a pass, swap single tile bits for
+                              outside bits while that admits more pending
+                              steps (fewer passes, more host time); 3 =
+                              climb + beam search over whole plans (several
+                              candidate masks per pass, the plan with the
+                              fewest passes, then the fewest tile pairs that
+                              share less than a 128-byte line; tens of ms of
+                              host time on up to 16 threads at M = 32,
+                              L = 1000);
+                              0 = climb + beam for M >= 30 (climb alone for
+                              circuits of a batch)                         */
     uint32_t xcd_swizzle;  /* 1 = off, 2 = on (default): the one-tile-per-
                               workgroup kernel maps 64 consecutive tiles to
                               one XCD (workgroups are dealt to the 8 XCDs in

@@ -101,7 +101,7 @@ struct Tuning {
     int mid_low_bits;     // forced low bits of the passes in between
     int min_overlap;      // tile bits shared by consecutive passes
     uint32_t rows_eb;     // log2 of the tile rows each thread owns
-    int plan_search;      // -1 = by size, 0 = off, 1 = on
+    int plan_search;      // -1 = by size, 0 = off, 1 = climb, 2 = climb + beam search
     bool xcd_swizzle;     // consecutive tiles on one XCD (one-tile-per-workgroup kernel)
 };
 
@@ -144,8 +144,8 @@ int tuning_from(const qsim_tuning *in, uint32_t elem, Tuning *out) {
             t.rows_eb = (uint32_t)__builtin_ctz(in->rows_per_thread);
         }
         if (in->plan_search) {
-            if (in->plan_search > 2) return fail(QSIM_ERR_INVALID, "plan_search out of range");
-            t.plan_search = in->plan_search == 2 ? 1 : 0;
+            if (in->plan_search > 3) return fail(QSIM_ERR_INVALID, "plan_search out of range");
+            t.plan_search = (int)in->plan_search - 1;
         }
         if (in->xcd_swizzle) {
             if (in->xcd_swizzle > 2) return fail(QSIM_ERR_INVALID, "xcd_swizzle out of range");
@@ -168,8 +168,9 @@ int tuning_from(const qsim_tuning *in, uint32_t elem, Tuning *out) {
     return QSIM_OK;
 }
 
-PlanConfig plan_config(const Tuning &t) {
+PlanConfig plan_config(const Tuning &t, uint32_t elem) {
     PlanConfig c;
+    c.line_bits = elem == 8 ? 4 : 3;   // 128-byte lines
     c.tile_bits = t.tile_bits;
     c.low_bits = t.low_bits;
     c.mid_low_bits = t.remap ? t.mid_low_bits : t.low_bits;
@@ -592,7 +593,7 @@ int prepare(qsim_state *s, const qsim_step *steps, uint64_t L, Prepared &pr) {
     const StepLists sl = split_steps(steps, L);
     std::vector<Pass> passes;
     try {
-        passes = plan_passes(M, sl.tg.data(), sl.cm.data(), sl.kd.data(), L, plan_config(s->tune));
+        passes = plan_passes(M, sl.tg.data(), sl.cm.data(), sl.kd.data(), L, plan_config(s->tune, s->elem));
     } catch (const std::exception &e) {
         return fail(QSIM_ERR_INVALID, std::string("planner: ") + e.what());
     }
@@ -803,10 +804,12 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
             prepare_small(s->M, elem, steps[c], L, bp.pr);
         } else {
             const StepLists sl = split_steps(steps[c], L);
-            PlanConfig pc = plan_config(s->tune);
+            PlanConfig pc = plan_config(s->tune, elem);
             pc.tile_bits = (int)Kb;
             pc.low_bits = std::min(pc.low_bits, (int)Kb);
             pc.mid_low_bits = std::min(pc.mid_low_bits, pc.low_bits);
+            pc.threads = 1;   // circuits are already planned on several threads
+            if (pc.search < 0 && s->M >= 30) pc.search = 1;   // batch planning: the climb alone
             try {
                 std::vector<Pass> passes = plan_passes(s->M, sl.tg.data(), sl.cm.data(), sl.kd.data(), L, pc);
                 bp.rc = prepare_passes(s->M, elem, passes, sl.tg.data(), sl.cm.data(), sl.kd.data(),
@@ -1390,7 +1393,7 @@ int qsim_autotune(qsim_state *s, const qsim_step *steps, uint64_t L, void *hip_s
         out->mid_low_bits = (uint32_t)t.mid_low_bits;
         out->min_overlap = (uint32_t)t.min_overlap;
         out->rows_per_thread = 1u << t.rows_eb;
-        out->plan_search = t.plan_search < 0 ? 0u : (t.plan_search ? 2u : 1u);
+        out->plan_search = t.plan_search < 0 ? 0u : (uint32_t)t.plan_search + 1u;
         out->xcd_swizzle = t.xcd_swizzle ? 2u : 1u;
     };
     if (L == 0 || (int)s->M <= s->tune.small_bits) {   // one launch: nothing to choose
@@ -1472,7 +1475,7 @@ int qsim_plan_describe(uint32_t M, qsim_dtype dtype, const qsim_step *steps, uin
     const StepLists sl = split_steps(steps, L);
     std::vector<Pass> passes;
     try {
-        passes = plan_passes(M, sl.tg.data(), sl.cm.data(), sl.kd.data(), L, plan_config(t));
+        passes = plan_passes(M, sl.tg.data(), sl.cm.data(), sl.kd.data(), L, plan_config(t, elem));
     } catch (const std::exception &e) {
         return fail(QSIM_ERR_INVALID, std::string("planner: ") + e.what());
     }

@@ -137,8 +137,11 @@ struct PlanConfig {
     int min_overlap = 0;    // tile bits a middle pass shares with the previous one
     int max_seg_steps = 1024;
     bool reorder = true;
-    int search = -1;        // tile-mask hill climb per pass: 1 on, 0 off, -1 on for M >= 30
+    int search = -1;        // tile-mask search: 0 off, 1 hill climb per pass, 2 climb + beam
+                            // search over whole plans, -1 climb + beam for M >= 30
     bool remap = true;      // permuted layouts between passes (middle tiles may use bits >= 32)
+    int threads = 0;        // host threads of the beam search (0 = hardware threads, at most 16)
+    int line_bits = 4;      // address bits a 128-byte line spans (4: 8-byte entries, 3: 16-byte)
 };
 
 // Split steps into passes (see planner.cpp).

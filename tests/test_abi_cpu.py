@@ -56,6 +56,8 @@ def test_invalid_m_and_dtype():
         qsim.plan_describe(qsim.MAX_M + 1, "c64", [], [])
     with pytest.raises(qsim.QsimError):
         qsim.plan_describe(8, "c64", [0], [0], tuning={"tile_bits": 20})
+    with pytest.raises(qsim.QsimError):
+        qsim.plan_describe(8, "c64", [0], [0], tuning={"plan_search": 4})
 
 
 def test_unknown_step_kind_rejected():
@@ -118,6 +120,11 @@ def _check_plan(M, dtype, tg, cm, tuning, kd=None):
     (8, 16, "c128", {"tile_bits": 8, "max_seg_steps": 9, "plan_search": 2}),
     (9, 16, "c64", {"tile_bits": 8, "reorder": False, "plan_search": 2}),
     (10, 13, "c64", {"tile_bits": 5, "low_bits": 1, "min_overlap": 5, "plan_search": 2}),
+    (11, 14, "c64", {"tile_bits": 6, "low_bits": 2, "plan_search": 3}),
+    (12, 16, "c128", {"tile_bits": 8, "max_seg_steps": 9, "plan_search": 3}),
+    (13, 16, "c64", {"tile_bits": 8, "reorder": False, "plan_search": 3}),
+    (14, 13, "c64", {"tile_bits": 5, "low_bits": 1, "plan_search": 3}),
+    (15, 18, "c128", {"tile_bits": 8, "mid_low_bits": 1, "plan_search": 3}),
 ])
 def test_planner_reorder_is_exact(seed, M, dtype, tuning):
     """The planner's execution order has the same product as the original
@@ -142,8 +149,56 @@ def test_planner_on_benchmark_workloads():
     # scan's steps in each pass; on this workload that saves passes.
     off, _, _ = _check_plan(32, "c64", tg, cm, {"plan_search": 1})
     assert len(masks) <= len(off)
+    climb, _, _ = _check_plan(32, "c64", tg, cm, {"plan_search": 2})
+    assert len(climb) <= len(off)
+    beam, _, order = _check_plan(32, "c64", tg, cm, {"plan_search": 3})
+    assert len(beam) < len(climb)
     tg, cm = W.m26_config()
     _check_plan(26, "c128", tg, cm, {})
+
+
+@pytest.mark.parametrize("seed,M,tile_bits,dtype", [
+    (30, 14, 6, "c64"), (31, 20, 8, "c64"), (30, 18, 8, "c128"), (38, 14, 6, "c64"), (36, 18, 8, "c128"),
+])
+def test_beam_search_saves_passes(seed, M, tile_bits, dtype):
+    """The beam search over whole plans (plan_search 3) finds plans with
+    fewer passes than a climb per pass on these diagrams; its plans are
+    valid, exact (oracle on address tags, the planner's order against the
+    original) and the same on every call (seeded draws, any thread count)."""
+    rng = np.random.default_rng(seed)
+    tg, cm = W.random_steps(rng, M, 150, (0, 3))
+    climb, _, _ = _check_plan(M, dtype, tg, cm, {"tile_bits": tile_bits, "plan_search": 2})
+    masks, lens, order = _check_plan(M, dtype, tg, cm, {"tile_bits": tile_bits, "plan_search": 3})
+    assert len(masks) < len(climb)
+    k1 = W.tag_state(M)
+    assert oracle.apply(M, k1, tg, cm).tobytes() == oracle.apply(M, k1, tg[order], cm[order]).tobytes()
+    again = qsim.plan_describe(M, dtype, tg, cm, {"tile_bits": tile_bits, "plan_search": 3})
+    assert again[0].tolist() == masks.tolist() and again[2].tolist() == order.tolist()
+
+
+def test_beam_search_with_phase_steps():
+    rng = np.random.default_rng(25)
+    M = 16
+    tg, cm = W.random_steps(rng, M, 200, (0, 3))
+    kd = (rng.random(200) < 0.3).astype(np.uint8)
+    masks, lens, order = _check_plan(M, "c64", tg, cm, {"tile_bits": 7, "plan_search": 3}, kd)
+    k1 = (np.arange(1 << M) + 1j * np.arange(1 << M)[::-1]).astype(np.complex128)
+    a = oracle.apply(M, k1, tg, cm, kind=kd)
+    b = oracle.apply(M, k1, tg[order], cm[order], kind=kd[order])
+    assert a.tobytes() == b.tobytes()
+
+
+def test_beam_search_beyond_32_address_bits():
+    """At M = 36 middle passes may hold bits 32 and up; the beam's plans
+    still start and end with tiles below bit 32 holding the low bits, and
+    reorder only commuting steps."""
+    tg, cm = W.m32_config(M=36, seed=36)
+    masks, lens, order = _check_plan(36, "c64", tg, cm, {"plan_search": 3})
+    m = [int(x) for x in masks]
+    assert m[0] < (1 << 32) and m[-1] < (1 << 32)
+    _order_commutes(tg, cm, None, order)
+    climb = qsim.plan_describe(36, "c64", tg, cm, {"plan_search": 2})[0]
+    assert len(m) <= len(climb)
 
 
 def test_planner_same_target_run_is_one_pass():

@@ -106,6 +106,9 @@ def test_sizes_default_tuning(q, M, dt):
     (10, 17, np.complex128, {"tile_bits": 11, "kernel_variant": 2, "wg_per_cu": 1, "remap": False}),
     (19, 20, np.complex64, {"tile_bits": 10, "xcd_swizzle": 1, "small_bits": 5}),
     (20, 21, np.complex128, {"tile_bits": 9, "xcd_swizzle": 2, "small_bits": 5}),
+    (21, 20, np.complex64, {"tile_bits": 8, "plan_search": 3, "small_bits": 5}),
+    (22, 18, np.complex128, {"tile_bits": 8, "plan_search": 3, "reorder": False, "small_bits": 5}),
+    (23, 22, np.complex64, {"tile_bits": 10, "plan_search": 3, "mid_low_bits": 1}),
 ])
 def test_many_passes(q, seed, M, dt, tuning):
     """Small tiles force many passes, outer steps and tile relabelling."""

@@ -101,6 +101,7 @@ def test_signed_sizes_default_tuning(q, M, dt):
     (9, 19, np.complex128, {"tile_bits": 13, "rows_per_thread": 16, "kernel_variant": 2}),
     (10, 18, np.complex64, {"tile_bits": 9, "rows_per_thread": 8, "kernel_variant": 3, "small_bits": 5}),
     (11, 20, np.complex64, {"tile_bits": 10, "plan_search": 2, "small_bits": 5}),
+    (12, 19, np.complex128, {"tile_bits": 8, "plan_search": 3, "small_bits": 5}),
 ])
 def test_signed_many_passes(q, seed, M, dt, tuning):
     """Small tiles force phase steps with bits on both sides of the tile
