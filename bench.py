@@ -345,13 +345,43 @@ def main():
         b_ms = (time.perf_counter() - t0) / 2 * 1e3
         blocked = {"ms_per_step": round(b_ms, 3), "passes": int(len(b_masks)),
                    "value": float(1 << M) * L / (b_ms * 1e-3)}
+        # Product-state input (Appendix 1): the product kernel and then the
+        # diagram, against the input formed inside the first pass.
+        qq = W.unit_qubits(M, np.complex64 if dt == "c64" else np.complex128, seed=wl["seed"] + 1)
+
+        def timed(fn, reps=2):
+            fn()
+            torch.cuda.synchronize()
+            st.profile(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / reps * 1e3
+            p = st.profile_read()
+            st.profile(False)
+            return ms, p
+
+        def unfused():
+            st.set_product(qq)
+            st.apply(tg, cm)
+
+        u_ms, _ = timed(unfused)
+        f_ms, fp = timed(lambda: st.apply_product(qq, tg, cm))
+        first = fp["other_ms"] / fp["other_launches"] if fp["other_launches"] else None
+        product = {"unfused_ms": round(u_ms, 3), "fused_ms": round(f_ms, 3),
+                   "speedup": round(u_ms / f_ms, 4), "passes": int(len(masks)),
+                   "first_pass_ms": round(first, 3) if first else None,
+                   "first_pass_write_GBps": round(nbytes / (first * 1e-3) / 1e9, 1) if first else None,
+                   "value": float(1 << M) * L / (f_ms * 1e-3)}
         st.close()
         del k1, other
         torch.cuda.empty_cache()
         k1 = other = None
         modes = {"batched": bench_batched(5), "served": bench_served(args.requests, W.SERVED_RATE),
                  "served_capacity": bench_served(args.requests, W.SERVED_RATE, calibrate=True),
-                 "signed": signed, "blocked_halves": blocked}
+                 "signed": signed, "blocked_halves": blocked, "product_input": product}
         torch.cuda.empty_cache()
 
     cpu = None

@@ -129,11 +129,27 @@ int qsim_write_portion(qsim_state *state, uint64_t offset, uint64_t count,
  * product is taken from q_M down to q_1 in the entries' precision (float
  * for QSIM_C64, double for QSIM_C128), each complex product formed as
  * (ac - bd) + (ad + bc)i with every operation rounded separately, so the
- * result does not depend on the device.  `qubits` (host memory, read
+ * result does not depend on the device (except the payload and sign of a
+ * NaN that a product makes, which IEEE 754 leaves to the implementation).  `qubits` (host memory, read
  * before the call returns) holds 2M complex numbers of the entry type:
  * q_b(v) at index 2(b-1) + v.  Enqueued on hip_stream; one write of the
  * state, no read. */
 int qsim_state_set_product(qsim_state *state, const void *qubits, void *hip_stream);
+
+/* Apply the wiring diagram to the product state q_M (x) ... (x) q_1
+ * (Appendix 1: the input calculated on the fly): current <- U_L ... U_1 k1
+ * with k1 the vector qsim_state_set_product would write, whatever the
+ * current vector holds.  The result is bit-identical to
+ * qsim_state_set_product followed by qsim_apply_steps.  When the plan
+ * starts with a tile pass of the one-tile-per-workgroup kernel with 32 rows
+ * per thread (states above the single-workgroup size with the default
+ * rows_per_thread), that pass forms each source tile from the qubits in LDS
+ * and never reads the state: the input is neither written nor read in HBM.
+ * Otherwise the product kernel runs first.  `qubits` as for
+ * qsim_state_set_product; steps, L, stream and errors as for
+ * qsim_apply_steps (L == 0 sets the product state). */
+int qsim_apply_steps_product(qsim_state *state, const void *qubits, const qsim_step *steps,
+                             uint64_t L, void *hip_stream);
 
 /* Apply the wiring diagram: current <- U_L ... U_1 current, with steps[0]
  * acting first (Sec. 2(a), 2(h)).  `steps` is caller-owned and is read

@@ -304,6 +304,9 @@ struct Launch {
     uint64_t n_tiles = 0;
     TileArgs ta{};
     TileMapArgs tm{};
+    bool product = false;    // TILE: form the source tile from qubits (first pass only)
+    size_t q_off = 0;        // byte offset of the qubits in the blob
+    ProductTileArgs pa{};
 };
 
 struct Prepared {
@@ -663,7 +666,9 @@ int enqueue(qsim_state *s, Prepared &pr, hipStream_t st) {
         void *dst = s->buf[s->cur ^ 1];
         hipEvent_t ev_a = nullptr;
         if ((e = prof_begin(s, st, &ev_a)) != hipSuccess) return device_fail(s, e, "profiling event");
-        const int kind = l.kind == Launch::TILE ? 0 : (l.kind == Launch::TILEMAP ? 1 : 2);
+        // The product-input pass counts as "other": it writes the state and
+        // reads nothing, unlike the tile passes whose bytes are summed.
+        const int kind = l.kind == Launch::TILE && !l.product ? 0 : (l.kind == Launch::TILEMAP ? 1 : 2);
         switch (l.kind) {
             case Launch::DIRECT:
                 e = launch_direct(s->elem, src, dst, n, reinterpret_cast<const TmStep *>(dev + l.steps_off), l.n, st);
@@ -683,7 +688,12 @@ int enqueue(qsim_state *s, Prepared &pr, hipStream_t st) {
             case Launch::TILE:
                 l.ta.inner = reinterpret_cast<const uint32_t *>(dev + l.inner_off);
                 l.ta.rec = static_cast<const uint32_t *>(s->rec.p);
-                e = launch_tile(s->elem, src, dst, l.n_tiles, l.ta, s->tune.variant, s->tune.wg_per_cu, st);
+                if (l.product) {
+                    l.pa.q = dev + l.q_off;
+                    e = launch_tile_product(s->elem, dst, l.n_tiles, l.ta, l.pa, st);
+                } else {
+                    e = launch_tile(s->elem, src, dst, l.n_tiles, l.ta, s->tune.variant, s->tune.wg_per_cu, st);
+                }
                 s->cur ^= 1;
                 break;
         }
@@ -1210,6 +1220,83 @@ int qsim_apply_steps(qsim_state *s, const qsim_step *steps, uint64_t L, void *hi
     DeviceGuard g(s->device);
     if (!g.ok) return device_fail(s, hipErrorInvalidDevice, "set device");
     return enqueue(s, pr, static_cast<hipStream_t>(hip_stream));
+}
+
+namespace {
+
+// Turn the first tile pass of `pr` into one that forms its source tile from
+// the qubits.  That pass reads the natural layout, so tile-index bit k is
+// logical address bit pos_src[k].  Returns false if the plan does not start
+// with a tile pass the product kernel runs (one tile per workgroup, 32 rows
+// per thread, at most 512 threads).
+bool make_product_pass(Prepared &pr, uint32_t M, uint32_t elem, const void *qubits) {
+    if (pr.launches.size() < 2 || pr.launches[0].kind != Launch::TILEMAP || pr.launches[1].kind != Launch::TILE)
+        return false;
+    Launch &l = pr.launches[1];
+    const uint32_t tb = l.ta.tb, K = tb + l.ta.eb;
+    if (l.ta.eb != 5 || tb > 9 || K > 16) return false;
+    ProductTileArgs pa{};
+    pa.M = M;
+    uint32_t k_of[64];
+    uint64_t I = 0;
+    for (uint32_t k = 0; k < K; ++k) {
+        I |= 1ull << l.ta.pos_src[k];
+        k_of[l.ta.pos_src[k]] = k;
+    }
+    for (uint32_t b = 0, i = 0; b < M; ++b)
+        if ((I >> b) & 1ull) {
+            pa.bit[i] = (uint8_t)b;
+            pa.tix[i] = (uint8_t)k_of[b];
+            ++i;
+        }
+    // LDS slot swizzle: the shift that spreads the writes of a wave (the
+    // 64 lanes at one entry) most evenly over the banks (slots mod 32 for
+    // 8-byte entries, mod 16 for 16-byte ones, per 32 or 16 lanes).
+    const uint32_t group = elem == 8 ? 32u : 16u;
+    uint32_t best_swz = 5, best_cost = ~0u;
+    for (uint32_t swz = 5; swz + 5 <= std::max<uint32_t>(K, 10u); ++swz) {
+        uint32_t cost = 0;
+        const uint32_t lanes = std::min<uint32_t>(64u, 1u << tb);
+        for (uint32_t g0 = 0; g0 < lanes; g0 += group) {
+            uint32_t count[32] = {0}, worst = 0;
+            for (uint32_t t = g0; t < std::min(g0 + group, lanes); ++t) {
+                uint32_t j = 0;
+                for (uint32_t i = 0; i < tb; ++i)
+                    if ((t >> i) & 1u) j |= 1u << pa.tix[5 + i];
+                const uint32_t slot = j ^ ((j >> swz) & 31u);
+                worst = std::max(worst, ++count[slot % group]);
+            }
+            cost += worst;
+        }
+        if (cost < best_cost) {
+            best_cost = cost;
+            best_swz = swz;
+        }
+    }
+    l.ta.swz = best_swz;
+    l.pa = pa;
+    l.product = true;
+    l.q_off = blob_push(pr.blob, qubits, (size_t)4 * M * (elem / 2));
+    return true;
+}
+
+}  // namespace
+
+int qsim_apply_steps_product(qsim_state *s, const void *qubits, const qsim_step *steps, uint64_t L,
+                             void *hip_stream) {
+    int rc = check_state(s);
+    if (rc) return rc;
+    if (!qubits) return fail(QSIM_ERR_INVALID, "qubits is NULL");
+    if ((rc = validate_steps(s->M, steps, L))) return rc;
+    Prepared pr;
+    if (L > 0 && (rc = prepare(s, steps, L, pr))) return rc;
+    DeviceGuard g(s->device);
+    if (!g.ok) return device_fail(s, hipErrorInvalidDevice, "set device");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if (L > 0 && make_product_pass(pr, s->M, s->elem, qubits)) return enqueue(s, pr, st);
+    // Small states and plans that start otherwise: the product kernel, then the diagram.
+    if ((rc = qsim_state_set_product(s, qubits, hip_stream))) return rc;
+    return L > 0 ? enqueue(s, pr, st) : QSIM_OK;
 }
 
 int qsim_apply_tile_pass(qsim_state *s, uint64_t tile_mask, const qsim_step *steps, uint64_t L, void *hip_stream) {

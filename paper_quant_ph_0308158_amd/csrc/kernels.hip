@@ -26,6 +26,7 @@
 // One pass therefore costs one read and one write of the state.
 #include <algorithm>
 #include <cstring>
+#include <type_traits>
 
 #include "qsim_internal.h"
 
@@ -207,7 +208,14 @@ __device__ __forceinline__ uint32_t sign_word(uint32_t v) { return (v >> kSignPl
 // kSignPlane of each source index says whether the entry is negated: both
 // its parts get their sign bit flipped.  SIGN is a template parameter so
 // that passes without phase steps run code with no trace of it.
-template <int ELEM, int EB, bool SIGN>
+// With SWZ the tile was staged with tile index j in LDS slot
+// j ^ ((j >> a.swz) & 31) (the product-input pass).
+template <bool SWZ>
+__device__ __forceinline__ uint32_t lds_slot(uint32_t j, uint32_t swz) {
+    return SWZ ? j ^ ((j >> swz) & 31u) : j;
+}
+
+template <int ELEM, int EB, bool SIGN, bool SWZ = false>
 __device__ __forceinline__ void tile_emit(const uint32_t (&w)[kPlanes], vec16 *__restrict__ dst, uint64_t dst_base,
                                           const TileArgs &a, const vec16 *lds) {
     constexpr uint32_t VPT = Shape<ELEM, EB>::VPT;
@@ -219,8 +227,8 @@ __device__ __forceinline__ void tile_emit(const uint32_t (&w)[kPlanes], vec16 *_
 #pragma unroll
             for (uint32_t r = 0; r < VPT; ++r) {
                 const uint32_t v0 = src_of(w, 2u * r), v1 = src_of(w, 2u * r + 1u);
-                const uint2 e0 = l2[v0 & kIndex];
-                const uint2 e1 = l2[v1 & kIndex];
+                const uint2 e0 = l2[lds_slot<SWZ>(v0 & kIndex, a.swz)];
+                const uint2 e1 = l2[lds_slot<SWZ>(v1 & kIndex, a.swz)];
                 const uint32_t m0 = sign_word(v0), m1 = sign_word(v1);
                 st_nt(dst + (dst_base + a.off_r_dst[r]) / EPV, make_uint4(e0.x ^ m0, e0.y ^ m0, e1.x ^ m1, e1.y ^ m1));
             }
@@ -228,7 +236,7 @@ __device__ __forceinline__ void tile_emit(const uint32_t (&w)[kPlanes], vec16 *_
 #pragma unroll
             for (uint32_t r = 0; r < VPT; ++r) {
                 const uint32_t v0 = src_of(w, r);
-                const vec16 e0 = lds[v0 & kIndex];
+                const vec16 e0 = lds[lds_slot<SWZ>(v0 & kIndex, a.swz)];
                 const uint32_t m0 = sign_word(v0);
                 st_nt(dst + (dst_base + a.off_r_dst[r]) / EPV, make_uint4(e0.x, e0.y ^ m0, e0.z, e0.w ^ m0));
             }
@@ -239,14 +247,14 @@ __device__ __forceinline__ void tile_emit(const uint32_t (&w)[kPlanes], vec16 *_
         const uint2 *l2 = reinterpret_cast<const uint2 *>(lds);
 #pragma unroll
         for (uint32_t r = 0; r < VPT; ++r) {
-            const uint2 e0 = l2[src_of(w, 2u * r)];
-            const uint2 e1 = l2[src_of(w, 2u * r + 1u)];
+            const uint2 e0 = l2[lds_slot<SWZ>(src_of(w, 2u * r), a.swz)];
+            const uint2 e1 = l2[lds_slot<SWZ>(src_of(w, 2u * r + 1u), a.swz)];
             st_nt(dst + (dst_base + a.off_r_dst[r]) / EPV, make_uint4(e0.x, e0.y, e1.x, e1.y));
         }
     } else {
 #pragma unroll
         for (uint32_t r = 0; r < VPT; ++r) {
-            const vec16 e0 = lds[src_of(w, r)];
+            const vec16 e0 = lds[lds_slot<SWZ>(src_of(w, r), a.swz)];
             st_nt(dst + (dst_base + a.off_r_dst[r]) / EPV, e0);
         }
     }
@@ -655,6 +663,102 @@ __global__ void __launch_bounds__(256) k_product(T *__restrict__ out, ProductArg
     }
 }
 
+// First pass of a diagram applied to q_M (x) ... (x) q_1: each workgroup
+// forms its source tile from the qubits in LDS (no HBM read), then walks,
+// gathers and stores like k_tile.  Thread t forms the 32 entries whose five
+// lowest tile bits run over all values and whose other tile bits are the
+// bits of t: their fold from q_M down shares every factor above the fifth
+// lowest tile bit, so a thread folds those once and then splits its partial
+// product at each of the five bits (2 + 4 + ... + 32 products), multiplying
+// all partials by the factors of the outside bits in between.  Every entry
+// still gets its factors in the order q_M, ..., q_1, each product rounded
+// as in k_product, so the tile holds exactly the values k_product writes.
+// Entries go to LDS slot j ^ ((j >> a.swz) & 31) of their tile index j: the
+// 64 lanes of a wave then write different banks (the host picks swz).
+template <typename T>
+__device__ __forceinline__ void product_source_tile(vec16 *lds, uint64_t src_base, const ProductTileArgs &pa,
+                                                    uint32_t tb, uint32_t swz) {
+    const T *q = static_cast<const T *>(pa.q);
+    const uint32_t t = threadIdx.x;
+    uint64_t addr = src_base;   // logical address with the five lowest tile bits clear
+    uint32_t jt = 0;
+    for (uint32_t i = 0; i < tb; ++i) {
+        const uint32_t ti = (t >> i) & 1u;
+        addr |= (uint64_t)ti << pa.bit[5 + i];
+        jt |= ti << pa.tix[5 + i];
+    }
+    // Factors are read at addresses that are the same for every lane (both
+    // values of a bit, then a per-lane select): scalar loads, not a chain of
+    // vector loads.
+    int lv = (int)pa.M - 1;
+    bool hi = (addr >> lv) & 1u;
+    T re = hi ? q[4 * lv + 2] : q[4 * lv], im = hi ? q[4 * lv + 3] : q[4 * lv + 1];
+#pragma unroll 4
+    for (--lv; lv > (int)pa.bit[4]; --lv) {
+        const T c0 = q[4 * lv], d0 = q[4 * lv + 1], c1 = q[4 * lv + 2], d1 = q[4 * lv + 3];
+        hi = (addr >> lv) & 1u;
+        cmul(re, im, hi ? c1 : c0, hi ? d1 : d0);
+    }
+    // Partial k covers the entries whose tile bits i..4 read k (bit 4 highest).
+    T pr[32], pi[32];
+    pr[0] = re;
+    pi[0] = im;
+#pragma unroll
+    for (int i = 4; i >= 0; --i) {
+        const int n = 1 << (4 - i);
+        const uint32_t b = pa.bit[i];
+        const T c0 = q[4 * b], d0 = q[4 * b + 1], c1 = q[4 * b + 2], d1 = q[4 * b + 3];
+#pragma unroll
+        for (int k = n - 1; k >= 0; --k) {
+            T r0 = pr[k], i0 = pi[k], r1 = pr[k], i1 = pi[k];
+            cmul(r0, i0, c0, d0);
+            cmul(r1, i1, c1, d1);
+            pr[2 * k] = r0;
+            pi[2 * k] = i0;
+            pr[2 * k + 1] = r1;
+            pi[2 * k + 1] = i1;
+        }
+        const int lo = i > 0 ? (int)pa.bit[i - 1] + 1 : 0;
+        for (int l = (int)b - 1; l >= lo; --l) {   // outside bits between tile bits (uniform)
+            const bool h = (src_base >> l) & 1u;
+            const T c = h ? q[4 * l + 2] : q[4 * l], d = h ? q[4 * l + 3] : q[4 * l + 1];
+#pragma unroll
+            for (int k = 0; k < 2 * n; ++k) cmul(pr[k], pi[k], c, d);
+        }
+    }
+    uint32_t jb[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) jb[i] = 1u << pa.tix[i];
+#pragma unroll
+    for (uint32_t e = 0; e < 32u; ++e) {
+        uint32_t j = jt;
+#pragma unroll
+        for (int i = 0; i < 5; ++i)
+            if ((e >> i) & 1u) j |= jb[i];
+        const uint32_t slot = lds_slot<true>(j, swz);
+        if constexpr (sizeof(T) == 4)
+            reinterpret_cast<float2 *>(lds)[slot] = make_float2(pr[e], pi[e]);
+        else
+            reinterpret_cast<double2 *>(lds)[slot] = make_double2(pr[e], pi[e]);
+    }
+}
+
+template <int ELEM, bool SIGN>
+__global__ void __launch_bounds__(512) k_tile_product(vec16 *__restrict__ dst, TileArgs a, ProductTileArgs pa,
+                                                      uint64_t n_tiles) {
+    using T = typename std::conditional<ELEM == 8, float, double>::type;
+    extern __shared__ vec16 lds[];
+    const uint64_t tile = xcd_tile(blockIdx.x, a.xcd);
+    if (tile >= n_tiles) return;   // uniform over the workgroup
+    const uint32_t *rec = a.rec + tile * a.rec_words;
+    product_source_tile<T>(lds, rec_base(rec), pa, a.tb, a.swz);
+    uint32_t w[kPlanes];
+    tile_sources<ELEM, 5, true>(w, a, rec + 2);
+    __syncthreads();
+    tile_emit<ELEM, 5, SIGN, true>(w, dst, outer_address(a, tile) + thread_offset<ELEM>(a.pos_dst, a.tb, threadIdx.x),
+                                   a, lds);
+}
+
 // ------------------------------------------------------------ materialised row array
 
 // Index vector: entry i holds the integer i (8-byte entries).  Applying a
@@ -871,6 +975,21 @@ hipError_t launch_product(uint32_t elem, void *out, uint32_t M, const void *qubi
         hipLaunchKernelGGL(k_product<double>, dim3((uint32_t)grid), dim3(bs), 0, st, (double *)out, a, n);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_tile_product(uint32_t elem, void *dst, uint64_t n_tiles, const TileArgs &a,
+                               const ProductTileArgs &pa, hipStream_t st) {
+    const size_t lds = (size_t)elem << (a.tb + 5);
+    const uint32_t threads = 1u << a.tb;
+    if (a.eb != 5 || threads > 512u) return hipErrorInvalidValue;
+    auto go = [&](auto kern) {
+        hipError_t e = allow_lds(kern, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3((uint32_t)n_tiles), dim3(threads), lds, st, (vec16 *)dst, a, pa, n_tiles);
+        return hipGetLastError();
+    };
+    if (elem == 8) return a.sign ? go(k_tile_product<8, true>) : go(k_tile_product<8, false>);
+    return a.sign ? go(k_tile_product<16, true>) : go(k_tile_product<16, false>);
 }
 
 hipError_t launch_iota(uint64_t *out, uint64_t n, hipStream_t st) {

@@ -64,12 +64,23 @@ struct TileArgs {
     uint32_t eb;            // log2(tile rows per thread): 3, 4 or 5
     uint32_t sign;          // 1 when the pass has phase steps (sign plane in use)
     uint32_t xcd;           // log2 of the consecutive tiles run on one XCD (0: none)
-    uint32_t pad;
+    uint32_t swz;           // product-input pass only: LDS slot of tile index j is
+                            // j ^ ((j >> swz) & 31) (spreads its writes over the banks)
     uint32_t off_r_src[32]; // element offset of the tile-index bits above the thread bits, per r (read)
     uint32_t off_r_dst[32]; // same for the write layout
     uint8_t pos_src[16];    // physical bit of tile-index bit b in the read layout
     uint8_t pos_dst[16];    // physical bit of tile-index bit b in the write layout
     uint8_t out_dst[kMaxOuterBits];  // physical bit (write layout) of outer-index bit q
+};
+
+// First pass of a diagram applied to a product state (Appendix 1): the
+// source tile is formed from the qubits in LDS instead of read from HBM.
+struct ProductTileArgs {
+    const void *q;          // q_b(v) at complex index 2(b-1) + v, in the entries' precision
+    uint32_t M;
+    uint32_t pad;
+    uint8_t bit[16];        // logical address bits of the tile, lowest first
+    uint8_t tix[16];        // tile-index bit of bit[i]
 };
 
 struct TileMapArgs {
@@ -173,6 +184,9 @@ hipError_t launch_plain_step(uint32_t elem, void *buf, uint32_t M, uint32_t targ
 hipError_t launch_plain_phase(uint32_t elem, void *buf, uint32_t M, uint64_t mask, hipStream_t st);
 hipError_t launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t st);
 hipError_t launch_product(uint32_t elem, void *out, uint32_t M, const void *qubits, hipStream_t st);
+// One tile per workgroup, 32 rows per thread (a.eb = 5), natural read layout.
+hipError_t launch_tile_product(uint32_t elem, void *dst, uint64_t n_tiles, const TileArgs &a,
+                               const ProductTileArgs &pa, hipStream_t st);
 hipError_t launch_iota(uint64_t *out, uint64_t n, hipStream_t st);
 hipError_t launch_narrow(const uint64_t *in, uint32_t *out, uint64_t n, hipStream_t st);
 hipError_t launch_gather(uint32_t elem, const void *src, void *dst, const uint32_t *x, uint64_t n, hipStream_t st);

@@ -37,7 +37,7 @@ EXPORTS = (
     "qsim_state_set_tuning", "qsim_plan_describe", "qsim_copy_bytes", "qsim_last_error",
     "qsim_version", "qsim_state_profile", "qsim_state_profile_read", "qsim_apply_tile_pass",
     "qsim_batch_last_status", "qsim_server_create", "qsim_server_submit", "qsim_server_drain",
-    "qsim_server_request_info", "qsim_server_stats", "qsim_server_destroy", "qsim_state_set_product",
+    "qsim_server_request_info", "qsim_server_stats", "qsim_server_destroy", "qsim_state_set_product", "qsim_apply_steps_product",
     "qsim_rowmap_build", "qsim_rowmap_apply", "qsim_autotune", "qsim_batch_set_tiles_per_item",
     "qsim_batch_tiles_per_item", "qsim_batch_autotune",
 )
@@ -126,6 +126,7 @@ def _load() -> ctypes.CDLL:
         "qsim_server_stats": (i32, [vp, vp, vp, vp, vp]),
         "qsim_server_destroy": (None, [vp]),
         "qsim_state_set_product": (i32, [vp, vp, vp]),
+        "qsim_apply_steps_product": (i32, [vp, vp, vp, u64, vp]),
         "qsim_rowmap_build": (i32, [u32, vp, u64, vp, vp]),
         "qsim_rowmap_apply": (i32, [vp, vp, vp]),
         "qsim_autotune": (i32, [vp, vp, u64, vp, vp]),
@@ -313,6 +314,16 @@ class State:
         if q.shape != (self.M, 2):
             raise ValueError("qubits must have shape (M, 2)")
         _check(_lib.qsim_state_set_product(self._h, q.ctypes.data, ctypes.c_void_p(_stream_ptr(stream))))
+
+    def apply_product(self, qubits: np.ndarray, target, cmask, stream=None, kind=None):
+        """current <- U_L ... U_1 (q_M (x) ... (x) q_1), the product input formed
+        inside the first pass (qsim_apply_steps_product)."""
+        q = np.ascontiguousarray(qubits, dtype=np_dtype(self.code))
+        if q.shape != (self.M, 2):
+            raise ValueError("qubits must have shape (M, 2)")
+        st = pack_steps(target, cmask, kind)
+        _check(_lib.qsim_apply_steps_product(self._h, q.ctypes.data, st.ctypes.data if len(st) else None, len(st),
+                                             ctypes.c_void_p(_stream_ptr(stream))))
 
     def rowmap_apply(self, x_ptr: int, stream=None):
         """current <- k1(x(i)) with a device row array from rowmap_build."""

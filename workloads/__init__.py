@@ -116,6 +116,15 @@ def special_values_state(rng: np.random.Generator, M: int, dtype=np.complex64) -
 
 # ---------------------------------------------------------------- states (device)
 
+def unit_qubits(M: int, dtype=np.complex64, seed: int = SEED_M32) -> np.ndarray:
+    """M seeded qubit pairs (q_b(0), q_b(1)), each a unit-norm complex
+    Gaussian 2-vector, as an (M, 2) array: the factors of a product-state
+    input (row b-1 holds q_b)."""
+    rng = np.random.default_rng(seed)
+    qq = rng.standard_normal((M, 2)) + 1j * rng.standard_normal((M, 2))
+    return (qq / np.linalg.norm(qq, axis=1, keepdims=True)).astype(dtype)
+
+
 def gaussian_state_torch(M: int, dtype: str, seed: int, device="cuda"):
     """Unit-norm complex Gaussian state generated where it will live (torch's
     seeded generator); used for sizes whose host generation would be slow.
