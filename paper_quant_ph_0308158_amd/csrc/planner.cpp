@@ -333,14 +333,14 @@ namespace {
 // Beam search over whole plans.  Taking the most steps in every pass is
 // not the fewest passes overall: which of several equally good masks a pass
 // takes decides what the later passes can take together.  The search keeps
-// the `kBeam` partial plans with the fewest pending steps after each number
-// of passes; each is extended by the masks of a hill climb from its greedy
-// mask (the best mask and the next best of its last round) and by climbs
-// from seeded random masks.  A plan ends with a pass whose tile holds the
-// low bits and lies below bit 32 (it writes the natural layout).  The
-// search runs only while it can still beat `limit` passes; random draws
-// are seeded from the pass number and the plan's rank, so the result does
-// not depend on the thread count.
+// the `kBeam` cheapest partial plans (pending steps, plus a charge for each
+// thin boundary, below) after each number of passes; each is extended by
+// the masks of a hill climb from its greedy mask (the best mask and the
+// next best of its last round) and by climbs from seeded random masks.  A
+// plan ends with a pass whose tile holds the low bits and lies below bit 32
+// (it writes the natural layout).  The search runs only while it can still
+// beat `limit` passes; random draws are seeded from the pass number and the
+// plan's rank, so the result does not depend on the thread count.
 std::vector<Pass> beam_plan(const Diagram &d, uint64_t L, uint64_t base, uint64_t mid_base, uint64_t low32,
                             uint64_t all, size_t limit) {
     constexpr size_t kBeam = 6, kAlts = 4;
@@ -412,17 +412,17 @@ std::vector<Pass> beam_plan(const Diagram &d, uint64_t L, uint64_t base, uint64_
             if (!f.empty() && (size_t)scan_fixed(d, beam[k].pending, f[0], nullptr, nullptr) == beam[k].pending.size())
                 final_mask[k] = f[0];
         }
+        // Of the plans that can end with this pass, the one with the fewest
+        // thin boundaries (the first such in rank order).
+        auto thin_at_end = [&](size_t j) {
+            return beam[j].thin + (level > 0 && is_thin(beam[j].masks.back(), final_mask[j]) ? 1 : 0);
+        };
         size_t end = beam.size();
-        for (size_t k = 0; k < beam.size(); ++k) {
-            if (!final_mask[k]) continue;
-            auto thin_at_end = [&](size_t j) {
-                return beam[j].thin + (level > 0 && is_thin(beam[j].masks.back(), final_mask[j]) ? 1 : 0);
-            };
-            if (end == beam.size() || thin_at_end(k) < thin_at_end(end)) end = k;
-        }
-        for (size_t k = end; k < beam.size(); k = beam.size()) {
-            // The plan that can end here with the fewest thin boundaries
-            // (the first such in rank order): replay its masks into passes.
+        for (size_t k = 0; k < beam.size(); ++k)
+            if (final_mask[k] && (end == beam.size() || thin_at_end(k) < thin_at_end(end))) end = k;
+        if (end < beam.size()) {
+            // replay its masks into passes
+            const size_t k = end;
             std::vector<Pass> plan;
             std::vector<uint32_t> pending(L);
             for (uint64_t s = 0; s < L; ++s) pending[s] = (uint32_t)s;
