@@ -214,8 +214,8 @@ def bench_served(n: int, rate: float, slots: int = 8, budget: float = 200e9, cal
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="m32", choices=["m32", "m34", "m26", "small", "batched", "served"])
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--rate", type=float, default=None, help="served: arrivals per second")
