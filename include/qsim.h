@@ -346,7 +346,8 @@ typedef struct {
                               fewest passes, then the fewest tile pairs that
                               share less than a 128-byte line; tens of ms of
                               host time on up to 16 threads at M = 32,
-                              L = 1000);
+                              L = 1000; diagrams with L x passes above 4e6
+                              keep the climb's plan);
                               0 = climb + beam for M >= 30 (climb alone for
                               circuits of a batch)                         */
     uint32_t xcd_swizzle;  /* 1 = off, 2 = on (default): the one-tile-per-

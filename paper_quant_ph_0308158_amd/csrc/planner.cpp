@@ -595,8 +595,11 @@ std::vector<Pass> plan_passes(uint32_t M, const uint32_t *target, const uint64_t
         }
     }
     // Every tile holds the middle low bits, so consecutive tiles share at
-    // least those; the beam search keeps no other overlap.
-    if (search >= 2 && min_ov <= mid_low && passes.size() > 2) {
+    // least those; the beam search keeps no other overlap.  Its host time
+    // grows with L times the number of passes (each pass level scans the
+    // pending steps): long diagrams keep the climb's plan.
+    constexpr double kBeamWork = 4e6;
+    if (search >= 2 && min_ov <= mid_low && passes.size() > 2 && (double)L * (double)passes.size() <= kBeamWork) {
         std::vector<Pass> b = beam_plan(d, L, base, mid_base, low32, all, passes.size());
         if (!b.empty() && b.size() < passes.size()) return b;
     }
