@@ -852,6 +852,7 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
     std::vector<BatchSmall> bsmall;
     std::vector<size_t> small_blob_off, pass_blob_off;   // per entry: offset of its circuit blob
     std::vector<uint32_t> small_circuit;
+    std::vector<std::pair<uint32_t, uint32_t>> circuit_first_pass;   // (circuit, index of its first pass)
     std::vector<size_t> pass_rec_off;                     // word offset of each pass's records
     std::vector<size_t> circuit_blob_off(n, 0);
     size_t blob_size = 0, rec_words_total = 0;
@@ -881,6 +882,7 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
             continue;
         }
         uint32_t level = 0;
+        circuit_first_pass.push_back({c, (uint32_t)bpass.size()});
         for (size_t i = 0; i + 1 < bp.pr.launches.size(); i += 2, ++level) {
             const Launch &lm = bp.pr.launches[i], &lt = bp.pr.launches[i + 1];
             BatchPass p{};
@@ -905,7 +907,10 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
 
     // 3. the queue: record blocks, then tiles level by level with the small
     // circuits spread between the levels as fillers (every item's
-    // dependencies come earlier in the queue)
+    // dependencies come earlier in the queue).  A circuit whose passes have
+    // few tiles runs whole in one workgroup (one item for all its passes,
+    // placed over the first half of the levels): as one item per pass it
+    // would wait at every level for its previous pass.
     std::vector<uint64_t> items;
     uint32_t n_rec_blocks = 0;
     for (size_t g = 0; g < bpass.size(); ++g) {
@@ -913,20 +918,34 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
         for (uint64_t b = 0; b < nb; ++b) items.push_back(batch_item(kItemRec, (uint32_t)g, (uint32_t)b));
         n_rec_blocks += (uint32_t)nb;
     }
+    std::vector<uint64_t> whole;                     // kItemCircuit items
+    std::vector<uint8_t> in_whole(bpass.size(), 0);
+    for (size_t k = 0; k < circuit_first_pass.size(); ++k) {
+        const uint32_t g0 = circuit_first_pass[k].second;
+        const uint32_t g1 = k + 1 < circuit_first_pass.size() ? circuit_first_pass[k + 1].second
+                                                                : (uint32_t)bpass.size();
+        if (g1 == g0 || bpass[g0].n_tiles > kBatchCircuitTiles) continue;
+        whole.push_back(batch_item(kItemCircuit, g0, g1 - g0));
+        for (uint32_t g = g0; g < g1; ++g) in_whole[g] = 1;
+    }
     std::vector<std::vector<uint32_t>> by_level(max_level);
-    for (size_t g = 0; g < bpass.size(); ++g) by_level[bpass[g].level].push_back((uint32_t)g);
+    for (size_t g = 0; g < bpass.size(); ++g)
+        if (!in_whole[g]) by_level[bpass[g].level].push_back((uint32_t)g);
     const uint32_t tpi = batch_ws().tiles_per_item.load();
     const size_t n_small = bsmall.size();
-    size_t small_next = 0;
-    const size_t levels = std::max<size_t>(max_level, 1);
+    size_t small_next = 0, whole_next = 0;
+    const size_t levels = std::max<size_t>(max_level, 1), whole_levels = (levels + 1) / 2;
     for (size_t lv = 0; lv < levels; ++lv) {
         if (lv < by_level.size())
             for (uint32_t g : by_level[lv])
                 for (uint64_t t = 0; t * tpi < bpass[g].n_tiles; ++t)
                     items.push_back(batch_item(kItemTile, g, (uint32_t)t));
+        const size_t wupto = whole.size() * std::min(lv + 1, whole_levels) / whole_levels;
+        for (; whole_next < wupto; ++whole_next) items.push_back(whole[whole_next]);
         const size_t upto = n_small * (lv + 1) / levels;
         for (; small_next < upto; ++small_next) items.push_back(batch_item(kItemSmall, (uint32_t)small_next, 0));
     }
+    for (; whole_next < whole.size(); ++whole_next) items.push_back(whole[whole_next]);
     for (; small_next < n_small; ++small_next) items.push_back(batch_item(kItemSmall, (uint32_t)small_next, 0));
     if (items.size() > 0xFFFFFFF0ull) return fail(QSIM_ERR_INVALID, "batch too large");
     lap("queue");

@@ -562,6 +562,38 @@ __global__ void __launch_bounds__(256) k_batch(const BatchPass *__restrict__ pas
             publish(&ctr[1], 1u);
         } else if (kind == kItemSmall) {
             small_item<ELEM, SIGN>(smalls[idx], lds);
+        } else if (kind == kItemCircuit) {
+            // Every pass of one circuit (passes idx .. idx + sub - 1), all in
+            // this workgroup: no other workgroup touches its buffers, so a
+            // pass only has to see this workgroup's stores of the one before.
+            if (tid == 0) {
+                wait_at_least(&ctr[1], n_rec_blocks, &ctr[2], spin_limit);
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
+            __syncthreads();
+            for (uint32_t p = 0; p < sub; ++p) {
+                const BatchPass &bp = passes[idx + p];
+                const TileArgs &a = bp.ta;
+                const vec16 *src = static_cast<const vec16 *>(bp.src);
+                vec16 *dst = static_cast<vec16 *>(bp.dst);
+                const uint32_t off_src = thread_offset<ELEM>(a.pos_src, a.tb, tid);
+                const uint32_t off_dst = thread_offset<ELEM>(a.pos_dst, a.tb, tid);
+                vec16 v[VPT];
+                load_tile<ELEM, 5>(v, src, rec_base(a.rec) + off_src, a);
+                for (uint64_t tile = 0; tile < bp.n_tiles; ++tile) {
+                    const uint64_t next_base =
+                        tile + 1 < bp.n_tiles ? rec_base(a.rec + (tile + 1) * a.rec_words) + off_src : ~0ull;
+                    tile_step<ELEM, 5, true, SIGN>(v, src, dst, outer_address(a, tile) + off_dst, next_base, a,
+                                                   a.rec + tile * a.rec_words + 2, lds);
+                    __syncthreads();
+                }
+                // this pass's stores done, then the CU's L1 dropped before
+                // the next pass reads what they wrote
+                __builtin_amdgcn_s_waitcnt(0);
+                __syncthreads();
+                if (tid == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                __syncthreads();
+            }
         } else {
             const BatchPass &bp = passes[idx];
             if (tid == 0) {

@@ -120,7 +120,10 @@ struct BatchSmall {
     uint32_t pad;
 };
 
-enum : uint32_t { kItemRec = 0, kItemSmall = 1, kItemTile = 2 };
+enum : uint32_t { kItemRec = 0, kItemSmall = 1, kItemTile = 2, kItemCircuit = 3 };
+// Circuits whose passes have at most this many tiles run every pass in one
+// workgroup (one kItemCircuit item) instead of one item per pass.
+constexpr uint64_t kBatchCircuitTiles = 16;
 
 __host__ __device__ inline uint64_t batch_item(uint32_t kind, uint32_t index, uint32_t sub) {
     return ((uint64_t)kind << 62) | ((uint64_t)(index & 0x3FFFFFFFu) << 32) | sub;
