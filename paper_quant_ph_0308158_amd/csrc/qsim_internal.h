@@ -133,9 +133,9 @@ __host__ __device__ inline uint64_t batch_item(uint32_t kind, uint32_t index, ui
 // blocks, [2] error flag (a dependency wait ran out), [3] reserved,
 // [4 + c] finished tiles of circuit c.
 constexpr uint32_t kBatchCtrHeader = 4;
-constexpr uint32_t kBatchGroup = 4;   // queue items taken per atomic
-constexpr uint32_t kBatchTiles = 16;  // default tiles of one pass per tile item (4: 24.4 ms, 8: 19.8, 16: 18.7,
-                                      // 32: 20.3 for 4096 circuits of M 8..20)
+constexpr uint32_t kBatchGroup = 1;   // queue items taken per atomic (4: 20.1 ms, 2: 19.3, 1: 18.6)
+constexpr uint32_t kBatchTiles = 32;  // default tiles of one pass per tile item (8: 20.7 ms, 16: 18.8, 24: 18.5,
+                                      // 32: 18.3 for 4096 circuits of M 8..20)
 constexpr uint32_t kBatchTilesMax = 256;
 
 // Host-side plan of the fused path.
