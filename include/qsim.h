@@ -220,7 +220,7 @@ int qsim_apply_batch(qsim_state *const *states, const qsim_step *const *steps,
 int qsim_batch_last_status(void);
 
 /* Tiles of one pass that a queue item of the batched kernel covers (1..256;
- * 0 restores the default, 16).  Larger items mean fewer completion
+ * 0 restores the default, 32).  Larger items mean fewer completion
  * handshakes, smaller ones a shorter tail at the end of each pass.
  * Process-wide; applies to later qsim_apply_batch calls.  QSIM_ERR_INVALID
  * above 256. */

@@ -306,12 +306,12 @@ def test_batch_tiles_per_item_setting():
     """The batched kernel's tiles per queue item: validated, process-wide,
     0 restores the default (host only, no device work)."""
     default = qsim.batch_tiles_per_item()
-    assert default == 16
-    qsim.batch_set_tiles_per_item(32)
-    assert qsim.batch_tiles_per_item() == 32
+    assert default == 32
+    qsim.batch_set_tiles_per_item(8)
+    assert qsim.batch_tiles_per_item() == 8
     with pytest.raises(qsim.QsimError) as ei:
         qsim.batch_set_tiles_per_item(257)
     assert ei.value.code == qsim.ERR_INVALID
-    assert qsim.batch_tiles_per_item() == 32
+    assert qsim.batch_tiles_per_item() == 8
     qsim.batch_set_tiles_per_item(0)
     assert qsim.batch_tiles_per_item() == default
