@@ -217,7 +217,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="m32", choices=["m32", "m34", "m26", "small", "batched", "served"])
-    ap.add_argument("--requests", type=int, default=200)
+    ap.add_argument("--requests", type=int, default=None, help="served: requests in the trace (default 1000)")
     ap.add_argument("--rate", type=float, default=None, help="served: arrivals per second")
     ap.add_argument("--calibrate", action="store_true", help="served: all requests arrive at once")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -244,6 +244,8 @@ def main():
     if args.workload == "batched":
         print(json.dumps(bench_batched(max(1, args.steps))), flush=True)
         return
+    if args.requests is None:
+        args.requests = W.SERVED_REQUESTS
     if args.workload == "served":
         rate = args.rate if args.rate is not None else W.SERVED_RATE
         print(json.dumps(bench_served(args.requests, rate, calibrate=args.calibrate)), flush=True)

@@ -35,7 +35,9 @@ SEED_M26 = 26
 SEED_M32 = 32
 SEED_BATCHED = 4096
 SEED_SERVED = 2028
-SERVED_RATE = 145.0  # requests per second: 0.8 x the one-at-a-time capacity measured on MI355X (181.6 req/s)
+SERVED_RATE = 122.0  # requests per second: 0.8 x the one-at-a-time capacity on MI355X for the
+                     # first 1000 requests of the trace (152.4-153.2 req/s)
+SERVED_REQUESTS = 1000
 
 
 def random_steps(rng: np.random.Generator, M: int, L: int, n_ctl: Tuple[int, int],
