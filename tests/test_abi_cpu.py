@@ -176,6 +176,16 @@ def test_beam_search_saves_passes(seed, M, tile_bits, dtype):
     assert again[0].tolist() == masks.tolist() and again[2].tolist() == order.tolist()
 
 
+def test_beam_search_skipped_for_long_diagrams():
+    """The beam search's host time grows with L times the passes: beyond
+    4e6 the climb's plan is kept (same masks and order)."""
+    tg, cm = W.m32_config(L=12000, seed=7)
+    climb = qsim.plan_describe(32, "c64", tg, cm, {"plan_search": 2})
+    beam = qsim.plan_describe(32, "c64", tg, cm, {"plan_search": 3})
+    assert len(climb[0]) * len(tg) > 4e6
+    assert beam[0].tolist() == climb[0].tolist() and beam[2].tolist() == climb[2].tolist()
+
+
 def test_beam_search_with_phase_steps():
     rng = np.random.default_rng(25)
     M = 16
