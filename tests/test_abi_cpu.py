@@ -176,6 +176,33 @@ def test_beam_search_saves_passes(seed, M, tile_bits, dtype):
     assert again[0].tolist() == masks.tolist() and again[2].tolist() == order.tolist()
 
 
+def test_beam_search_random_diagrams():
+    """Beam-search plans of 24 seeded random diagrams (sizes, tiles, control
+    counts, phase steps, no reordering) are valid plans, never longer than
+    the climb's, and their order has the same product (oracle, tag state)."""
+    rng = np.random.default_rng(77)
+    for case in range(24):
+        M = int(rng.integers(11, 16))
+        K = int(rng.integers(5, min(M - 2, 9) + 1))
+        L = int(rng.integers(20, 160))
+        tg, cm = W.random_steps(rng, M, L, (0, int(rng.integers(1, 5))))
+        kd = (rng.random(L) < 0.25).astype(np.uint8) if case % 3 == 0 else None
+        tun = {"tile_bits": K, "low_bits": int(rng.integers(1, min(K, 5) + 1))}
+        if case % 5 == 4:
+            tun["reorder"] = False
+        climb = qsim.plan_describe(M, "c64", tg, cm, dict(tun, plan_search=2), kind=kd)[0]
+        masks, lens, order = _check_plan(M, "c64", tg, cm, dict(tun, plan_search=3), kd)
+        assert len(masks) <= len(climb), (case, len(masks), len(climb))
+        if kd is None:
+            k1 = W.tag_state(M)
+            assert oracle.apply(M, k1, tg, cm).tobytes() == oracle.apply(M, k1, tg[order], cm[order]).tobytes(), case
+        else:
+            k1 = (np.arange(1 << M) + 1j * np.arange(1 << M)[::-1]).astype(np.complex128)
+            a = oracle.apply(M, k1, tg, cm, kind=kd)
+            b = oracle.apply(M, k1, tg[order], cm[order], kind=kd[order])
+            assert a.tobytes() == b.tobytes(), case
+
+
 def test_beam_search_skipped_for_long_diagrams():
     """The beam search's host time grows with L times the passes: beyond
     4e6 the climb's plan is kept (same masks and order)."""
