@@ -20,6 +20,40 @@ def header_symbols():
     return sorted(set(re.findall(r"\b(qsim_[a-z_]+)\s*\(", text)))
 
 
+def test_plain_c_caller(tmp_path):
+    """The boundary is plain C: a C99 program that includes include/qsim.h
+    and links libqsim.so plans the paper's Fig. 2 diagram on the host
+    (qsim_plan_describe: no device work) and reads the library version."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lib = qsim.lib()._name
+    prog = tmp_path / "caller.c"
+    prog.write_text(r"""
+#include <stdio.h>
+#include "qsim.h"
+int main(void) {
+    /* Fig. 2: NOT a(2); NOT a(1) controlled by a(2); NOT a(2) */
+    qsim_step st[3] = {{1, QSIM_STEP_NOT, 0}, {0, QSIM_STEP_NOT, 2}, {1, QSIM_STEP_NOT, 0}};
+    uint32_t n = 0, len[8], order[8];
+    uint64_t mask[8];
+    int rc = qsim_plan_describe(12, QSIM_C64, st, 3, NULL, &n, mask, len, 8, order);
+    if (rc != QSIM_OK) { printf("rc %d %s\n", rc, qsim_last_error()); return 1; }
+    printf("%s passes %u steps %u\n", qsim_version(), n, len[0]);
+    return 0;
+}
+""")
+    exe = tmp_path / "caller"
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Werror", f"-I{os.path.join(ROOT, 'include')}", str(prog),
+                        lib, f"-Wl,-rpath,{os.path.dirname(lib)}", "-o", str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "passes 1 steps 3" in r.stdout
+
+
 def test_exports_every_header_symbol():
     syms = header_symbols()
     assert len(syms) >= 15
