@@ -369,6 +369,22 @@ def main():
             st.set_product(qq)
             st.apply(tg, cm)
 
+        # Same-target runs in the plain path (Sec. 2(i)): the paper's parity
+        # diagram (Sec. 4, M-1 steps on target a(1)) as one plain call (runs of
+        # up to 16 steps share a launch), one plain call per step, and the
+        # fused tile path.
+        ptg, pcm = W.parity_circuit(M)
+
+        def plain_steps():
+            for s_ in range(len(ptg)):
+                st.apply_plain(ptg[s_:s_ + 1], pcm[s_:s_ + 1])
+
+        r_ms, _ = timed(lambda: st.apply_plain(ptg, pcm), reps=1)
+        s_ms, _ = timed(plain_steps, reps=1)
+        f_ms_p, _ = timed(lambda: st.apply(ptg, pcm), reps=1)
+        plain_runs = {"diagram": f"parity of qubits 2..{M} onto qubit 1 ({len(ptg)} steps, one target)",
+                      "plain_runs_ms": round(r_ms, 3), "plain_per_step_ms": round(s_ms, 3),
+                      "fused_ms": round(f_ms_p, 3), "runs_speedup": round(s_ms / r_ms, 2)}
         u_ms, _ = timed(unfused)
         f_ms, fp = timed(lambda: st.apply_product(qq, tg, cm))
         first = fp["other_ms"] / fp["other_launches"] if fp["other_launches"] else None
@@ -383,7 +399,8 @@ def main():
         k1 = other = None
         modes = {"batched": bench_batched(5), "served": bench_served(args.requests, W.SERVED_RATE),
                  "served_capacity": bench_served(args.requests, W.SERVED_RATE, calibrate=True),
-                 "signed": signed, "blocked_halves": blocked, "product_input": product}
+                 "signed": signed, "blocked_halves": blocked, "product_input": product,
+                 "plain_same_target_runs": plain_runs}
         torch.cuda.empty_cache()
 
     cpu = None

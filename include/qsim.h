@@ -182,8 +182,11 @@ int qsim_rowmap_apply(qsim_state *state, const uint32_t *x_dev, void *hip_stream
 /* Same result as qsim_apply_steps, computed the plain way: one in-place
  * kernel launch per step that interchanges every pair of rows the step
  * toggles, or negates the rows a phase step selects (the state is
- * recalculated after each step, Sec. 2(h)).  A
- * comparator for the fused path; not faster. */
+ * recalculated after each step, Sec. 2(h)).  Consecutive NOT steps on one
+ * target (up to 16) share one launch that interchanges a pair when an odd
+ * number of their control conditions hold (the toggle parity of the
+ * same-target shortcut, Sec. 2(i)).  A comparator for the fused path; not
+ * faster. */
 int qsim_apply_steps_plain(qsim_state *state, const qsim_step *steps,
                            uint64_t L, void *hip_stream);
 

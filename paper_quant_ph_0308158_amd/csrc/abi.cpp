@@ -1351,15 +1351,28 @@ int qsim_apply_steps_plain(qsim_state *s, const qsim_step *steps, uint64_t L, vo
     if (L == 0) return QSIM_OK;
     DeviceGuard g(s->device);
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    for (uint64_t i = 0; i < L; ++i) {
+    for (uint64_t i = 0; i < L;) {
+        // consecutive NOT steps on one target run as one launch (toggle parity)
+        uint64_t j = i + 1;
+        if (steps[i].kind == QSIM_STEP_NOT)
+            while (j < L && j - i < kPlainRunMax && steps[j].kind == QSIM_STEP_NOT && steps[j].target == steps[i].target)
+                ++j;
         hipEvent_t ev_a = nullptr;
         hipError_t e = prof_begin(s, st, &ev_a);
-        if (e == hipSuccess)
-            e = steps[i].kind == QSIM_STEP_PHASE
-                    ? launch_plain_phase(s->elem, s->buf[s->cur], s->M, phase_mask(steps[i]), st)
-                    : launch_plain_step(s->elem, s->buf[s->cur], s->M, steps[i].target, steps[i].control_mask, st);
+        if (e == hipSuccess) {
+            if (steps[i].kind == QSIM_STEP_PHASE) {
+                e = launch_plain_phase(s->elem, s->buf[s->cur], s->M, phase_mask(steps[i]), st);
+            } else if (j - i == 1) {
+                e = launch_plain_step(s->elem, s->buf[s->cur], s->M, steps[i].target, steps[i].control_mask, st);
+            } else {
+                uint64_t cms[kPlainRunMax];
+                for (uint64_t q = i; q < j; ++q) cms[q - i] = steps[q].control_mask;
+                e = launch_plain_run(s->elem, s->buf[s->cur], s->M, steps[i].target, cms, (uint32_t)(j - i), st);
+            }
+        }
         if (e == hipSuccess) e = prof_end(s, st, 2, ev_a, 0);
         if (e != hipSuccess) return device_fail(s, e, "plain step launch");
+        i = j;
     }
     s->last_stream = st;
     return QSIM_OK;

@@ -437,6 +437,40 @@ __global__ void __launch_bounds__(256) k_plain_step(uint8_t *__restrict__ buf, u
     }
 }
 
+// A run of NOT steps on one target t (controls never include t, so every
+// step's condition reads the same bits in both rows of a pair): applied one
+// after another they interchange the pair (i, i | 2^t) once per step whose
+// controls hold, so the run interchanges it exactly when an odd number of
+// them hold (the toggle parity of Sec. 2(i)).  One thread per pair.
+struct PlainRun {
+    uint64_t cm[kPlainRunMax];
+    uint32_t k;
+};
+
+template <int ELEM>
+__global__ void __launch_bounds__(256) k_plain_run(uint8_t *__restrict__ buf, uint64_t half_n, uint32_t t,
+                                                   PlainRun r) {
+    const uint64_t T = 1ull << t;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < half_n; q += stride) {
+        const uint64_t lo = ((q >> t) << (t + 1)) | (q & (T - 1));
+        uint32_t odd = 0;
+        for (uint32_t j = 0; j < r.k; ++j) odd ^= (lo & r.cm[j]) == r.cm[j] ? 1u : 0u;
+        if (!odd) continue;
+        if (ELEM == 8) {
+            uint64_t *b = reinterpret_cast<uint64_t *>(buf);
+            const uint64_t a0 = b[lo], a1 = b[lo | T];
+            b[lo] = a1;
+            b[lo | T] = a0;
+        } else {
+            vec16 *b = reinterpret_cast<vec16 *>(buf);
+            const vec16 a0 = b[lo], a1 = b[lo | T];
+            b[lo] = a1;
+            b[lo | T] = a0;
+        }
+    }
+}
+
 // Plain phase step: every row whose bits in `mask` are all 1 is negated in
 // place (sign bits of both parts flipped).  One thread per row of the
 // 2^(M - |mask|) selected rows: the row counter is spread into the free bits.
@@ -954,6 +988,22 @@ hipError_t launch_plain_step(uint32_t elem, void *buf, uint32_t M, uint32_t targ
     else
         hipLaunchKernelGGL(k_plain_step<16>, dim3((uint32_t)grid), dim3(bs), 0, st, (uint8_t *)buf, half_n,
                            target, cmask);
+    return hipGetLastError();
+}
+
+hipError_t launch_plain_run(uint32_t elem, void *buf, uint32_t M, uint32_t target, const uint64_t *cmasks,
+                            uint32_t k, hipStream_t st) {
+    if (k < 1 || k > kPlainRunMax) return hipErrorInvalidValue;
+    PlainRun r{};
+    for (uint32_t j = 0; j < k; ++j) r.cm[j] = cmasks[j];
+    r.k = k;
+    const uint64_t half_n = 1ull << (M - 1);
+    const uint32_t bs = 256;
+    const uint64_t grid = std::min<uint64_t>((half_n + bs - 1) / bs, 1ull << 22);
+    if (elem == 8)
+        hipLaunchKernelGGL(k_plain_run<8>, dim3((uint32_t)grid), dim3(bs), 0, st, (uint8_t *)buf, half_n, target, r);
+    else
+        hipLaunchKernelGGL(k_plain_run<16>, dim3((uint32_t)grid), dim3(bs), 0, st, (uint8_t *)buf, half_n, target, r);
     return hipGetLastError();
 }
 

@@ -185,6 +185,10 @@ hipError_t launch_tile(uint32_t elem, const void *src, void *dst, uint64_t n_til
 hipError_t launch_plain_step(uint32_t elem, void *buf, uint32_t M, uint32_t target,
                              uint64_t cmask, hipStream_t st);
 hipError_t launch_plain_phase(uint32_t elem, void *buf, uint32_t M, uint64_t mask, hipStream_t st);
+// A run of k (2..kPlainRunMax) NOT steps on one target as one in-place launch.
+constexpr uint32_t kPlainRunMax = 16;
+hipError_t launch_plain_run(uint32_t elem, void *buf, uint32_t M, uint32_t target, const uint64_t *cmasks,
+                            uint32_t k, hipStream_t st);
 hipError_t launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t st);
 hipError_t launch_product(uint32_t elem, void *out, uint32_t M, const void *qubits, hipStream_t st);
 // One tile per workgroup, 32 rows per thread (a.eb = 5), natural read layout.

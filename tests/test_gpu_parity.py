@@ -164,6 +164,49 @@ def test_plain_path(q):
             assert_same(run_gpu(q, M, k1, tg, cm, plain=True), oracle.apply(M, k1, tg, cm), "plain")
 
 
+def run_plain_kinds(q, M, k1, tg, cm, kd):
+    dt = "c64" if k1.dtype == np.complex64 else "c128"
+    with q.State(M, dt) as s:
+        s.write(k1)
+        s.apply_plain(tg, cm, stream=0, kind=kd)
+        return s.read()
+
+
+def test_plain_same_target_runs(q):
+    """Consecutive NOT steps on one target share one plain launch that
+    interchanges a pair when an odd number of their conditions hold (Sec.
+    2(i)): the paper's parity diagram (Sec. 4: M-1 steps on one target, two
+    launches), runs of 1..40 steps (split every 16) with 0..4 controls and
+    repeated masks (pairs toggled twice stay), interrupted by phase steps."""
+    rng = np.random.default_rng(60)
+    for M in (12, 20):
+        tg, cm = W.parity_circuit(M)
+        k1 = W.alternating_state(M)
+        say("plain parity diagram", M)
+        k2 = run_gpu(q, M, k1, tg, cm, plain=True)
+        assert_same(k2, oracle.apply(M, k1, tg, cm), "plain parity diagram")
+        want = np.array([(-1.0) ** bin(i).count("1") for i in range(1 << M)]) * 2.0 ** (-M / 2)
+        assert np.array_equal(k2.real, want) and not k2.imag.any()
+    for dt, M, seed in ((np.complex64, 17, 61), (np.complex128, 15, 62), (np.complex64, 19, 63)):
+        r = np.random.default_rng(seed)
+        tgs, cms = [], []
+        while len(tgs) < 300:
+            t = int(r.integers(0, M))
+            run = int(r.integers(1, 41))
+            t_run, c_run = W.random_steps(r, M, run, (0, 4), targets=[t] * run)
+            if run > 3:
+                c_run[2] = c_run[0]             # a repeated condition toggles a pair twice
+            tgs += list(t_run)
+            cms += list(c_run)
+        tg = np.array(tgs, dtype=np.uint32)
+        cm = np.array(cms, dtype=np.uint64)
+        kd = (r.random(len(tg)) < 0.05).astype(np.uint8)
+        k1 = W.gaussian_state(r, M, dt)
+        say("plain runs", M, dt.__name__)
+        assert_same(run_plain_kinds(q, M, k1, tg, cm, kd), oracle.apply(M, k1, tg, cm, kind=kd), "plain runs")
+        assert_same(run_gpu(q, M, k1, tg, cm, plain=True), oracle.apply(M, k1, tg, cm), "plain runs, NOT only")
+
+
 def test_empty_and_unconditional(q):
     rng = np.random.default_rng(7)
     M = 16
