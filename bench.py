@@ -163,7 +163,7 @@ def bench_batched(reps: int = 3):
             "speedup_vs_plain": round(out["plain"]["ms"] / out["batched"]["ms"], 2)}
 
 
-def bench_served(n: int, rate: float, slots: int = 8, budget: float = 200e9, calibrate: bool = False):
+def bench_served(n: int, rate: float, slots: int = 4, budget: float = 200e9, calibrate: bool = False):
     """The served configuration: Poisson arrivals of circuit requests (M
     log-uniform over [12, 29) floored, L uniform in 50..2000, 0..3 controls,
     complex64, the alternating input generated on the device), admitted into

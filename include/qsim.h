@@ -256,7 +256,7 @@ typedef struct qsim_server qsim_server;
 
 typedef struct {
     uint64_t hbm_budget_bytes; /* arena size (0 = 200e9 bytes)               */
-    uint32_t max_slots;        /* requests on the device at once (0 = 8)      */
+    uint32_t max_slots;        /* requests on the device at once (0 = 4)      */
     uint32_t portion_entries;  /* rows per read-back portion (0 = 2^20)       */
     uint32_t fcfs;             /* 1 = one request at a time, arrival order    */
     uint32_t max_bypass;       /* times the queue head may be overtaken (0 = 64) */
