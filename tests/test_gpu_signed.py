@@ -193,6 +193,29 @@ def test_signed_batch(q):
         s.close()
 
 
+@pytest.mark.parametrize("dt,seed", [(np.complex64, 7610), (np.complex128, 7611)])
+def test_signed_batch_mid_size_whole_circuits(q, dt, seed):
+    """Mid-size circuits (passes of at most 16 tiles) run whole in one
+    workgroup, mixed with tiled and in-LDS ones, deep diagrams (up to 600
+    steps, many passes each), phase steps; every result against the oracle."""
+    rng = np.random.default_rng(seed)
+    circuits = W.batched_config(n=120, seed=seed, m_range=(11, 18), l_range=(100, 600))
+    code = "c64" if dt == np.complex64 else "c128"
+    states, ins, kinds = [], [], []
+    for c in circuits:
+        k1 = W.gaussian_state(rng, c.M, dt)
+        s = q.State(c.M, code)
+        s.write(k1)
+        states.append(s); ins.append(k1)
+        kinds.append((rng.random(c.L) < 0.2).astype(np.uint8))
+    say("signed batch, mid-size whole circuits", code)
+    q.apply_batch(states, [(c.target, c.cmask, k) for c, k in zip(circuits, kinds)], stream=0)
+    q.batch_status()
+    for c, s, k1, kd in zip(circuits, states, ins, kinds):
+        assert_same(s.read(), oracle.apply(c.M, k1, c.target, c.cmask, kind=kd, threads=8), f"batch M={c.M} L={c.L}")
+        s.close()
+
+
 def test_signed_server(q):
     rng = np.random.default_rng(7700)
     reqs = []
