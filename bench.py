@@ -224,6 +224,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-modes", action="store_true",
                     help="skip the batched and served comparisons of the default run")
+    ap.add_argument("--skip-batched-served", action="store_true",
+                    help="run the other modes (signed, blocked halves, product input, plain runs) only")
     ap.add_argument("--tuning", default=None, help="JSON dict of qsim_tuning fields")
     ap.add_argument("--autotune", action="store_true", help="pick the tuning with qsim_autotune first")
     args = ap.parse_args()
@@ -397,10 +399,11 @@ def main():
         del k1, other
         torch.cuda.empty_cache()
         k1 = other = None
-        modes = {"batched": bench_batched(5), "served": bench_served(args.requests, W.SERVED_RATE),
-                 "served_capacity": bench_served(args.requests, W.SERVED_RATE, calibrate=True),
-                 "signed": signed, "blocked_halves": blocked, "product_input": product,
+        modes = {"signed": signed, "blocked_halves": blocked, "product_input": product,
                  "plain_same_target_runs": plain_runs}
+        if not args.skip_batched_served:
+            modes = {"batched": bench_batched(5), "served": bench_served(args.requests, W.SERVED_RATE),
+                     "served_capacity": bench_served(args.requests, W.SERVED_RATE, calibrate=True), **modes}
         torch.cuda.empty_cache()
 
     cpu = None
