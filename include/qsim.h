@@ -161,6 +161,31 @@ int qsim_apply_steps_product(qsim_state *state, const void *qubits, const qsim_s
 int qsim_apply_steps(qsim_state *state, const qsim_step *steps, uint64_t L,
                      void *hip_stream);
 
+/* Bytes of device scratch that qsim_apply_steps_noalloc may use: one array
+ * of this size on each device the library runs on, held until the process
+ * ends. */
+#define QSIM_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* qsim_apply_steps for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, result and errors as qsim_apply_steps, with
+ * the same kernels; the uploaded plan and the per-tile records of the
+ * current pass live in the library's per-device scratch array of
+ * QSIM_NOALLOC_SCRATCH_BYTES instead of buffers the state grows.  The call
+ * makes no hipMalloc, hipFree, pinned host allocation or other device
+ * allocation: the plan travels to the device in kernel arguments, so
+ * `steps` may be freed on return and the call does not wait for the
+ * device.  Every call on one device shares that device's scratch, whose
+ * contents are whatever the last call left: calls on one stream are
+ * ordered, but calls whose work may overlap on one device (other streams,
+ * other threads) race and must be ordered by the caller.
+ * QSIM_ERR_NOMEM, with nothing enqueued, if the plan and one pass's tile
+ * records need more than QSIM_NOALLOC_SCRATCH_BYTES (the largest states
+ * with small tiles or very long passes).  Launches are not timed by
+ * qsim_state_profile. */
+int qsim_apply_steps_noalloc(qsim_state *state, const qsim_step *steps, uint64_t L,
+                             void *hip_stream);
+
 /* The row array x of a whole diagram of QSIM_STEP_NOT steps (a row array
  * holds no signs: phase steps are rejected with QSIM_ERR_INVALID)
  * (Sec. 2(h), Summary of Method): x(i)

@@ -648,24 +648,20 @@ hipError_t prof_collect(qsim_state *s) {
     return hipSuccess;
 }
 
-int enqueue(qsim_state *s, Prepared &pr, hipStream_t st) {
+// Enqueue the launches of `pr` on `st`, with the plan blob already on the
+// device at `dev` (or enqueued ahead of them on `st`) and `rec` holding
+// room for the tile records of one pass.  With `timed` the launches are
+// bracketed by profiling events when the state's profiling is on.
+int enqueue_launches(qsim_state *s, Prepared &pr, hipStream_t st, uint8_t *dev, uint32_t *rec, bool timed) {
     hipError_t e;
-    if ((e = s->stage.ensure(pr.blob.size())) != hipSuccess) return device_fail(s, e, "host staging");
-    if ((e = s->plan.ensure(pr.blob.size())) != hipSuccess) return device_fail(s, e, "plan buffer");
-    if (pr.rec_bytes && (e = s->rec.ensure(pr.rec_bytes)) != hipSuccess) return device_fail(s, e, "tile records");
-    std::memcpy(s->stage.p, pr.blob.data(), pr.blob.size());
-    if ((e = hipMemcpyAsync(s->plan.p, s->stage.p, pr.blob.size(), hipMemcpyHostToDevice, st)) != hipSuccess)
-        return device_fail(s, e, "plan upload");
-    if ((e = hipEventRecord(s->stage.ev, st)) != hipSuccess) return device_fail(s, e, "event record");
-    s->stage.pending = true;
-    uint8_t *dev = static_cast<uint8_t *>(s->plan.p);
+    const bool prof = timed && s->profiling;
     const uint64_t n = 1ull << s->M;
     const uint64_t pass_bytes = 2ull * n * s->elem;
     for (Launch &l : pr.launches) {
         const void *src = s->buf[s->cur];
         void *dst = s->buf[s->cur ^ 1];
         hipEvent_t ev_a = nullptr;
-        if ((e = prof_begin(s, st, &ev_a)) != hipSuccess) return device_fail(s, e, "profiling event");
+        if (prof && (e = prof_begin(s, st, &ev_a)) != hipSuccess) return device_fail(s, e, "profiling event");
         // The product-input pass counts as "other": it writes the state and
         // reads nothing, unlike the tile passes whose bytes are summed.
         const int kind = l.kind == Launch::TILE && !l.product ? 0 : (l.kind == Launch::TILEMAP ? 1 : 2);
@@ -682,12 +678,12 @@ int enqueue(qsim_state *s, Prepared &pr, hipStream_t st) {
                 break;
             case Launch::TILEMAP:
                 l.tm.steps = reinterpret_cast<const TmStep *>(dev + l.steps_off);
-                l.tm.rec = static_cast<uint32_t *>(s->rec.p);
+                l.tm.rec = rec;
                 e = launch_tilemap(l.tm, st);
                 break;
             case Launch::TILE:
                 l.ta.inner = reinterpret_cast<const uint32_t *>(dev + l.inner_off);
-                l.ta.rec = static_cast<const uint32_t *>(s->rec.p);
+                l.ta.rec = rec;
                 if (l.product) {
                     l.pa.q = dev + l.q_off;
                     e = launch_tile_product(s->elem, dst, l.n_tiles, l.ta, l.pa, st);
@@ -698,17 +694,65 @@ int enqueue(qsim_state *s, Prepared &pr, hipStream_t st) {
                 break;
         }
         if (e != hipSuccess) return device_fail(s, e, "kernel launch");
-        if ((e = prof_end(s, st, kind, ev_a, kind == 1 ? 0 : pass_bytes)) != hipSuccess)
+        if (prof && (e = prof_end(s, st, kind, ev_a, kind == 1 ? 0 : pass_bytes)) != hipSuccess)
             return device_fail(s, e, "profiling event");
     }
     s->last_stream = st;
     return QSIM_OK;
 }
 
+// Upload the plan through the state's pinned staging buffer into its own
+// plan buffer, then enqueue the launches (the state's buffers grow as
+// needed).
+int enqueue(qsim_state *s, Prepared &pr, hipStream_t st) {
+    hipError_t e;
+    if ((e = s->stage.ensure(pr.blob.size())) != hipSuccess) return device_fail(s, e, "host staging");
+    if ((e = s->plan.ensure(pr.blob.size())) != hipSuccess) return device_fail(s, e, "plan buffer");
+    if (pr.rec_bytes && (e = s->rec.ensure(pr.rec_bytes)) != hipSuccess) return device_fail(s, e, "tile records");
+    std::memcpy(s->stage.p, pr.blob.data(), pr.blob.size());
+    if ((e = hipMemcpyAsync(s->plan.p, s->stage.p, pr.blob.size(), hipMemcpyHostToDevice, st)) != hipSuccess)
+        return device_fail(s, e, "plan upload");
+    if ((e = hipEventRecord(s->stage.ev, st)) != hipSuccess) return device_fail(s, e, "event record");
+    s->stage.pending = true;
+    return enqueue_launches(s, pr, st, static_cast<uint8_t *>(s->plan.p), static_cast<uint32_t *>(s->rec.p), true);
+}
+
 int check_state(const qsim_state *s) {
     if (!s) return fail(QSIM_ERR_INVALID, "state is NULL");
     if (s->poisoned) return fail(QSIM_ERR_DEVICE, "state is poisoned by an earlier device error");
     return QSIM_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ allocation-free apply
+
+// Device scratch of qsim_apply_steps_noalloc: the plan blob at the start,
+// the tile records of the current pass after it.  Each device that runs the
+// library holds its own copy until the process ends.  Host code never uses
+// the array's name as an address: the address on each device comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+static __device__ __align__(256) uint8_t scratch[QSIM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kScratchDevices] = {};
+
+// Address of `scratch` on device `dev` (the current device).
+hipError_t scratch_address(int dev, void **out) {
+    if (dev < 0 || dev >= kScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 }  // namespace
@@ -1239,6 +1283,32 @@ int qsim_apply_steps(qsim_state *s, const qsim_step *steps, uint64_t L, void *hi
     DeviceGuard g(s->device);
     if (!g.ok) return device_fail(s, hipErrorInvalidDevice, "set device");
     return enqueue(s, pr, static_cast<hipStream_t>(hip_stream));
+}
+
+int qsim_apply_steps_noalloc(qsim_state *s, const qsim_step *steps, uint64_t L, void *hip_stream) {
+    int rc = check_state(s);
+    if (rc) return rc;
+    if ((rc = validate_steps(s->M, steps, L))) return rc;
+    if (L == 0) return QSIM_OK;
+    Prepared pr;
+    if ((rc = prepare(s, steps, L, pr))) return rc;
+    // the records start on a 256-byte boundary after the blob
+    pr.blob.resize((pr.blob.size() + 255) & ~size_t(255), 0);
+    const uint64_t need = (uint64_t)pr.blob.size() + pr.rec_bytes;
+    if (need > QSIM_NOALLOC_SCRATCH_BYTES)
+        return fail(QSIM_ERR_NOMEM, "qsim_apply_steps_noalloc: the plan and one pass's tile records need " +
+                                        std::to_string(need) + " bytes, above the scratch of " +
+                                        std::to_string((uint64_t)QSIM_NOALLOC_SCRATCH_BYTES) + " bytes");
+    DeviceGuard g(s->device);
+    if (!g.ok) return device_fail(s, hipErrorInvalidDevice, "set device");
+    void *base = nullptr;
+    hipError_t e = scratch_address(s->device, &base);
+    if (e != hipSuccess) return device_fail(s, e, "scratch address");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if ((e = launch_put(base, pr.blob.data(), pr.blob.size(), st)) != hipSuccess)
+        return device_fail(s, e, "plan upload");
+    uint8_t *dev = static_cast<uint8_t *>(base);
+    return enqueue_launches(s, pr, st, dev, reinterpret_cast<uint32_t *>(dev + pr.blob.size()), false);
 }
 
 namespace {

@@ -508,6 +508,17 @@ __global__ void __launch_bounds__(256) k_copy(const vec16 *__restrict__ src, vec
         st_nt(dst + i, ld_nt(src + i));
 }
 
+// Upload of host bytes through a kernel's argument block: the runtime copies
+// the arguments when the launch is enqueued, so the source may be freed at
+// once and no staging memory is needed (the allocation-free entry point).
+struct PutArgs {
+    uint32_t words[kPutChunkBytes / 4];
+};
+
+__global__ void __launch_bounds__(256) k_put(uint32_t *__restrict__ dst, PutArgs a, uint32_t n_words) {
+    for (uint32_t i = threadIdx.x; i < n_words; i += blockDim.x) dst[i] = a.words[i];
+}
+
 // ------------------------------------------------------------ batched mode
 
 // Publishing an item's results to workgroups on other XCDs (separate L2
@@ -1091,6 +1102,22 @@ hipError_t launch_gather(uint32_t elem, const void *src, void *dst, const uint32
     else
         hipLaunchKernelGGL(k_gather<16>, grid, dim3(256), 0, st, (const uint8_t *)src, (uint8_t *)dst, x, n);
     return hipGetLastError();
+}
+
+hipError_t launch_put(void *dst, const void *src, size_t bytes, hipStream_t st) {
+    if (bytes & 3u) return hipErrorInvalidValue;
+    const uint8_t *p = static_cast<const uint8_t *>(src);
+    uint8_t *d = static_cast<uint8_t *>(dst);
+    for (size_t off = 0; off < bytes; off += kPutChunkBytes) {
+        const size_t n = std::min<size_t>(kPutChunkBytes, bytes - off);
+        PutArgs a;
+        std::memcpy(a.words, p + off, n);
+        hipLaunchKernelGGL(k_put, dim3(1), dim3(256), 0, st, reinterpret_cast<uint32_t *>(d + off), a,
+                           (uint32_t)(n / 4));
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t st) {

@@ -190,6 +190,12 @@ constexpr uint32_t kPlainRunMax = 16;
 hipError_t launch_plain_run(uint32_t elem, void *buf, uint32_t M, uint32_t target, const uint64_t *cmasks,
                             uint32_t k, hipStream_t st);
 hipError_t launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t st);
+// Copy `bytes` (a multiple of 4) of host memory to device memory `dst` in
+// stream order, carried in kernel arguments of kPutChunkBytes each: no
+// staging buffer, and `src` may be reused as soon as the call returns.
+constexpr uint32_t kPutChunkBytes = 2048;
+hipError_t launch_put(void *dst, const void *src, size_t bytes, hipStream_t st);
+
 hipError_t launch_product(uint32_t elem, void *out, uint32_t M, const void *qubits, hipStream_t st);
 // One tile per workgroup, 32 rows per thread (a.eb = 5), natural read layout.
 hipError_t launch_tile_product(uint32_t elem, void *dst, uint64_t n_tiles, const TileArgs &a,

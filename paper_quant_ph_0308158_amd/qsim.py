@@ -39,7 +39,7 @@ EXPORTS = (
     "qsim_batch_last_status", "qsim_server_create", "qsim_server_submit", "qsim_server_drain",
     "qsim_server_request_info", "qsim_server_stats", "qsim_server_destroy", "qsim_state_set_product", "qsim_apply_steps_product",
     "qsim_rowmap_build", "qsim_rowmap_apply", "qsim_autotune", "qsim_batch_set_tiles_per_item",
-    "qsim_batch_tiles_per_item", "qsim_batch_autotune",
+    "qsim_batch_tiles_per_item", "qsim_batch_autotune", "qsim_apply_steps_noalloc",
 )
 
 
@@ -134,6 +134,7 @@ def _load() -> ctypes.CDLL:
         "qsim_batch_set_tiles_per_item": (i32, [u32]),
         "qsim_batch_tiles_per_item": (u32, []),
         "qsim_batch_autotune": (i32, [vp, vp, vp, u32, vp, vp]),
+        "qsim_apply_steps_noalloc": (i32, [vp, vp, u64, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -307,6 +308,13 @@ class State:
     def apply_packed(self, steps: np.ndarray, stream=None):
         _check(_lib.qsim_apply_steps(self._h, steps.ctypes.data if len(steps) else None, len(steps),
                                      ctypes.c_void_p(_stream_ptr(stream))))
+
+    def apply_noalloc(self, target, cmask, stream=None, kind=None):
+        """qsim_apply_steps_noalloc: the same result, with the plan and tile
+        records in the library's per-device scratch (no device allocation)."""
+        st = pack_steps(target, cmask, kind)
+        _check(_lib.qsim_apply_steps_noalloc(self._h, st.ctypes.data if len(st) else None, len(st),
+                                             ctypes.c_void_p(_stream_ptr(stream))))
 
     def set_product(self, qubits: np.ndarray, stream=None):
         """k1 = q_M (x) ... (x) q_1 from qubits[b-1] = (q_b(0), q_b(1)) (shape (M, 2))."""
