@@ -92,7 +92,7 @@ def cpu_baseline(wl, k1_host, seconds: float):
     import numpy as np
     import oracle
     M, tg, cm = wl["M"], wl["target"], wl["cmask"]
-    threads = int(os.environ.get("QSIM_ORACLE_THREADS", min(os.cpu_count() or 1, 16)))
+    threads, why = oracle_threads()
     buf = k1_host
     t0 = time.perf_counter()
     oracle.apply_inplace(M, buf, tg[:1], cm[:1], threads=threads)
@@ -106,14 +106,60 @@ def cpu_baseline(wl, k1_host, seconds: float):
     oracle.apply_inplace(M, buf, tg[1 + n:2 + n], cm[1 + n:2 + n], threads=1)
     d1 = time.perf_counter() - t0
     return {"value": float((1 << M) * n / dt), "unit": "amplitude-step updates/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "cores_why": why, "host_cpus": os.cpu_count(), "model": cpu_model(),
             "sample": f"steps 2..{n + 1} of the same {len(tg)}-step diagram on the full 2^{M}-entry "
                       f"input (plain pair-swap loop, OpenMP over rows, {dt:.1f} s)",
             "single_thread": {"value": float((1 << M) / d1), "cores": 1,
                               "sample": f"step {n + 2} of the same diagram on one thread ({d1:.1f} s)"}}
 
 
-def bench_batched(reps: int = 3):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_threads():
+    """Threads for the oracle's OpenMP loop: every CPU this process may run
+    on, unless OMP_NUM_THREADS (the share of the host's CPUs a one-GPU job
+    is given) or QSIM_ORACLE_THREADS sets fewer."""
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    for var in ("QSIM_ORACLE_THREADS", "OMP_NUM_THREADS"):
+        v = os.environ.get(var)
+        if v and v.isdigit() and 0 < int(v) < avail:
+            return int(v), f"{var}={v} (of {avail} CPUs this process may use)"
+    return avail, f"all {avail} CPUs this process may use"
+
+
+def cpu_configs(reps: int = 3):
+    """The oracle on the two configurations small enough to run whole, best
+    of `reps`: M=10 complex128 L=20 and M=26 complex128 L=200."""
+    import numpy as np
+    import oracle
+    import workloads as W
+    threads, _ = oracle_threads()
+    out = {}
+    for name, M, (tg, cm), k1 in (
+            ("m10_c128_L20", 10, W.small_config(), W.alternating_state(10)),
+            ("m26_c128_L200", 26, W.m26_config(), W.gaussian_state_torch(26, "c128", seed=W.SEED_M26).cpu().numpy())):
+        best = None
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            oracle.apply(M, k1, tg, cm, threads=threads)
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        out[name] = {"best_of": reps, "ms": round(best * 1e3, 3), "cores": threads,
+                     "value": float((1 << M) * len(tg) / best), "unit": "amplitude-step updates/s"}
+        del k1
+    return out
+
+
+def bench_batched(reps: int = 3, plain_too: bool = True, autotune: bool = True):
     """The batched configuration: 4096 independent circuits (M uniform in
     8..20, L uniform in 10..500, 0..3 controls, complex64), all states
     resident on the device.  Timed three ways on the same states and
@@ -123,10 +169,8 @@ def bench_batched(reps: int = 3):
     import workloads as W
     from paper_quant_ph_0308158_amd import qsim
     circuits = W.batched_config()
-    states = []
-    for i, c in enumerate(circuits):
-        k1 = W.gaussian_state_torch(c.M, "c64", seed=1000 + i)
-        states.append(qsim.State(c.M, "c64", buffers=(k1, torch.empty_like(k1))))
+    k1s, spares = W.gaussian_states_grouped_torch([c.M for c in circuits], "c64", seed=W.SEED_BATCHED)
+    states = [qsim.State(c.M, "c64", buffers=(k1, sp)) for c, k1, sp in zip(circuits, k1s, spares)]
     steps = [(c.target, c.cmask) for c in circuits]
     packed = [qsim.pack_steps(t, cm) for t, cm in steps]
     batch = qsim.PackedBatch(steps)
@@ -141,11 +185,15 @@ def bench_batched(reps: int = 3):
         qsim.apply_batch_packed(states, batch)
 
     # the batch autotuner picks the tiles per queue item (states unchanged)
-    t0 = time.perf_counter()
-    tiles = qsim.batch_autotune(states, batch)
-    tune_s = time.perf_counter() - t0
-    out = {}
+    tiles, tune_s = None, None
+    if autotune:
+        t0 = time.perf_counter()
+        tiles = qsim.batch_autotune(states, batch)
+        tune_s = time.perf_counter() - t0
+    out = {"plain": None}
     for name, fn in (("plain", plain), ("batched", batched)):
+        if name == "plain" and not plain_too:
+            continue
         fn()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -157,10 +205,66 @@ def bench_batched(reps: int = 3):
     qsim.batch_status()
     for st in states:
         st.close()
+    # a plain copy of a known size in the same process: the reference that
+    # scales rocprofv3's byte counters for the batched kernel
+    cb = 1 << 31
+    a = torch.empty(cb, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    qsim.copy_bytes(b.data_ptr(), a.data_ptr(), cb)
+    torch.cuda.synchronize()
+    del a, b
     return {"workload": "batched_4096_M8-20_L10-500_c64", "circuits": len(circuits),
             "amplitude_step_updates": updates, "plain": out["plain"], "batched": out["batched"],
-            "autotune": {"tiles_per_item": tiles, "seconds": round(tune_s, 2)},
-            "speedup_vs_plain": round(out["plain"]["ms"] / out["batched"]["ms"], 2)}
+            "autotune": {"tiles_per_item": tiles, "seconds": round(tune_s, 2) if tune_s else None},
+            "speedup_vs_plain": round(out["plain"]["ms"] / out["batched"]["ms"], 2) if out["plain"] else None}
+
+
+def bench_rowmap(reps: int, warmup: int):
+    """The materialised row array at M = 32, complex64: the row array x of
+    the 1000-step headline diagram is built once (qsim_rowmap_build), then
+    applied `reps` times (qsim_rowmap_apply: k2(i) = k1(x(i)), one gather).
+    Algorithmic bytes per apply: 2^M x (4 B of x + 8 B read + 8 B written);
+    the apply's duration comes from HIP events on its stream."""
+    import torch
+    import workloads as W
+    from paper_quant_ph_0308158_amd import qsim
+    M = 32
+    tg, cm = W.m32_config()
+    x = torch.empty(1 << M, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    qsim.rowmap_build(M, tg, cm, x)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    k1 = W.gaussian_state_torch(M, "c64", seed=W.SEED_M32)
+    b1 = torch.empty_like(k1)
+    st = qsim.State(M, "c64", buffers=(k1, b1))
+    for _ in range(warmup):
+        st.rowmap_apply(x.data_ptr())
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * reps)]
+    t0 = time.perf_counter()
+    for r in range(reps):
+        ev[2 * r].record(stream)
+        st.rowmap_apply(x.data_ptr())
+        ev[2 * r + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    avg_ms = sum(ev[2 * r].elapsed_time(ev[2 * r + 1]) for r in range(reps)) / reps
+    alg = float(1 << M) * (4 + 2 * 8)
+    st.close()
+    # a plain copy of a known size in the same process (scales rocprofv3's
+    # byte counters)
+    qsim.copy_bytes(b1.data_ptr(), k1.data_ptr(), 8 << M)
+    torch.cuda.synchronize()
+    del x, k1, b1
+    torch.cuda.empty_cache()
+    achieved = alg / (avg_ms * 1e-3) / 1e9
+    return {"workload": "rowmap_m32_c64_L1000", "build_ms": round(build_ms, 2), "apply_ms": round(avg_ms, 3),
+            "wall_ms_per_apply": round(wall * 1e3, 3), "updates_per_s": float(1 << M) * len(tg) / (avg_ms * 1e-3),
+            "roofline": {"bound": "hbm", "kernel": "k_gather", "achieved": round(achieved, 1),
+                         "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                         "algorithmic_bytes_per_launch": int(alg), "avg_launch_ms": round(avg_ms, 4)}}
 
 
 def bench_served(n: int, rate: float, slots: int = 4, budget: float = 200e9, calibrate: bool = False):
@@ -216,7 +320,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="m32", choices=["m32", "m34", "m26", "small", "batched", "served"])
+    ap.add_argument("--workload", default="m32", choices=["m32", "m34", "m26", "small", "batched", "served", "rowmap"])
     ap.add_argument("--requests", type=int, default=None, help="served: requests in the trace (default 1000)")
     ap.add_argument("--rate", type=float, default=None, help="served: arrivals per second")
     ap.add_argument("--calibrate", action="store_true", help="served: all requests arrive at once")
@@ -226,6 +330,8 @@ def main():
                     help="skip the batched and served comparisons of the default run")
     ap.add_argument("--skip-batched-served", action="store_true",
                     help="run the other modes (signed, blocked halves, product input, plain runs) only")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="batched: time the batched launch only (no per-circuit plain run, no autotune)")
     ap.add_argument("--tuning", default=None, help="JSON dict of qsim_tuning fields")
     ap.add_argument("--autotune", action="store_true", help="pick the tuning with qsim_autotune first")
     args = ap.parse_args()
@@ -243,8 +349,12 @@ def main():
     from paper_quant_ph_0308158_amd import qsim
 
     torch.cuda.set_device(0)
+    if args.workload == "rowmap":
+        print(json.dumps(bench_rowmap(max(1, args.steps), max(0, args.warmup))), flush=True)
+        return
     if args.workload == "batched":
-        print(json.dumps(bench_batched(max(1, args.steps))), flush=True)
+        print(json.dumps(bench_batched(max(1, args.steps), plain_too=not args.no_plain,
+                                       autotune=not args.no_plain)), flush=True)
         return
     if args.requests is None:
         args.requests = W.SERVED_REQUESTS
@@ -416,6 +526,8 @@ def main():
         torch.cuda.empty_cache()
         cpu = cpu_baseline(wl, host, args.cpu_seconds)
         del host
+        if args.workload == "m32":
+            cpu["configs"] = cpu_configs()
     st.close()
 
     out = {

@@ -94,27 +94,35 @@ typedef struct qsim_state qsim_state;
 #define QSIM_MAX_M 36u
 
 /* Create a state of 2^M entries of `dtype` on the current HIP device:
- * allocates two device buffers of 2^M * elem bytes.  The contents are
+ * allocates two device buffers of 2^M * elem bytes.  The state is the
+ * paper's vector k1 of 2^M rows, one per address of M bits (Sec. 2(b)),
+ * holding complex amplitudes of arbitrary magnitude and phase (Sec. 1).  The contents are
  * undefined until written (qsim_write_portion or through the pointer of
  * qsim_state_current()).  Returns NULL on bad M / dtype (QSIM_ERR_INVALID)
  * or allocation failure (QSIM_ERR_NOMEM). */
 qsim_state *qsim_state_create(uint32_t M, qsim_dtype dtype);
 
 /* Wrap two caller-owned device buffers of 2^M * elem bytes each (for example
- * torch tensors).  buf0 holds k1; buf1 is scratch.  Both must be 16-byte
+ * torch tensors): the same 2^M-row vector as qsim_state_create (Sec. 1,
+ * Sec. 2(b)) in memory the caller provides.  buf0 holds k1; buf1 is scratch.  Both must be 16-byte
  * aligned, must not overlap and must outlive the state.  NULL on error. */
 qsim_state *qsim_state_wrap(uint32_t M, qsim_dtype dtype, void *buf0, void *buf1);
 
 /* Release the state (and its buffers if it allocated them).  Waits for work
- * enqueued on the state to finish.  NULL is ignored. */
+ * enqueued on the state to finish.  NULL is ignored.  (Resource management;
+ * no passage of the paper.) */
 void qsim_state_destroy(qsim_state *state);
 
-/* Number of address bits and entry size in bytes of a state (0 on NULL). */
+/* Number of address bits M (Sec. 2(b)) and entry size in bytes of a state
+ * (0 on NULL). */
 uint32_t qsim_state_qubits(const qsim_state *state);
 uint32_t qsim_state_elem_bytes(const qsim_state *state);
 
 /* Device pointer to the buffer that holds the current vector (k1 before any
- * apply, k2 after).  Valid until the next apply on the state. */
+ * apply, k2 = U k1 after, Sec. 2(a)).  Valid until the next apply on the
+ * state.  (Which of the two buffers holds it is a property of this
+ * library's out-of-place passes; the paper keeps k1 and k2 as separate
+ * arrays, Sec. 4.) */
 const void *qsim_state_current(const qsim_state *state);
 
 /* Copy `count` entries from host memory into rows [offset, offset+count) of
@@ -222,15 +230,19 @@ int qsim_apply_steps_plain(qsim_state *state, const qsim_step *steps,
 int qsim_read_portion(const qsim_state *state, uint64_t offset, uint64_t count,
                       void *host_dst);
 
-/* Stream-ordered variant: enqueues the device-to-host copy on `hip_stream`
- * after the work already enqueued on it.  `host_dst` should be pinned
+/* Stream-ordered variant of qsim_read_portion (the same contiguous
+ * portions, Abstract and Conclusions): enqueues the device-to-host copy on
+ * `hip_stream` after the work already enqueued on it.  `host_dst` should be pinned
  * (hipHostMalloc) memory and must stay valid until the stream reaches the
  * copy. */
 int qsim_read_portion_async(const qsim_state *state, uint64_t offset,
                             uint64_t count, void *host_dst, void *hip_stream);
 
 /* Apply n independent wiring diagrams to n distinct states in one
- * persistent kernel launch (batched mode).  Circuit c applies
+ * persistent kernel launch (batched mode).  Each circuit is the operation
+ * of qsim_apply_steps (Sec. 2(a), 2(h)); running many at once is this
+ * library's use of the parts that may run simultaneously (Sec. 2(i),
+ * Parallelism) across circuits, which the paper does not treat.  Circuit c applies
  * steps[c][0 .. Ls[c]-1] to states[c] exactly as qsim_apply_steps would;
  * the results are bit-identical to n separate calls.  The states may differ
  * in M but must share one dtype.  All circuits are validated before any
@@ -238,8 +250,8 @@ int qsim_read_portion_async(const qsim_state *state, uint64_t offset,
 int qsim_apply_batch(qsim_state *const *states, const qsim_step *const *steps,
                      const uint64_t *Ls, uint32_t n, void *hip_stream);
 
-/* Wait for every qsim_apply_batch launch of the process still in flight
- * and report whether all launches since the previous call completed
+/* (No passage of the paper: status of the batched launches.)  Wait for
+ * every qsim_apply_batch launch of the process still in flight and report whether all launches since the previous call completed
  * cleanly: QSIM_OK, or QSIM_ERR_DEVICE if a HIP error occurred or a tile's
  * wait for the previous pass of its circuit ran out in one of them (the
  * results of that batch are then invalid).  Batches may be enqueued back to
@@ -247,7 +259,8 @@ int qsim_apply_batch(qsim_state *const *states, const qsim_step *const *steps,
  * and uploads one batch's plan while the previous batch runs. */
 int qsim_batch_last_status(void);
 
-/* Tiles of one pass that a queue item of the batched kernel covers (1..256;
+/* (No passage of the paper: a launch parameter of batched mode.)  Tiles of
+ * one pass that a queue item of the batched kernel covers (1..256;
  * 0 restores the default, 32).  Larger items mean fewer completion
  * handshakes, smaller ones a shorter tail at the end of each pass.
  * Process-wide; applies to later qsim_apply_batch calls.  QSIM_ERR_INVALID
@@ -300,7 +313,9 @@ typedef struct {
     uint64_t bytes;       /* bytes read back                                 */
 } qsim_request_info;
 
-/* Create a server on the current device; allocates the arena.  cfg may be
+/* Create a server on the current device; allocates the arena.  (Serving
+ * runtime around qsim_apply_steps; the paper's counterpart is only the
+ * hand-off of results in portions, Abstract and Conclusions.)  cfg may be
  * NULL (defaults).  NULL on failure (no device, arena allocation failed,
  * max_slots > 64). */
 qsim_server *qsim_server_create(const qsim_server_config *cfg);
@@ -315,21 +330,22 @@ int64_t qsim_server_submit(qsim_server *server, uint32_t M, qsim_dtype dtype,
                            const void *host_k1, const qsim_step *steps,
                            uint64_t L);
 
-/* Wait until every submitted request is done. */
+/* Wait until every submitted request is done.  (No passage of the paper.) */
 int qsim_server_drain(qsim_server *server);
 
-/* Status, timestamps and digest of request `id` (QSIM_ERR_RANGE for an
- * unknown id). */
+/* (No passage of the paper.)  Status, timestamps and digest of request
+ * `id` (QSIM_ERR_RANGE for an unknown id). */
 int qsim_server_request_info(qsim_server *server, int64_t id,
                              qsim_request_info *out);
 
-/* Arena size and use, queued and running request counts (any pointer may
- * be NULL). */
+/* (No passage of the paper.)  Arena size and use, queued and running
+ * request counts (any pointer may be NULL). */
 int qsim_server_stats(qsim_server *server, uint64_t *arena_bytes,
                       uint64_t *arena_used, uint32_t *queued,
                       uint32_t *running);
 
-/* Drain, stop the workers and free the arena.  NULL is ignored. */
+/* Drain, stop the workers and free the arena.  NULL is ignored.  (No
+ * passage of the paper.) */
 void qsim_server_destroy(qsim_server *server);
 
 /* ---------------------------------------------------------------- tuning */
@@ -385,7 +401,9 @@ typedef struct {
 } qsim_tuning;
 
 /* Set (tuning != NULL) or reset to defaults (NULL) the parameters used by
- * later applies on `state`.  QSIM_ERR_INVALID on out-of-range values. */
+ * later applies on `state`.  QSIM_ERR_INVALID on out-of-range values.
+ * (Launch parameters; the paper's only counterpart is the user-controlled
+ * trade-off between processors and memory of the Conclusions.) */
 int qsim_state_set_tuning(qsim_state *state, const qsim_tuning *tuning);
 
 /* Apply the steps, in the order given, as a single fused pass through
@@ -432,7 +450,8 @@ int qsim_plan_describe(uint32_t M, qsim_dtype dtype, const qsim_step *steps,
 
 /* ---------------------------------------------------------------- timing */
 
-/* Per-kernel device time of the applies on one state, taken with HIP events
+/* (Measurement; no passage of the paper.)  Per-kernel device time of the
+ * applies on one state, taken with HIP events
  * recorded on the stream of each launch (a few microseconds of gap per
  * launch while enabled). */
 typedef struct {
@@ -446,23 +465,26 @@ typedef struct {
 } qsim_profile;
 
 /* enable = 1: clear the counters and time every later launch on `state`;
- * enable = 0: stop timing. */
+ * enable = 0: stop timing.  (Measurement; no passage of the paper.) */
 int qsim_state_profile(qsim_state *state, int enable);
 
-/* Wait for the timed launches to finish and report their totals. */
+/* Wait for the timed launches to finish and report their totals.
+ * (Measurement; no passage of the paper.) */
 int qsim_state_profile_read(qsim_state *state, qsim_profile *out);
 
 /* ---------------------------------------------------------------- misc */
 
 /* Stream copy of `bytes` bytes (a multiple of 16) from src to dst, device
  * pointers, 16-byte aligned: the achievable-bandwidth reference that the
- * fused path's traffic is compared against. */
+ * fused path's traffic is compared against.  (Measurement; no passage of
+ * the paper.) */
 int qsim_copy_bytes(void *dst, const void *src, uint64_t bytes, void *hip_stream);
 
-/* Message describing the last failure on the calling thread ("" if none). */
+/* Message describing the last failure on the calling thread ("" if none).
+ * (Error reporting; no passage of the paper.) */
 const char *qsim_last_error(void);
 
-/* Library version string. */
+/* Library version string.  (No passage of the paper.) */
 const char *qsim_version(void);
 
 #ifdef __cplusplus

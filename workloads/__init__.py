@@ -150,6 +150,33 @@ def gaussian_state_torch(M: int, dtype: str, seed: int, device="cuda"):
     return torch.view_as_complex(v)
 
 
+def gaussian_states_grouped_torch(Ms: Sequence[int], dtype: str, seed: int, device="cuda"):
+    """One unit-norm complex Gaussian state per entry of ``Ms`` (torch's seeded
+    generator), drawn per distinct size as one (count, 2^M) tensor, so a
+    batch of thousands of states takes a few dozen kernel launches.  Returns
+    (states, spares): row views in the order of ``Ms`` and an uninitialised
+    buffer of the same size for each."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    fdt = torch.float32 if dtype == "c64" else torch.float64
+    states: List = [None] * len(Ms)
+    spares: List = [None] * len(Ms)
+    for m in sorted(set(int(x) for x in Ms)):
+        idx = [i for i, x in enumerate(Ms) if int(x) == m]
+        v = torch.empty(len(idx), 1 << m, 2, dtype=fdt, device=device)
+        v.normal_(generator=g)
+        nrm = v.double().square().sum(dim=(1, 2), keepdim=True).sqrt()
+        v.div_(nrm.to(fdt))
+        c = torch.view_as_complex(v)
+        sp = torch.empty_like(c)
+        for r, i in enumerate(idx):
+            states[i] = c[r]
+            spares[i] = sp[r]
+    return states, spares
+
+
 # ---------------------------------------------------------------- configurations
 
 def small_config(seed: int = SEED_SMALL, M: int = 10, L: int = 20) -> Steps:
