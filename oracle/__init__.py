@@ -22,7 +22,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# QSIM_ORACLE_LIB names another build of oracle.c to load (the sanitizer
+# check runs the pins against one built with AddressSanitizer and UBSan).
+_LIB = os.environ.get("QSIM_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
@@ -34,6 +36,11 @@ def build(force: bool = True) -> str:
                "-Wall", "-Wextra", "-o", tmp, _SRC]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
+    return _LIB
+
+
+def library_path() -> str:
+    """Path of the oracle library this process loads."""
     return _LIB
 
 

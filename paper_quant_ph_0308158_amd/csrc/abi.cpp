@@ -31,6 +31,30 @@ int fail(int code, const std::string &msg) {
     return code;
 }
 
+// Host-side fault injection for tests of the error paths.  With
+// QSIM_FAULT_INJECT = "<site>:<n>" the n-th check of <site> (counted from 1
+// since the variable last changed) reports a HIP error after the real call
+// has succeeded, so the error handling runs while the device sees nothing
+// unusual.  Sites: "launch" (each kernel launch of an apply), "upload" (the
+// plan upload of an apply), "read" (a portion read), "batch" (a batched
+// launch).
+hipError_t injected(const char *site) {
+    const char *v = std::getenv("QSIM_FAULT_INJECT");
+    if (!v || !*v) return hipSuccess;
+    static std::mutex mu;
+    static std::string spec;
+    static uint64_t count = 0;
+    std::lock_guard<std::mutex> lk(mu);
+    if (spec != v) {
+        spec = v;
+        count = 0;
+    }
+    const char *colon = std::strchr(v, ':');
+    if (!colon || (size_t)(colon - v) != std::strlen(site) || std::strncmp(v, site, colon - v) != 0) return hipSuccess;
+    const uint64_t n = std::strtoull(colon + 1, nullptr, 10);
+    return ++count == n ? hipErrorUnknown : hipSuccess;
+}
+
 std::atomic<uint64_t> g_allocated{0};
 
 // Optional cap on the bytes that qsim_state_create may allocate, from the
@@ -656,6 +680,7 @@ int enqueue_launches(qsim_state *s, Prepared &pr, hipStream_t st, uint8_t *dev, 
     hipError_t e;
     const bool prof = timed && s->profiling;
     const uint64_t n = 1ull << s->M;
+    s->last_stream = st;   // set first: a failure part-way still leaves launched work to wait for
     const uint64_t pass_bytes = 2ull * n * s->elem;
     for (Launch &l : pr.launches) {
         const void *src = s->buf[s->cur];
@@ -693,6 +718,7 @@ int enqueue_launches(qsim_state *s, Prepared &pr, hipStream_t st, uint8_t *dev, 
                 s->cur ^= 1;
                 break;
         }
+        if (e == hipSuccess) e = injected("launch");
         if (e != hipSuccess) return device_fail(s, e, "kernel launch");
         if (prof && (e = prof_end(s, st, kind, ev_a, kind == 1 ? 0 : pass_bytes)) != hipSuccess)
             return device_fail(s, e, "profiling event");
@@ -710,8 +736,10 @@ int enqueue(qsim_state *s, Prepared &pr, hipStream_t st) {
     if ((e = s->plan.ensure(pr.blob.size())) != hipSuccess) return device_fail(s, e, "plan buffer");
     if (pr.rec_bytes && (e = s->rec.ensure(pr.rec_bytes)) != hipSuccess) return device_fail(s, e, "tile records");
     std::memcpy(s->stage.p, pr.blob.data(), pr.blob.size());
-    if ((e = hipMemcpyAsync(s->plan.p, s->stage.p, pr.blob.size(), hipMemcpyHostToDevice, st)) != hipSuccess)
-        return device_fail(s, e, "plan upload");
+    s->last_stream = st;
+    e = hipMemcpyAsync(s->plan.p, s->stage.p, pr.blob.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = injected("upload");
+    if (e != hipSuccess) return device_fail(s, e, "plan upload");
     if ((e = hipEventRecord(s->stage.ev, st)) != hipSuccess) return device_fail(s, e, "event record");
     s->stage.pending = true;
     return enqueue_launches(s, pr, st, static_cast<uint8_t *>(s->plan.p), static_cast<uint32_t *>(s->rec.p), true);
@@ -1076,7 +1104,10 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
                          reinterpret_cast<const BatchSmall *>(dev + small_off),
                          reinterpret_cast<const uint64_t *>(dev + items_off), (uint32_t)items.size(), ctr_dev,
                          n_rec_blocks, 1u << 24, tpi, st);
+        if (e == hipSuccess) e = injected("batch");
         if (e != hipSuccess) {
+            // whatever did launch finishes before the slot can be reused
+            (void)hipStreamSynchronize(st);
             for (uint32_t c = 0; c < n; ++c) states[c]->poisoned = true;
             return fail(QSIM_ERR_DEVICE, std::string("batch launch: ") + hipGetErrorString(e));
         }
@@ -1305,6 +1336,7 @@ int qsim_apply_steps_noalloc(qsim_state *s, const qsim_step *steps, uint64_t L, 
     hipError_t e = scratch_address(s->device, &base);
     if (e != hipSuccess) return device_fail(s, e, "scratch address");
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    s->last_stream = st;
     if ((e = launch_put(base, pr.blob.data(), pr.blob.size(), st)) != hipSuccess)
         return device_fail(s, e, "plan upload");
     uint8_t *dev = static_cast<uint8_t *>(base);
@@ -1421,6 +1453,7 @@ int qsim_apply_steps_plain(qsim_state *s, const qsim_step *steps, uint64_t L, vo
     if (L == 0) return QSIM_OK;
     DeviceGuard g(s->device);
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    s->last_stream = st;
     for (uint64_t i = 0; i < L;) {
         // consecutive NOT steps on one target run as one launch (toggle parity)
         uint64_t j = i + 1;
@@ -1461,6 +1494,7 @@ int qsim_read_portion(const qsim_state *cs, uint64_t offset, uint64_t count, voi
     if (e != hipSuccess) return device_fail(s, e, "synchronize");
     e = hipMemcpy(host_dst, static_cast<const uint8_t *>(s->buf[s->cur]) + offset * s->elem, count * s->elem,
                   hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = injected("read");
     if (e != hipSuccess) return device_fail(s, e, "read portion");
     return QSIM_OK;
 }

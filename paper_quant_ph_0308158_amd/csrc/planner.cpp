@@ -33,7 +33,7 @@
 #include <stdexcept>
 #include <thread>
 
-#include "qsim_internal.h"
+#include "planner.h"
 
 namespace qsim {
 
@@ -485,7 +485,10 @@ std::vector<Pass> plan_passes(uint32_t M, const uint32_t *target, const uint64_t
     const uint64_t low32 = all & 0xFFFFFFFFull;
     uint64_t allowed = low32;
     auto set_allowed = [&](bool natural) { allowed = (natural || !cfg.remap) ? low32 : all; };
-    const int low = std::min<int>(std::max(cfg.low_bits, 1), K);
+    // The forced low bits leave a tile bit free whenever the state is larger
+    // than one tile: a step whose target lies outside them and whose control
+    // lies among them needs its target in the tile.
+    const int low = std::min<int>(std::max(cfg.low_bits, 1), (int)M > K ? K - 1 : K);
     const uint64_t base = (1ull << low) - 1ull;
     std::vector<uint32_t> pending(L);
     for (uint64_t s = 0; s < L; ++s) pending[s] = (uint32_t)s;
@@ -558,7 +561,21 @@ std::vector<Pass> plan_passes(uint32_t M, const uint32_t *target, const uint64_t
     auto next_pass = [&](uint64_t start, uint64_t fallback) {
         Pass p = build_pass(start);
         if (p.steps.empty() && start != fallback) p = build_pass(fallback);
-        if (p.steps.empty()) throw std::logic_error("planner made no progress");
+        if (p.steps.empty() && passes.empty() && cfg.remap && (allowed & ~low32) == 0 && all != low32) {
+            // The first pass reads the natural layout, so its tile bits lie
+            // below 32; when every step it could take waits behind one that
+            // targets a bit at or above 32 with a control among the low
+            // bits, a pass without steps moves the state into a permuted
+            // layout in which the next pass may tile that bit.
+            Pass head;
+            head.tile_mask = base;
+            for (uint32_t b = 0; b < 32 && b < M && popc(head.tile_mask) < K; ++b) head.tile_mask |= 1ull << b;
+            return head;
+        }
+        if (p.steps.empty())
+            throw std::logic_error(cfg.remap ? "planner made no progress"
+                                             : "a step targets an address bit at or above 32 with a control that "
+                                               "every tile holds; this needs permuted layouts (remap on)");
         return p;
     };
     while (!pending.empty()) {

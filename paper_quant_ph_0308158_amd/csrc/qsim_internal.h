@@ -8,6 +8,8 @@
 #include <string>
 #include <vector>
 
+#include "planner.h"
+
 namespace qsim {
 
 // Entries per LDS tile are 2^(tb + eb): every thread of a tile workgroup owns
@@ -17,10 +19,6 @@ constexpr int kPlanes = 16;        // bit-plane registers per thread (tile bits 
 constexpr int kMaxTileBits = 14;   // 2^14 entries * 8 B = 128 KiB of LDS
 constexpr int kMaxOuterBits = 48;
 constexpr uint32_t kMaxQubits = 36;    // largest M of a state
-
-// Step kinds as the library stores them (the public qsim_step_kind values).
-constexpr uint8_t kStepNot = 0;
-constexpr uint8_t kStepPhase = 1;
 
 // Bit-plane that carries the sign of each row during the inner walk: tile
 // indices have at most kMaxTileBits bits, so plane 15 is free.  A phase
@@ -137,31 +135,6 @@ constexpr uint32_t kBatchGroup = 1;   // queue items taken per atomic (4: 20.1 m
 constexpr uint32_t kBatchTiles = 32;  // default tiles of one pass per tile item (8: 20.7 ms, 16: 18.8, 24: 18.5,
                                       // 32: 18.3 for 4096 circuits of M 8..20)
 constexpr uint32_t kBatchTilesMax = 256;
-
-// Host-side plan of the fused path.
-struct Pass {
-    uint64_t tile_mask = 0;          // address bits inside a tile
-    std::vector<uint32_t> steps;     // original step indices, execution order
-};
-
-struct PlanConfig {
-    int tile_bits = 13;
-    int low_bits = 5;       // low address bits in the tiles of the first and last pass
-    int mid_low_bits = 0;   // same for the passes in between (0 = low_bits)
-    int min_overlap = 0;    // tile bits a middle pass shares with the previous one
-    int max_seg_steps = 1024;
-    bool reorder = true;
-    int search = -1;        // tile-mask search: 0 off, 1 hill climb per pass, 2 climb + beam
-                            // search over whole plans, -1 climb + beam for M >= 30
-    bool remap = true;      // permuted layouts between passes (middle tiles may use bits >= 32)
-    int threads = 0;        // host threads of the beam search (0 = hardware threads, at most 16)
-    int line_bits = 4;      // address bits a 128-byte line spans (4: 8-byte entries, 3: 16-byte)
-};
-
-// Split steps into passes (see planner.cpp).
-// kind may be null (every step a controlled NOT).
-std::vector<Pass> plan_passes(uint32_t M, const uint32_t *target, const uint64_t *cmask, const uint8_t *kind,
-                              uint64_t L, const PlanConfig &cfg);
 
 }  // namespace qsim
 

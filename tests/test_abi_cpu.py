@@ -386,3 +386,13 @@ def test_batch_tiles_per_item_setting():
     assert qsim.batch_tiles_per_item() == 8
     qsim.batch_set_tiles_per_item(0)
     assert qsim.batch_tiles_per_item() == default
+
+
+def test_budget_rejects_state_creation(monkeypatch):
+    """QSIM_HBM_BUDGET_BYTES caps what qsim_state_create may allocate: a
+    state beyond it fails with QSIM_ERR_NOMEM before any device call (so
+    this holds without a GPU too)."""
+    monkeypatch.setenv("QSIM_HBM_BUDGET_BYTES", str(1 << 20))
+    with pytest.raises(qsim.QsimError):
+        qsim.State(20, "c64")                 # 2 x 8 MiB > 1 MiB
+    assert "QSIM_HBM_BUDGET_BYTES" in qsim.last_error()

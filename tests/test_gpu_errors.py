@@ -1,0 +1,118 @@
+"""Error paths on the device, forced from the host (no kernel faults):
+the HBM budget turns state creation into QSIM_ERR_NOMEM, and
+QSIM_FAULT_INJECT makes a chosen HIP call report an error after it has
+succeeded, which must poison the state so every later call on it returns
+QSIM_ERR_DEVICE while other states keep working."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def q():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_quant_ph_0308158_amd import qsim
+    return qsim
+
+
+def _expect(q, code, fn, *a, **k):
+    with pytest.raises(q.QsimError) as ei:
+        fn(*a, **k)
+    assert ei.value.code == code, (ei.value.code, q.last_error())
+
+
+def test_budget_limits_created_states(q, monkeypatch):
+    monkeypatch.setenv("QSIM_HBM_BUDGET_BYTES", "1")
+    say("budget: create refused")
+    with pytest.raises(q.QsimError):
+        q.State(12, "c64")
+    assert "QSIM_HBM_BUDGET_BYTES" in q.last_error()
+    monkeypatch.delenv("QSIM_HBM_BUDGET_BYTES")
+    with q.State(12, "c64") as s:          # no cap: the same state is created
+        assert s.n == 1 << 12
+
+
+def _poisoned(q, s, tg, cm):
+    """Every later call on a poisoned state reports QSIM_ERR_DEVICE."""
+    _expect(q, q.ERR_DEVICE, s.apply, tg, cm, stream=0)
+    _expect(q, q.ERR_DEVICE, s.apply_noalloc, tg, cm, stream=0)
+    _expect(q, q.ERR_DEVICE, s.apply_plain, tg, cm, stream=0)
+    _expect(q, q.ERR_DEVICE, s.read)
+    _expect(q, q.ERR_DEVICE, s.write, np.zeros(s.n, dtype=np.complex64))
+
+
+@pytest.mark.parametrize("site", ["launch:3", "upload:1"])
+def test_injected_apply_error_poisons_state(q, monkeypatch, site):
+    rng = np.random.default_rng(8100)
+    M = 19
+    tg, cm = W.random_steps(rng, M, 200, (0, 3))
+    k1 = W.gaussian_state(rng, M, np.complex64)
+    s = q.State(M, "c64")
+    s.set_tuning({"tile_bits": 10, "small_bits": 5})
+    s.write(k1)
+    say("inject", site)
+    monkeypatch.setenv("QSIM_FAULT_INJECT", site)
+    _expect(q, q.ERR_DEVICE, s.apply, tg, cm, stream=0)
+    monkeypatch.delenv("QSIM_FAULT_INJECT")
+    _poisoned(q, s, tg, cm)
+    s.close()
+    with q.State(M, "c64") as t:          # another state is unaffected
+        t.write(k1)
+        t.apply(tg, cm, stream=0)
+        assert t.read().tobytes() == oracle.apply(M, k1, tg, cm).tobytes()
+
+
+def test_injected_read_error_poisons_state(q, monkeypatch):
+    M = 14
+    k1 = W.gaussian_state(np.random.default_rng(8101), M, np.complex64)
+    s = q.State(M, "c64")
+    s.write(k1)
+    monkeypatch.setenv("QSIM_FAULT_INJECT", "read:1")
+    say("inject read")
+    _expect(q, q.ERR_DEVICE, s.read)
+    monkeypatch.delenv("QSIM_FAULT_INJECT")
+    _poisoned(q, s, np.zeros(1, np.uint32), np.zeros(1, np.uint64))
+    s.close()
+
+
+def test_injected_batch_error_poisons_its_states(q, monkeypatch):
+    rng = np.random.default_rng(8102)
+    circuits = W.batched_config(n=12, seed=8103, m_range=(5, 17), l_range=(1, 80))
+    ins = [W.gaussian_state(rng, c.M, np.complex64) for c in circuits]
+    states = []
+    for c, k1 in zip(circuits, ins):
+        s = q.State(c.M, "c64")
+        s.write(k1)
+        states.append(s)
+    steps = [(c.target, c.cmask) for c in circuits]
+    monkeypatch.setenv("QSIM_FAULT_INJECT", "batch:1")
+    say("inject batch")
+    _expect(q, q.ERR_DEVICE, q.apply_batch, states, steps, stream=0)
+    monkeypatch.delenv("QSIM_FAULT_INJECT")
+    for s in states:
+        _expect(q, q.ERR_DEVICE, s.read)
+        s.close()
+    q.batch_status()                      # the failed call left no batch in flight
+    fresh = []
+    for c, k1 in zip(circuits, ins):      # new states batch normally
+        s = q.State(c.M, "c64")
+        s.write(k1)
+        fresh.append(s)
+    q.apply_batch(fresh, steps, stream=0)
+    q.batch_status()
+    for c, s, k1 in zip(circuits, fresh, ins):
+        assert s.read().tobytes() == oracle.apply(c.M, k1, c.target, c.cmask).tobytes()
+        s.close()
