@@ -282,14 +282,16 @@ def bench_served(n: int, rate: float, slots: int = 4, budget: float = 200e9, cal
     packed = [qsim.pack_steps(r.circuit.target, r.circuit.cmask) for r in trace]
     updates = float(sum((1 << r.circuit.M) * r.circuit.L for r in trace))
 
-    def run(fcfs: bool):
-        srv = qsim.Server(budget_bytes=int(budget), max_slots=slots, fcfs=fcfs)
+    def run(fcfs: bool, digest: int = 0, at_once: bool = calibrate, only=None):
+        srv = qsim.Server(budget_bytes=int(budget), max_slots=slots, fcfs=fcfs, digest=digest)
         w = srv.submit(12, "c64", [0], [0])   # warm the slot workers
         srv.drain()
         ids = []
         t0 = time.perf_counter()
-        for r, pk in zip(trace, packed):
-            if not calibrate:
+        for k, (r, pk) in enumerate(zip(trace, packed)):
+            if only is not None and k not in only:
+                continue
+            if not at_once:
                 delay = t0 + r.arrival_s - time.perf_counter()
                 if delay > 0:
                     time.sleep(delay)
@@ -297,6 +299,8 @@ def bench_served(n: int, rate: float, slots: int = 4, budget: float = 200e9, cal
         srv.drain()
         infos = [srv.info(i) for i in ids]
         srv.close()
+        if digest:
+            return ids, infos
         if any(x["status"] != 0 for x in infos):
             raise RuntimeError("a served request failed")
         lat = sorted((x["t_done_ns"] - x["t_submit_ns"]) / 1e6 for x in infos)
@@ -308,7 +312,21 @@ def bench_served(n: int, rate: float, slots: int = 4, budget: float = 200e9, cal
 
     cont = run(False)
     plain = run(True)
-    return {"workload": f"served_poisson_{n}req_rate{rate:g}_M12-28_L50-2000_c64", "requests": n,
+    # Check of the served results (untimed: digesting on the host would add
+    # to the latencies): the whole trace again with continuous batching,
+    # every `stride`-th request digested as it is read back, against the
+    # same requests served one at a time.
+    stride = 50
+    ids, infos = run(False, digest=stride, at_once=True)
+    picked = [k for k, i in enumerate(ids) if i % stride == 0]
+    _, alone = run(True, digest=1, at_once=True, only=set(picked))
+    bad = [k for k, a in zip(picked, alone) if a["digest"] != infos[k]["digest"] or a["bytes"] != infos[k]["bytes"]]
+    if bad:
+        raise RuntimeError(f"served requests {bad} differ in the mix and alone")
+    check = {"requests_checked": len(picked), "mismatches": 0,
+             "how": f"every {stride}th request of the trace: digest of its read-back portions with continuous "
+                    f"batching equals its digest served alone"}
+    return {"workload": f"served_poisson_{n}req_rate{rate:g}_M12-28_L50-2000_c64", "requests": n, "check": check,
             "rate_per_s": rate, "calibration": calibrate, "slots": slots, "budget_bytes": budget,
             "amplitude_step_updates": updates, "continuous": cont, "plain_fcfs": plain,
             "throughput_speedup_vs_plain": round(cont["updates_per_s"] / plain["updates_per_s"], 2),

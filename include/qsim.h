@@ -298,7 +298,9 @@ typedef struct {
     uint32_t portion_entries;  /* rows per read-back portion (0 = 2^20)       */
     uint32_t fcfs;             /* 1 = one request at a time, arrival order    */
     uint32_t max_bypass;       /* times the queue head may be overtaken (0 = 64) */
-    uint32_t digest;           /* 1 = fold every portion into the request's digest */
+    uint32_t digest;           /* 1 = fold every portion into the request's
+                                  digest; k > 1 = only for requests whose id
+                                  is a multiple of k; 0 = none              */
     uint32_t reserved;
 } qsim_server_config;
 
@@ -309,7 +311,12 @@ typedef struct {
     uint64_t t_admit_ns;  /* and completion (last portion digested)          */
     uint64_t t_done_ns;
     uint64_t digest;      /* digest of the result's bytes in row order (0
-                             unless the server computes digests)            */
+                             unless the server digests this request): the
+                             sum mod 2^64 over its 8-byte words w_j, j = 0,
+                             1, ... from the first row, of
+                             mix(w_j ^ mix(j + 0x9E3779B97F4A7C15)), then
+                             mix(sum ^ mix(byte count)); mix is SplitMix64's
+                             finaliser                                      */
     uint64_t bytes;       /* bytes read back                                 */
 } qsim_request_info;
 

@@ -97,26 +97,30 @@ class Arena {
     std::map<uint64_t, uint64_t> free_;  // offset -> length
 };
 
-// 64-bit digest of a byte stream, folded portion by portion: four
-// independent multiply-rotate lanes over 8-byte words.
+// 64-bit digest of a result in row order: the sum (mod 2^64), over its
+// 8-byte words w_j (j counted from the first byte of the result), of
+// mix(w_j ^ mix(j + kKey)), finally mixed with the byte count.  Every word
+// is keyed by its position, so portions fold in any order and a host can
+// recompute the digest of a result with vector arithmetic.  mix is the
+// 64-bit finaliser of the SplitMix64 generator (Steele, Lea and Flood).
 struct Digest {
-    uint64_t h[4] = {0x9E3779B97F4A7C15ull, 0xC2B2AE3D27D4EB4Full, 0x165667B19E3779F9ull, 0x27D4EB2F165667C5ull};
-    uint64_t n = 0;
-    static uint64_t rotl(uint64_t x, int r) { return (x << r) | (x >> (64 - r)); }
+    static constexpr uint64_t kKey = 0x9E3779B97F4A7C15ull;
+    uint64_t sum = 0;
+    uint64_t n = 0;   // bytes folded
+    static uint64_t mix(uint64_t z) {
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    }
     void add(const void *p, size_t bytes) {
         const uint64_t *w = static_cast<const uint64_t *>(p);
-        const size_t nw = bytes / 8;
-        size_t i = 0;
-        for (; i + 4 <= nw; i += 4)
-            for (int k = 0; k < 4; ++k) h[k] = rotl(h[k] ^ (w[i + k] * 0x9FB21C651E98DF25ull), 27) * 0x9E3779B97F4A7C15ull;
-        for (; i < nw; ++i) h[i & 3] = rotl(h[i & 3] ^ (w[i] * 0x9FB21C651E98DF25ull), 27) * 0x9E3779B97F4A7C15ull;
+        const uint64_t j0 = n / 8;
+        uint64_t acc = 0;
+        for (size_t i = 0; i < bytes / 8; ++i) acc += mix(w[i] ^ mix(j0 + i + kKey));
+        sum += acc;
         n += bytes;
     }
-    uint64_t value() const {
-        uint64_t x = n * 0xFF51AFD7ED558CCDull;
-        for (int k = 0; k < 4; ++k) x = rotl(x ^ h[k], 31) * 0xC4CEB9FE1A85EC53ull;
-        return x ^ (x >> 29);
-    }
+    uint64_t value() const { return mix(sum ^ mix(n)); }
 };
 
 struct Request {
@@ -238,6 +242,8 @@ void qsim_server::worker_main(uint32_t slot) {
         }
         int status = ok ? QSIM_OK : QSIM_ERR_DEVICE;
         Digest dg;
+        // digest = 1: every request; k > 1: every k-th request by id
+        const bool digest = cfg.digest == 1 || (cfg.digest > 1 && r->id % cfg.digest == 0);
         const uint64_t n = 1ull << r->M;
         const uint64_t half = r->bytes / 2;
         uint8_t *b0 = arena.ptr(r->arena_off), *b1 = b0 + half;
@@ -278,7 +284,7 @@ void qsim_server::worker_main(uint32_t slot) {
             for (uint64_t p = 0; p < nport && status == QSIM_OK; ++p) {
                 const int k = (int)(p & 1);
                 if (hipEventSynchronize(ev[k]) != hipSuccess) { status = QSIM_ERR_DEVICE; break; }
-                if (cfg.digest) dg.add(pinned[k], cnt[k] * r->elem);
+                if (digest) dg.add(pinned[k], cnt[k] * r->elem);
                 else dg.n += cnt[k] * r->elem;
                 if (p + 2 < nport) status = issue(p + 2);
             }
@@ -287,7 +293,7 @@ void qsim_server::worker_main(uint32_t slot) {
         {
             std::lock_guard<std::mutex> lk(mu);
             r->info.status = status;
-            r->info.digest = cfg.digest ? dg.value() : 0;
+            r->info.digest = digest ? dg.value() : 0;
             r->info.bytes = dg.n;
             r->info.t_done_ns = now_ns();
             r->info.done = 1;

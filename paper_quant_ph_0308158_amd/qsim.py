@@ -493,14 +493,14 @@ class Server:
     with an HBM arena, or one request at a time with ``fcfs=True``."""
 
     def __init__(self, budget_bytes: int = 0, max_slots: int = 0, portion_entries: int = 0,
-                 fcfs: bool = False, max_bypass: int = 0, digest: bool = False):
+                 fcfs: bool = False, max_bypass: int = 0, digest=False):
         cfg = ServerConfig()
         cfg.hbm_budget_bytes = int(budget_bytes)
         cfg.max_slots = int(max_slots)
         cfg.portion_entries = int(portion_entries)
         cfg.fcfs = 1 if fcfs else 0
         cfg.max_bypass = int(max_bypass)
-        cfg.digest = 1 if digest else 0
+        cfg.digest = int(digest)     # True / 1: every request; k > 1: every k-th request by id
         h = _lib.qsim_server_create(ctypes.byref(cfg))
         if not h:
             raise QsimError(ERR_NOMEM, "qsim_server_create failed")
@@ -553,20 +553,56 @@ class Server:
         self.close()
 
 
-def digest_bytes(data: bytes) -> int:
-    """The server's 64-bit digest of a result, recomputed on the host (for
-    checking a read-back result against a reference)."""
-    M64 = (1 << 64) - 1
+_MIX1 = np.uint64(0xBF58476D1CE4E5B9)
+_MIX2 = np.uint64(0x94D049BB133111EB)
+_DIGEST_KEY = np.uint64(0x9E3779B97F4A7C15)
 
-    def rotl(x, r):
-        return ((x << r) | (x >> (64 - r))) & M64
 
-    w = np.frombuffer(data, dtype=np.uint64)
-    h = [0x9E3779B97F4A7C15, 0xC2B2AE3D27D4EB4F, 0x165667B19E3779F9, 0x27D4EB2F165667C5]
-    for i, x in enumerate(w.tolist()):
-        k = i & 3
-        h[k] = (rotl(h[k] ^ ((x * 0x9FB21C651E98DF25) & M64), 27) * 0x9E3779B97F4A7C15) & M64
-    x = (len(data) * 0xFF51AFD7ED558CCD) & M64
-    for k in range(4):
-        x = (rotl(x ^ h[k], 31) * 0xC4CEB9FE1A85EC53) & M64
-    return x ^ (x >> 29)
+def _mix(z: np.ndarray) -> np.ndarray:
+    """SplitMix64's finaliser on a uint64 array (products wrap mod 2^64)."""
+    z = (z ^ (z >> np.uint64(30))) * _MIX1
+    z = (z ^ (z >> np.uint64(27))) * _MIX2
+    return z ^ (z >> np.uint64(31))
+
+
+class Digest:
+    """Host-side copy of the server's result digest (qsim_request_info.digest),
+    for checking a result read back some other way: the sum mod 2^64 over
+    the result's 8-byte words w_j of mix(w_j ^ mix(j + key)), then mixed
+    with the byte count.  Portions are added in row order."""
+
+    def __init__(self):
+        self.sum = 0
+        self.n = 0
+
+    def add(self, data, chunk_words: int = 1 << 21, threads: int = 8):
+        w = np.frombuffer(data, dtype=np.uint64) if isinstance(data, (bytes, bytearray, memoryview)) \
+            else np.ascontiguousarray(data).view(np.uint64).ravel()
+        j0 = self.n // 8
+
+        def part_sum(off):
+            part = w[off:off + chunk_words]
+            with np.errstate(over="ignore"):
+                j = np.arange(j0 + off, j0 + off + len(part), dtype=np.uint64) + _DIGEST_KEY
+                return int(_mix(part ^ _mix(j)).sum(dtype=np.uint64))
+
+        offs = range(0, len(w), chunk_words)
+        if len(offs) > 1 and threads > 1:
+            from concurrent.futures import ThreadPoolExecutor
+            with ThreadPoolExecutor(max_workers=threads) as ex:   # numpy releases the GIL
+                total = sum(ex.map(part_sum, offs))
+        else:
+            total = sum(part_sum(o) for o in offs)
+        self.sum = (self.sum + total) & ((1 << 64) - 1)
+        self.n += 8 * len(w)
+        return self
+
+    def value(self) -> int:
+        with np.errstate(over="ignore"):
+            n = _mix(np.array([self.n], dtype=np.uint64))[0]
+            return int(_mix(np.array([np.uint64(self.sum) ^ n], dtype=np.uint64))[0])
+
+
+def digest_bytes(data) -> int:
+    """The server's digest of a whole result (bytes or a numpy array)."""
+    return Digest().add(data).value()

@@ -356,37 +356,6 @@ def test_m26_config_full(q):
     assert_same(k2, ref, "m26 config")
 
 
-def test_m32_config_sampled(q):
-    """M=32, complex64 (32 GiB per buffer), L=1000, 1..3 controls: sampled
-    rows against the oracle's row map, then the involution on the device."""
-    import torch
-    M = 32
-    tg, cm = W.m32_config()
-    say("m32: generate")
-    k1_dev = W.gaussian_state_torch(M, "c64", seed=W.SEED_M32)
-    rng = np.random.default_rng(32)
-    rows = np.concatenate([rng.integers(0, 1 << M, size=2000, dtype=np.uint64),
-                           np.arange(64, dtype=np.uint64),
-                           (1 << M) - 1 - np.arange(64, dtype=np.uint64)])
-    src_rows = np.array([oracle.source_index(M, tg, cm, int(i)) for i in rows], dtype=np.int64)
-    expect = k1_dev.view(torch.int64)[torch.from_numpy(src_rows).cuda()].cpu().numpy()
-    b1 = torch.empty_like(k1_dev)
-    s = q.State(M, "c64", buffers=(k1_dev, b1))
-    say("m32: apply")
-    s.apply(tg, cm)
-    torch.cuda.synchronize()
-    cur = k1_dev if s.current_ptr() == k1_dev.data_ptr() else b1
-    got = cur.view(torch.int64)[torch.from_numpy(rows.astype(np.int64)).cuda()].cpu().numpy()
-    np.testing.assert_array_equal(got, expect)
-    say("m32: involution")
-    s.apply(tg[::-1].copy(), cm[::-1].copy())
-    torch.cuda.synchronize()
-    cur = k1_dev if s.current_ptr() == k1_dev.data_ptr() else b1
-    s.close()
-    k1_again = W.gaussian_state_torch(M, "c64", seed=W.SEED_M32)
-    assert torch.equal(cur.view(torch.int64), k1_again.view(torch.int64))
-
-
 # ------------------------------------------------------------------ serving
 
 def _server_requests(seed, n, m_range, l_max):
