@@ -69,10 +69,10 @@ def workload(name: str):
     raise ValueError(name)
 
 
-def stored_traffic(wl_name: str):
-    """HBM bytes per tile-pass launch from the committed rocprofv3 counter
+def stored_traffic(wl_name: str, kernel: str = "k_tile"):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary, if it was taken on the current kernel source."""
-    path = os.path.join(PROFILES, f"k_tile_{wl_name}_pmc.md")
+    path = os.path.join(PROFILES, f"{kernel}_{wl_name}_pmc.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
@@ -162,9 +162,11 @@ def cpu_configs(reps: int = 3):
 def bench_batched(reps: int = 3, plain_too: bool = True, autotune: bool = True):
     """The batched configuration: 4096 independent circuits (M uniform in
     8..20, L uniform in 10..500, 0..3 controls, complex64), all states
-    resident on the device.  Timed three ways on the same states and
+    resident on the device.  Timed two ways on the same states and
     circuits, each including host planning: plain (one qsim_apply_steps per
-    circuit, serially on one stream) and batched (one qsim_apply_batch)."""
+    circuit, serially on one stream, over `reps` rounds) and batched (one
+    qsim_apply_batch per round, 20 rounds back to back).  The kernel's own
+    time per launch comes from qsim_batch_last_info."""
     import torch
     import workloads as W
     from paper_quant_ph_0308158_amd import qsim
@@ -184,25 +186,43 @@ def bench_batched(reps: int = 3, plain_too: bool = True, autotune: bool = True):
     def batched():
         qsim.apply_batch_packed(states, batch)
 
-    # the batch autotuner picks the tiles per queue item (states unchanged)
-    tiles, tune_s = None, None
+    # the batch autotuner picks the batched-mode parameters (states unchanged)
+    tuned, tune_s = None, None
     if autotune:
         t0 = time.perf_counter()
-        tiles = qsim.batch_autotune(states, batch)
+        tuned = qsim.batch_autotune(states, batch)
         tune_s = time.perf_counter() - t0
     out = {"plain": None}
-    for name, fn in (("plain", plain), ("batched", batched)):
+    # batches back to back (20 of them: the host plans each batch while the
+    # device runs the one before, so one batch's host time is spread over
+    # the run); the plain comparator over `reps` rounds
+    for name, fn, k in (("plain", plain, reps), ("batched", batched, 20)):
         if name == "plain" and not plain_too:
             continue
         fn()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(reps):
+        for _ in range(k):
             fn()
         torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / reps
+        dt = (time.perf_counter() - t0) / k
         out[name] = {"ms": round(dt * 1e3, 3), "updates_per_s": updates / dt}
     qsim.batch_status()
+    # the kernel's own time, launch by launch (HIP events on its stream)
+    infos = []
+    for _ in range(reps):
+        batched()
+        infos.append(qsim.batch_last_info())
+    qsim.batch_status()
+    info = infos[-1]
+    kernel_ms = sum(i["kernel_ms"] for i in infos) / len(infos)
+    achieved = info["algorithmic_bytes"] / (kernel_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": "k_batch", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                "traffic": stored_traffic("batched_4096", kernel="k_batch"),
+                "algorithmic_bytes_per_launch": int(info["algorithmic_bytes"]), "avg_launch_ms": round(kernel_ms, 4),
+                "launches": len(infos), "passes": info["passes"], "items": info["items"],
+                "workgroups": info["workgroups"]}
     for st in states:
         st.close()
     # a plain copy of a known size in the same process: the reference that
@@ -215,7 +235,10 @@ def bench_batched(reps: int = 3, plain_too: bool = True, autotune: bool = True):
     del a, b
     return {"workload": "batched_4096_M8-20_L10-500_c64", "circuits": len(circuits),
             "amplitude_step_updates": updates, "plain": out["plain"], "batched": out["batched"],
-            "autotune": {"tiles_per_item": tiles, "seconds": round(tune_s, 2) if tune_s else None},
+            "roofline": roofline, "tuning": info["tuning"],
+            "autotune": ({"chosen": {k: tuned[k] for k in qsim.BATCH_TUNING_FIELDS}, "from_cache": tuned["from_cache"],
+                          "seconds": round(tune_s, 2), "batch_ms_chosen": round(tuned["best_ms"], 3),
+                          "batch_ms_defaults": round(tuned["default_ms"], 3)} if tuned else None),
             "speedup_vs_plain": round(out["plain"]["ms"] / out["batched"]["ms"], 2) if out["plain"] else None}
 
 

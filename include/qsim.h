@@ -259,25 +259,86 @@ int qsim_apply_batch(qsim_state *const *states, const qsim_step *const *steps,
  * and uploads one batch's plan while the previous batch runs. */
 int qsim_batch_last_status(void);
 
-/* (No passage of the paper: a launch parameter of batched mode.)  Tiles of
- * one pass that a queue item of the batched kernel covers (1..256;
- * 0 restores the default, 32).  Larger items mean fewer completion
- * handshakes, smaller ones a shorter tail at the end of each pass.
- * Process-wide; applies to later qsim_apply_batch calls.  QSIM_ERR_INVALID
- * above 256. */
+/* Launch parameters of batched mode (no passage of the paper: how the
+ * circuits of one launch are cut into queue items).  Zero in any field
+ * selects the default. */
+typedef struct {
+    uint32_t tiles_per_item; /* tiles of one pass per queue item (1..256;
+                                default 32): larger items mean fewer
+                                completion handshakes, smaller ones more
+                                workgroups on each pass                   */
+    uint32_t tile_bits;      /* log2 entries per tile of the tiled circuits
+                                (10..13; default 13 for QSIM_C64, 12 for
+                                QSIM_C128); circuits with M <= tile_bits run
+                                whole in one workgroup's LDS              */
+    uint32_t circuit_tiles;  /* circuits whose passes have at most this many
+                                tiles run every pass in one workgroup (one
+                                queue item, no waits between passes);
+                                default 32; 1 = none                      */
+    uint32_t plan_search;    /* pass planning of each circuit: 1 = greedy
+                                scan (default), 2 = with the mask climb
+                                (fewer passes, more host time)            */
+    uint32_t order;          /* queue order: 1 = pass level by pass level,
+                                2 = critical path first (default): the host
+                                simulates the resident workgroups taking
+                                items and queues first the ready item with
+                                the longest remaining chain of passes     */
+    uint32_t from_cache;     /* output of qsim_batch_autotune: 1 when the
+                                setting came from the tuning cache        */
+    float best_ms;           /* output of qsim_batch_autotune: measured time
+                                per batch of the chosen setting in a long
+                                run of batches, the larger of the kernel's
+                                device time and the host's enqueue time
+                                (0 when taken from the cache)             */
+    float default_ms;        /* the same for the defaults                  */
+} qsim_batch_tuning;
+
+/* Set (t != NULL) or reset (NULL) the batched-mode parameters used by
+ * later qsim_apply_batch calls on states of `dtype`.  Process-wide.
+ * QSIM_ERR_INVALID on out-of-range values. */
+int qsim_batch_set_tuning(qsim_dtype dtype, const qsim_batch_tuning *t);
+int qsim_batch_get_tuning(qsim_dtype dtype, qsim_batch_tuning *out);
+
+/* Shorthands for the tiles_per_item field, for both dtypes (0 restores the
+ * default).  QSIM_ERR_INVALID above 256. */
 int qsim_batch_set_tiles_per_item(uint32_t tiles);
 uint32_t qsim_batch_tiles_per_item(void);
 
-/* Choose the tiles per queue item for a batch by measurement: for each
- * candidate (4, 8, 16, 32, 64) the batch is applied, then the batch of
- * reversed diagrams, which undoes it (every step is its own inverse,
- * Sec. 2(a)), and the pair is timed; the fastest becomes the process-wide
- * setting and is stored to *tiles_out (may be NULL).  Arguments as for
- * qsim_apply_batch; the states' contents are unchanged on return.
- * Synchronous. */
+/* Choose the batched-mode parameters for a batch by measurement (Sec. 2(a):
+ * each trial applies the batch and then the batch of reversed diagrams,
+ * which undoes it, since every step matrix is its own inverse; the states'
+ * contents are unchanged on return).  Starting from the defaults, one
+ * parameter at a time takes each of its candidate values (queue order,
+ * tile size, planning, whole-circuit cut-off, tiles per item) and keeps
+ * the fastest, by the time per batch of a long run of batches (the host
+ * plans each batch while the device runs the one before, so the larger of
+ * the two); the result becomes the setting for the batch's dtype and is
+ * copied to *out (may be NULL).  When the environment variable
+ * QSIM_TUNING_CACHE names a file, the choice is looked up there first under
+ * the key (device architecture, dtype, range of M, range of L rounded out
+ * to powers of two) and, when measured, stored there (a JSON object).
+ * Arguments as for qsim_apply_batch.  Synchronous. */
 int qsim_batch_autotune(qsim_state *const *states, const qsim_step *const *steps,
                         const uint64_t *Ls, uint32_t n, void *hip_stream,
-                        uint32_t *tiles_out);
+                        qsim_batch_tuning *out);
+
+/* What the last qsim_apply_batch launch did (waits for it): circuits,
+ * queue items, tiled passes (whole-in-LDS circuits count one pass each),
+ * the algorithmic bytes (one read and one write of a circuit's state per
+ * pass, summed), the kernel's device time from HIP events recorded on its
+ * stream, and the parameters it ran with.  QSIM_ERR_INVALID if no batch
+ * has run. */
+typedef struct {
+    uint32_t circuits;
+    uint32_t items;
+    uint32_t passes;
+    uint32_t workgroups;       /* workgroups of the launch                  */
+    uint64_t algorithmic_bytes;
+    double kernel_ms;
+    qsim_batch_tuning tuning;
+} qsim_batch_info;
+
+int qsim_batch_last_info(qsim_batch_info *out);
 
 /* ---------------------------------------------------------------- serving */
 

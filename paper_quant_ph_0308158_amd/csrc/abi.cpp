@@ -10,7 +10,10 @@
 #include <atomic>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <queue>
+#include <cmath>
 #include <new>
 #include <string>
 #include <vector>
@@ -789,25 +792,66 @@ namespace {
 
 // ------------------------------------------------------------ batched mode
 
+// Launch parameters of batched mode for one dtype (qsim_batch_tuning).
+struct BatchTune {
+    uint32_t tiles_per_item = 32;
+    uint32_t tile_bits = 0;        // 0: 13 for 8-byte entries, 12 for 16-byte ones
+    uint32_t circuit_tiles = 32;   // measured: 32 15.46 ms, 16 15.57, 8 15.67 per 4096-circuit batch
+    uint32_t plan_search = 1;      // 1 greedy scan, 2 with the mask climb
+    uint32_t order = 2;            // 1 level by level, 2 critical path first
+};
+
+uint32_t batch_tile_bits(const BatchTune &t, uint32_t elem) { return t.tile_bits ? t.tile_bits : (elem == 8 ? 13u : 12u); }
+
+void export_batch_tune(const BatchTune &t, uint32_t elem, qsim_batch_tuning *out) {
+    std::memset(out, 0, sizeof(*out));
+    out->tiles_per_item = t.tiles_per_item;
+    out->tile_bits = batch_tile_bits(t, elem);
+    out->circuit_tiles = t.circuit_tiles;
+    out->plan_search = t.plan_search;
+    out->order = t.order;
+}
+
+int batch_tune_from(const qsim_batch_tuning *in, BatchTune *out) {
+    BatchTune t;
+    if (in) {
+        if (in->tiles_per_item) t.tiles_per_item = in->tiles_per_item;
+        if (in->tile_bits) t.tile_bits = in->tile_bits;
+        if (in->circuit_tiles) t.circuit_tiles = in->circuit_tiles;
+        if (in->plan_search) t.plan_search = in->plan_search;
+        if (in->order) t.order = in->order;
+    }
+    if (t.tiles_per_item > kBatchTilesMax) return fail(QSIM_ERR_INVALID, "tiles_per_item above 256");
+    if (t.tile_bits && (t.tile_bits < 10 || t.tile_bits > 13)) return fail(QSIM_ERR_INVALID, "batch tile_bits out of 10..13");
+    if (t.circuit_tiles > kBatchTilesMax) return fail(QSIM_ERR_INVALID, "circuit_tiles above 256");
+    if (t.plan_search < 1 || t.plan_search > 2) return fail(QSIM_ERR_INVALID, "batch plan_search must be 1 or 2");
+    if (t.order < 1 || t.order > 2) return fail(QSIM_ERR_INVALID, "batch order must be 1 or 2");
+    *out = t;
+    return QSIM_OK;
+}
+
 // Process-wide workspace of the batched launch, in two slots used in turn:
 // while one batch's kernel runs, the next batch's plan is uploaded into the
 // other slot on a side stream, ordered by events (the upload waits until
 // the slot's previous kernel is done; the kernel waits for its upload).
 struct BatchSlot {
     DevBuf ws;          // counters, items, pass and circuit descriptors, step arrays
-    DevBuf rec;         // tile-map records of every pass
     HostStage stage;    // pinned staging of the upload
     uint32_t *hdr = nullptr;          // pinned copy of the counter header, written after the kernel
     hipEvent_t uploaded = nullptr;    // upload finished
     hipEvent_t done = nullptr;        // kernel and header copy finished
+    hipEvent_t k0 = nullptr, k1 = nullptr;   // around the kernel (timing)
     bool pending = false;
+    bool timed = false;
+    qsim_batch_info info{};
 };
 
 struct BatchWorkspace {
     std::mutex mu;
-    std::atomic<uint32_t> tiles_per_item{kBatchTiles};   // qsim_batch_set_tiles_per_item / qsim_batch_autotune
+    BatchTune tune[2];                // per dtype (qsim_batch_set_tuning / qsim_batch_autotune)
     BatchSlot slot[2];
     int next = 0;                     // slot of the next batch
+    int last = -1;                    // slot of the last batch launched
     hipStream_t upload = nullptr;     // side stream for plan uploads (default priority)
     int device = -1;                  // device the streams and buffers belong to
     int status = QSIM_OK;             // first failure since the last status query
@@ -818,7 +862,8 @@ BatchWorkspace &batch_ws() {
     return w;
 }
 
-// Wait for a slot's launch and fold its error flag into the sticky status.
+// Wait for a slot's launch, fold its error flag into the sticky status and
+// read its kernel time.
 void batch_collect(BatchWorkspace &w, BatchSlot &b) {
     if (!b.pending) return;
     b.pending = false;
@@ -826,6 +871,10 @@ void batch_collect(BatchWorkspace &w, BatchSlot &b) {
     int rc = QSIM_OK;
     if (e != hipSuccess) rc = fail(QSIM_ERR_DEVICE, std::string("batch: ") + hipGetErrorString(e));
     else if (b.hdr[2]) rc = fail(QSIM_ERR_DEVICE, "batch: a dependency wait timed out; results are invalid");
+    if (rc == QSIM_OK && b.timed) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, b.k0, b.k1) == hipSuccess) b.info.kernel_ms = ms;
+    }
     if (rc != QSIM_OK && w.status == QSIM_OK) w.status = rc;
 }
 
@@ -848,12 +897,94 @@ struct BatchCircuitPlan {
     std::string err;
 };
 
+// Queue order of batched mode by list scheduling: the resident workgroups
+// are simulated taking items in turn, each item ready once the previous
+// pass of its circuit has finished (plus a little slack, so that the real
+// workgroup rarely arrives before its predecessor's last tile is done),
+// and among the ready items the one with the longest remaining chain (its
+// own time plus that of the later passes of its circuit) goes first.
+// Times are estimates in units of one tile (a tile item: its tiles; a
+// whole circuit: all of its tiles; a small circuit: its share of a tile)
+// plus a fixed cost per item.  The GPU takes items in the resulting order;
+// an item whose predecessor has not finished after all only waits longer,
+// so an estimate error costs time, never correctness (every item's
+// predecessors come earlier in the order).
+struct SimItem {
+    uint64_t word;          // queue entry
+    float dur;              // estimated duration
+    float prio;             // remaining chain, itself included
+    uint32_t next_pass;     // first item of the next pass of its circuit (~0u: none)
+    uint32_t pass_id;       // pass of the item (~0u: independent item)
+};
+
+std::vector<uint64_t> order_critical_path(const std::vector<SimItem> &items, const std::vector<uint32_t> &pass_items,
+                                          const std::vector<uint32_t> &pass_first, uint64_t workers, float slack) {
+    // pass_items[p] = items of pass p, pass_first[p] = index of its first item
+    // (the items of a pass are consecutive)
+    std::vector<uint32_t> left(pass_items);
+    auto cmp = [&](uint32_t a, uint32_t b) {   // max-heap on prio, then creation order
+        if (items[a].prio != items[b].prio) return items[a].prio < items[b].prio;
+        return a > b;
+    };
+    std::vector<uint32_t> ready;
+    ready.reserve(items.size());
+    std::vector<uint8_t> has_pred(items.size(), 0);
+    for (const SimItem &it : items)
+        if (it.next_pass != ~0u) has_pred[it.next_pass] = 1;
+    for (uint32_t i = 0; i < items.size(); ++i) {
+        const uint32_t p = items[i].pass_id;
+        // ready at the start: independent items and the first pass of each chain
+        const bool dependent = p != ~0u && has_pred[pass_first[p]];
+        if (!dependent) ready.push_back(i);
+    }
+    std::make_heap(ready.begin(), ready.end(), cmp);
+    using Ev = std::pair<float, uint32_t>;   // (time, item): item finishes, or (with the top bit) a pass becomes ready
+    std::priority_queue<Ev, std::vector<Ev>, std::greater<Ev>> events;
+    std::vector<uint64_t> order;
+    order.reserve(items.size());
+    float now = 0;
+    uint64_t free_w = std::max<uint64_t>(workers, 1);
+    while (order.size() < items.size()) {
+        while (free_w > 0 && !ready.empty()) {
+            std::pop_heap(ready.begin(), ready.end(), cmp);
+            const uint32_t i = ready.back();
+            ready.pop_back();
+            order.push_back(items[i].word);
+            events.push({now + items[i].dur, i});
+            --free_w;
+        }
+        if (events.empty()) break;   // cannot happen: every pass follows one that finishes
+        const Ev ev = events.top();
+        events.pop();
+        now = ev.first;
+        if (ev.second & 0x80000000u) {   // the next pass of a chain becomes ready
+            const uint32_t f = ev.second & 0x7FFFFFFFu, p = items[f].pass_id;
+            for (uint32_t j = f; j < f + pass_items[p]; ++j) {
+                ready.push_back(j);
+                std::push_heap(ready.begin(), ready.end(), cmp);
+            }
+            continue;
+        }
+        ++free_w;
+        const SimItem &it = items[ev.second];
+        if (it.pass_id != ~0u && --left[it.pass_id] == 0 && it.next_pass != ~0u)
+            events.push({now + slack, it.next_pass | 0x80000000u});
+    }
+    return order;
+}
+
 int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, const uint64_t *Ls, uint32_t n,
                   hipStream_t st) {
     const uint32_t elem = states[0]->elem;
-    const uint32_t tb = elem == 8 ? 8u : 7u;      // 2^13 (8 B) / 2^12 (16 B) entries per tile
-    const uint32_t Kb = tb + 5;
-    const uint32_t threads = 1u << tb;
+    BatchWorkspace &w = batch_ws();
+    BatchTune tune;
+    {
+        std::lock_guard<std::mutex> lk(w.mu);
+        tune = w.tune[elem == 8 ? 0 : 1];
+    }
+    const uint32_t Kb = batch_tile_bits(tune, elem);
+    const uint32_t tb = Kb - 5;
+    if ((size_t)elem << Kb > 128 * 1024) return fail(QSIM_ERR_INVALID, "batch tiles above 128 KiB of LDS");
 
     // Phase timings on stderr when QSIM_TRACE_BATCH is set.
     const bool trace = std::getenv("QSIM_TRACE_BATCH") != nullptr;
@@ -891,7 +1022,7 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
             pc.low_bits = std::min(pc.low_bits, (int)Kb);
             pc.mid_low_bits = std::min(pc.mid_low_bits, pc.low_bits);
             pc.threads = 1;   // circuits are already planned on several threads
-            if (pc.search < 0 && s->M >= 30) pc.search = 1;   // batch planning: the climb alone
+            pc.search = (tune.plan_search == 2 || s->M >= 30) ? 1 : 0;   // never the beam search here
             try {
                 std::vector<Pass> passes = plan_passes(s->M, sl.tg.data(), sl.cm.data(), sl.kd.data(), L, pc);
                 bp.rc = prepare_passes(s->M, elem, passes, sl.tg.data(), sl.cm.data(), sl.kd.data(),
@@ -919,17 +1050,20 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
         if (plans[c].rc) return fail(plans[c].rc, "circuit " + std::to_string(c) + ": " + plans[c].err);
     lap("plan");
 
-    // 2. lay out the workspace: header counters, items, passes, smalls, blob
+    // 2. descriptors: passes of the tiled circuits, the small circuits,
+    // and where each circuit's blob goes
     std::vector<BatchPass> bpass;
     std::vector<BatchSmall> bsmall;
     std::vector<size_t> small_blob_off, pass_blob_off;   // per entry: offset of its circuit blob
     std::vector<uint32_t> small_circuit;
     std::vector<std::pair<uint32_t, uint32_t>> circuit_first_pass;   // (circuit, index of its first pass)
-    std::vector<size_t> pass_rec_off;                     // word offset of each pass's records
     std::vector<size_t> circuit_blob_off(n, 0);
-    size_t blob_size = 0, rec_words_total = 0;
-    uint32_t max_level = 0;
+    size_t blob_size = 0;
+    uint32_t rec_stride = 2;
+    uint64_t max_tiles = 0;
     bool any_sign = false;   // some tile or small item has phase steps
+    uint64_t alg_bytes = 0;
+    uint32_t n_passes = 0;
     for (uint32_t c = 0; c < n; ++c) {
         circuit_blob_off[c] = blob_size;
         blob_size += (plans[c].pr.blob.size() + 255) & ~size_t(255);
@@ -938,6 +1072,7 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
         BatchCircuitPlan &bp = plans[c];
         qsim_state *s = states[c];
         if (bp.pr.launches.empty()) continue;
+        const uint64_t state_bytes = (uint64_t)elem << s->M;
         if (bp.direct || bp.small) {
             const Launch &l = bp.pr.launches[0];
             BatchSmall sm{};
@@ -951,12 +1086,18 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
             bsmall.push_back(sm);
             small_blob_off.push_back(circuit_blob_off[c] + (bp.direct ? l.steps_off : l.inner_off));
             small_circuit.push_back(c);
+            alg_bytes += 2 * state_bytes;
+            ++n_passes;
             continue;
         }
         uint32_t level = 0;
         circuit_first_pass.push_back({c, (uint32_t)bpass.size()});
+        const uint64_t n_tiles = 1ull << (s->M - Kb);
         for (size_t i = 0; i + 1 < bp.pr.launches.size(); i += 2, ++level) {
             const Launch &lm = bp.pr.launches[i], &lt = bp.pr.launches[i + 1];
+            // every pass of a circuit has 2^(M - tile bits) tiles of one shape
+            if (lt.n_tiles != n_tiles || lt.ta.tb != tb || lt.ta.eb != 5)
+                return fail(QSIM_ERR_INVALID, "circuit " + std::to_string(c) + ": a pass has another tile shape");
             BatchPass p{};
             p.ta = lt.ta;
             any_sign |= p.ta.sign != 0;
@@ -970,55 +1111,109 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
             pass_blob_off.push_back(circuit_blob_off[c]);
             // remember both step-array offsets inside the circuit blob
             bpass.back().ta.inner = reinterpret_cast<const uint32_t *>(lt.inner_off);
+            bpass.back().ta.rec = nullptr;
             bpass.back().tm.steps = reinterpret_cast<const TmStep *>(lm.steps_off);
-            pass_rec_off.push_back(rec_words_total);
-            rec_words_total += (size_t)lt.n_tiles * lt.ta.rec_words;
+            bpass.back().tm.rec = nullptr;
+            rec_stride = std::max(rec_stride, lt.ta.rec_words);
+            alg_bytes += 2 * state_bytes;
+            ++n_passes;
         }
-        max_level = std::max(max_level, level);
+        // the per-circuit counter counts every finished tile of the circuit
+        if ((uint64_t)level * n_tiles > 0xFFFFFFFFull)
+            return fail(QSIM_ERR_INVALID, "circuit " + std::to_string(c) + ": passes x tiles beyond 2^32 - 1");
+        max_tiles = std::max(max_tiles, n_tiles);
     }
 
-    // 3. the queue: record blocks, then tiles level by level with the small
-    // circuits spread between the levels as fillers (every item's
-    // dependencies come earlier in the queue).  A circuit whose passes have
-    // few tiles runs whole in one workgroup (one item for all its passes,
-    // placed over the first half of the levels): as one item per pass it
-    // would wait at every level for its previous pass.
-    std::vector<uint64_t> items;
-    uint32_t n_rec_blocks = 0;
-    for (size_t g = 0; g < bpass.size(); ++g) {
-        const uint64_t nb = (bpass[g].n_tiles + threads - 1) / threads;
-        for (uint64_t b = 0; b < nb; ++b) items.push_back(batch_item(kItemRec, (uint32_t)g, (uint32_t)b));
-        n_rec_blocks += (uint32_t)nb;
-    }
-    std::vector<uint64_t> whole;                     // kItemCircuit items
-    std::vector<uint8_t> in_whole(bpass.size(), 0);
+    // 3. the items: one per small circuit, one per mid-size circuit (every
+    // pass in one workgroup: no waits between its passes), and blocks of
+    // tiles_per_item tiles of each pass of the others
+    const uint32_t tpi = std::max<uint32_t>(1, tune.tiles_per_item);
+    std::vector<uint8_t> whole_circ(circuit_first_pass.size(), 0);
+    for (size_t k = 0; k < circuit_first_pass.size(); ++k)
+        whole_circ[k] = bpass[circuit_first_pass[k].second].n_tiles <= tune.circuit_tiles;
+    uint64_t rec_tiles = 0;   // tiles whose records one item holds in LDS at once
     for (size_t k = 0; k < circuit_first_pass.size(); ++k) {
-        const uint32_t g0 = circuit_first_pass[k].second;
-        const uint32_t g1 = k + 1 < circuit_first_pass.size() ? circuit_first_pass[k + 1].second
-                                                                : (uint32_t)bpass.size();
-        if (g1 == g0 || bpass[g0].n_tiles > kBatchCircuitTiles) continue;
-        whole.push_back(batch_item(kItemCircuit, g0, g1 - g0));
-        for (uint32_t g = g0; g < g1; ++g) in_whole[g] = 1;
+        const uint64_t nt = bpass[circuit_first_pass[k].second].n_tiles;
+        rec_tiles = std::max<uint64_t>(rec_tiles, whole_circ[k] ? nt : std::min<uint64_t>(nt, tpi));
     }
-    std::vector<std::vector<uint32_t>> by_level(max_level);
-    for (size_t g = 0; g < bpass.size(); ++g)
-        if (!in_whole[g]) by_level[bpass[g].level].push_back((uint32_t)g);
-    const uint32_t tpi = batch_ws().tiles_per_item.load();
+    const size_t lds = ((size_t)elem << Kb) + (size_t)rec_tiles * rec_stride * 4;
+    if (lds > 160 * 1024) return fail(QSIM_ERR_INVALID, "batch: tile and records need more LDS than a workgroup has");
+    uint64_t workers = 0;
+    hipError_t e = batch_grid(elem, tb, any_sign, lds, &workers);
+    if (e != hipSuccess) return fail(QSIM_ERR_DEVICE, std::string("batch occupancy: ") + hipGetErrorString(e));
+
+    std::vector<uint64_t> items;
     const size_t n_small = bsmall.size();
-    size_t small_next = 0, whole_next = 0;
-    const size_t levels = std::max<size_t>(max_level, 1), whole_levels = (levels + 1) / 2;
-    for (size_t lv = 0; lv < levels; ++lv) {
-        if (lv < by_level.size())
-            for (uint32_t g : by_level[lv])
-                for (uint64_t t = 0; t * tpi < bpass[g].n_tiles; ++t)
-                    items.push_back(batch_item(kItemTile, g, (uint32_t)t));
-        const size_t wupto = whole.size() * std::min(lv + 1, whole_levels) / whole_levels;
-        for (; whole_next < wupto; ++whole_next) items.push_back(whole[whole_next]);
-        const size_t upto = n_small * (lv + 1) / levels;
-        for (; small_next < upto; ++small_next) items.push_back(batch_item(kItemSmall, (uint32_t)small_next, 0));
+    if (tune.order == 2) {
+        std::vector<SimItem> sim;
+        std::vector<uint32_t> pass_items, pass_first;
+        const float kItemCost = 0.25f;   // per-item cost in tiles (wait, drain, first load)
+        const float kSlack = 2.0f;       // a pass's successors become ready this many tiles after it ends
+        for (size_t k = 0; k < n_small; ++k) {
+            const float d = std::ldexp(1.0f, (int)bsmall[k].M - (int)Kb) + kItemCost;
+            sim.push_back({batch_item(kItemSmall, (uint32_t)k, 0), d, d, ~0u, ~0u});
+        }
+        for (size_t k = 0; k < circuit_first_pass.size(); ++k) {
+            const uint32_t g0 = circuit_first_pass[k].second;
+            const uint32_t g1 = k + 1 < circuit_first_pass.size() ? circuit_first_pass[k + 1].second
+                                                                    : (uint32_t)bpass.size();
+            const uint64_t nt = bpass[g0].n_tiles;
+            if (whole_circ[k]) {
+                const float d = (float)(g1 - g0) * ((float)nt + kItemCost);
+                sim.push_back({batch_item(kItemCircuit, g0, g1 - g0), d, d, ~0u, ~0u});
+                continue;
+            }
+            const float pass_d = (float)std::min<uint64_t>(nt, tpi) + kItemCost + kSlack;
+            uint32_t prev_first = ~0u;
+            for (uint32_t g = g0; g < g1; ++g) {
+                const uint32_t first = (uint32_t)sim.size(), pid = (uint32_t)pass_items.size();
+                const float remaining = (float)(g1 - g) * pass_d;
+                for (uint64_t t = 0; t * tpi < nt; ++t) {
+                    const float d = (float)std::min<uint64_t>(tpi, nt - t * tpi) + kItemCost;
+                    sim.push_back({batch_item(kItemTile, g, (uint32_t)t), d, remaining, ~0u, pid});
+                }
+                pass_items.push_back((uint32_t)sim.size() - first);
+                pass_first.push_back(first);
+                if (prev_first != ~0u)
+                    for (uint32_t j = prev_first; j < first; ++j) sim[j].next_pass = first;
+                prev_first = first;
+            }
+        }
+        items = order_critical_path(sim, pass_items, pass_first, workers, kSlack);
+        if (items.size() != sim.size()) return fail(QSIM_ERR_INVALID, "batch: queue ordering failed");
+    } else {
+        // level by level, with the small circuits spread between the levels
+        // and the mid-size ones over the first half of them
+        uint32_t max_level = 0;
+        for (const BatchPass &p : bpass) max_level = std::max(max_level, p.level + 1);
+        std::vector<uint64_t> whole;
+        std::vector<uint8_t> in_whole(bpass.size(), 0);
+        for (size_t k = 0; k < circuit_first_pass.size(); ++k) {
+            if (!whole_circ[k]) continue;
+            const uint32_t g0 = circuit_first_pass[k].second;
+            const uint32_t g1 = k + 1 < circuit_first_pass.size() ? circuit_first_pass[k + 1].second
+                                                                    : (uint32_t)bpass.size();
+            whole.push_back(batch_item(kItemCircuit, g0, g1 - g0));
+            for (uint32_t g = g0; g < g1; ++g) in_whole[g] = 1;
+        }
+        std::vector<std::vector<uint32_t>> by_level(max_level);
+        for (size_t g = 0; g < bpass.size(); ++g)
+            if (!in_whole[g]) by_level[bpass[g].level].push_back((uint32_t)g);
+        size_t small_next = 0, whole_next = 0;
+        const size_t levels = std::max<size_t>(max_level, 1), whole_levels = (levels + 1) / 2;
+        for (size_t lv = 0; lv < levels; ++lv) {
+            if (lv < by_level.size())
+                for (uint32_t g : by_level[lv])
+                    for (uint64_t t = 0; t * tpi < bpass[g].n_tiles; ++t)
+                        items.push_back(batch_item(kItemTile, g, (uint32_t)t));
+            const size_t wupto = whole.size() * std::min(lv + 1, whole_levels) / whole_levels;
+            for (; whole_next < wupto; ++whole_next) items.push_back(whole[whole_next]);
+            const size_t upto = n_small * (lv + 1) / levels;
+            for (; small_next < upto; ++small_next) items.push_back(batch_item(kItemSmall, (uint32_t)small_next, 0));
+        }
+        for (; whole_next < whole.size(); ++whole_next) items.push_back(whole[whole_next]);
+        for (; small_next < n_small; ++small_next) items.push_back(batch_item(kItemSmall, (uint32_t)small_next, 0));
     }
-    for (; whole_next < whole.size(); ++whole_next) items.push_back(whole[whole_next]);
-    for (; small_next < n_small; ++small_next) items.push_back(batch_item(kItemSmall, (uint32_t)small_next, 0));
     if (items.size() > 0xFFFFFFF0ull) return fail(QSIM_ERR_INVALID, "batch too large");
     lap("queue");
 
@@ -1029,23 +1224,21 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
     const size_t blob_off = (small_off + bsmall.size() * sizeof(BatchSmall) + 255) & ~size_t(255);
     const size_t total = blob_off + blob_size;
 
-    BatchWorkspace &w = batch_ws();
     std::lock_guard<std::mutex> lk(w.mu);
-    hipError_t e;
     if (w.device != states[0]->device) {
         // the workspace moves to this device: finish and free what it held
         for (BatchSlot &b : w.slot) {
             batch_collect(w, b);
             b.ws.release();
-            b.rec.release();
             b.stage.release();
             if (b.hdr) (void)hipHostFree(b.hdr);
-            if (b.uploaded) (void)hipEventDestroy(b.uploaded);
-            if (b.done) (void)hipEventDestroy(b.done);
+            for (hipEvent_t ev : {b.uploaded, b.done, b.k0, b.k1})
+                if (ev) (void)hipEventDestroy(ev);
             b = BatchSlot{};
         }
         if (w.upload) (void)hipStreamDestroy(w.upload);
         w.upload = nullptr;
+        w.last = -1;
         w.device = states[0]->device;
     }
     if (!w.upload && (e = hipStreamCreateWithFlags(&w.upload, hipStreamNonBlocking)) != hipSuccess)
@@ -1060,19 +1253,16 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
         return fail(QSIM_ERR_DEVICE, "batch event");
     if (!b.done && (e = hipEventCreateWithFlags(&b.done, hipEventDisableTiming)) != hipSuccess)
         return fail(QSIM_ERR_DEVICE, "batch event");
+    if (!b.k0 && (e = hipEventCreate(&b.k0)) != hipSuccess) return fail(QSIM_ERR_DEVICE, "batch event");
+    if (!b.k1 && (e = hipEventCreate(&b.k1)) != hipSuccess) return fail(QSIM_ERR_DEVICE, "batch event");
     if ((e = b.ws.ensure(total)) != hipSuccess) return fail(QSIM_ERR_NOMEM, "batch workspace");
-    if (rec_words_total && (e = b.rec.ensure(rec_words_total * 4)) != hipSuccess)
-        return fail(QSIM_ERR_NOMEM, "batch tile records");
     if ((e = b.stage.ensure(total)) != hipSuccess) return fail(QSIM_ERR_DEVICE, "batch staging");
     uint8_t *dev = static_cast<uint8_t *>(b.ws.p);
-    uint32_t *rec_dev = static_cast<uint32_t *>(b.rec.p);
     // device pointers inside the descriptors
     for (size_t g = 0; g < bpass.size(); ++g) {
         const size_t cb = blob_off + pass_blob_off[g];
         bpass[g].ta.inner = reinterpret_cast<const uint32_t *>(dev + cb + reinterpret_cast<size_t>(bpass[g].ta.inner));
         bpass[g].tm.steps = reinterpret_cast<const TmStep *>(dev + cb + reinterpret_cast<size_t>(bpass[g].tm.steps));
-        bpass[g].ta.rec = rec_dev + pass_rec_off[g];
-        bpass[g].tm.rec = rec_dev + pass_rec_off[g];
     }
     for (size_t k = 0; k < bsmall.size(); ++k) {
         const uint8_t *p = dev + blob_off + small_blob_off[k];
@@ -1080,13 +1270,31 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
         else bsmall[k].ta.inner = reinterpret_cast<const uint32_t *>(p);
     }
     uint8_t *h = static_cast<uint8_t *>(b.stage.p);
-    std::memset(h, 0, ctr_bytes);
-    std::memcpy(h + items_off, items.data(), items.size() * 8);
-    if (!bpass.empty()) std::memcpy(h + pass_off, bpass.data(), bpass.size() * sizeof(BatchPass));
-    if (!bsmall.empty()) std::memcpy(h + small_off, bsmall.data(), bsmall.size() * sizeof(BatchSmall));
-    for (uint32_t c = 0; c < n; ++c)
-        if (!plans[c].pr.blob.empty())
-            std::memcpy(h + blob_off + circuit_blob_off[c], plans[c].pr.blob.data(), plans[c].pr.blob.size());
+    {
+        // the copies into the pinned staging buffer, in pieces of at most
+        // 1 MiB shared among a few host threads
+        struct Piece { uint8_t *dst; const void *src; size_t n; };
+        std::vector<Piece> pieces;
+        auto add = [&](uint8_t *dst, const void *src, size_t bytes) {
+            for (size_t o = 0; o < bytes; o += (1u << 20))
+                pieces.push_back({dst + o, static_cast<const uint8_t *>(src) + o, std::min<size_t>(1u << 20, bytes - o)});
+        };
+        std::memset(h, 0, ctr_bytes);
+        add(h + items_off, items.data(), items.size() * 8);
+        add(h + pass_off, bpass.data(), bpass.size() * sizeof(BatchPass));
+        add(h + small_off, bsmall.data(), bsmall.size() * sizeof(BatchSmall));
+        for (uint32_t c = 0; c < n; ++c) add(h + blob_off + circuit_blob_off[c], plans[c].pr.blob.data(), plans[c].pr.blob.size());
+        std::atomic<size_t> next{0};
+        auto worker = [&]() {
+            for (size_t k; (k = next.fetch_add(64)) < pieces.size();)
+                for (size_t q = k; q < std::min(k + 64, pieces.size()); ++q) std::memcpy(pieces[q].dst, pieces[q].src, pieces[q].n);
+        };
+        const size_t nt = std::min<size_t>(8, std::max<size_t>(1, total >> 22));   // a thread per 4 MiB, at most 8
+        std::vector<std::thread> pool;
+        for (size_t t = 1; t < nt; ++t) pool.emplace_back(worker);
+        worker();
+        for (auto &t : pool) t.join();
+    }
     lap("stage");
     // Upload on the side stream (after the slot's previous kernel, which
     // the collect above has already waited for), then the kernel on the
@@ -1099,11 +1307,13 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
     if ((e = hipEventRecord(b.uploaded, w.upload)) != hipSuccess) return fail(QSIM_ERR_DEVICE, "batch event");
     if ((e = hipStreamWaitEvent(st, b.uploaded, 0)) != hipSuccess) return fail(QSIM_ERR_DEVICE, "batch event");
     uint32_t *ctr_dev = reinterpret_cast<uint32_t *>(dev);
+    b.timed = false;
     if (!items.empty()) {
+        b.timed = hipEventRecord(b.k0, st) == hipSuccess;
         e = launch_batch(elem, tb, any_sign, reinterpret_cast<const BatchPass *>(dev + pass_off),
                          reinterpret_cast<const BatchSmall *>(dev + small_off),
                          reinterpret_cast<const uint64_t *>(dev + items_off), (uint32_t)items.size(), ctr_dev,
-                         n_rec_blocks, 1u << 24, tpi, st);
+                         1u << 24, tpi, rec_stride, lds, st);
         if (e == hipSuccess) e = injected("batch");
         if (e != hipSuccess) {
             // whatever did launch finishes before the slot can be reused
@@ -1111,11 +1321,20 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
             for (uint32_t c = 0; c < n; ++c) states[c]->poisoned = true;
             return fail(QSIM_ERR_DEVICE, std::string("batch launch: ") + hipGetErrorString(e));
         }
+        b.timed = b.timed && hipEventRecord(b.k1, st) == hipSuccess;
     }
     if ((e = hipMemcpyAsync(b.hdr, ctr_dev, kBatchCtrHeader * 4, hipMemcpyDeviceToHost, st)) != hipSuccess)
         return fail(QSIM_ERR_DEVICE, std::string("batch status copy: ") + hipGetErrorString(e));
     if ((e = hipEventRecord(b.done, st)) != hipSuccess) return fail(QSIM_ERR_DEVICE, "batch event");
     b.pending = true;
+    b.info = qsim_batch_info{};
+    b.info.circuits = n;
+    b.info.items = (uint32_t)items.size();
+    b.info.passes = n_passes;
+    b.info.workgroups = (uint32_t)std::min<uint64_t>(workers, items.size());
+    b.info.algorithmic_bytes = alg_bytes;
+    export_batch_tune(tune, elem, &b.info.tuning);
+    w.last = w.next;
     w.next ^= 1;
     lap("launch");
     // every circuit's result sits in the buffer its last pass wrote
@@ -1540,59 +1759,319 @@ int qsim_batch_last_status(void) {
     return batch_status();
 }
 
-int qsim_batch_set_tiles_per_item(uint32_t tiles) {
-    if (tiles == 0) tiles = kBatchTiles;
-    if (tiles > kBatchTilesMax) return fail(QSIM_ERR_INVALID, "tiles_per_item above 256");
-    batch_ws().tiles_per_item.store(tiles);
+int qsim_batch_set_tuning(qsim_dtype dtype, const qsim_batch_tuning *t) {
+    const uint32_t elem = elem_of(dtype);
+    if (!elem) return fail(QSIM_ERR_INVALID, "dtype must be QSIM_C64 or QSIM_C128");
+    BatchTune bt;
+    int rc = batch_tune_from(t, &bt);
+    if (rc) return rc;
+    if (((size_t)elem << batch_tile_bits(bt, elem)) > 128 * 1024)
+        return fail(QSIM_ERR_INVALID, "batch tiles above 128 KiB of LDS");
+    BatchWorkspace &w = batch_ws();
+    std::lock_guard<std::mutex> lk(w.mu);
+    w.tune[elem == 8 ? 0 : 1] = bt;
     return QSIM_OK;
 }
 
-uint32_t qsim_batch_tiles_per_item(void) { return batch_ws().tiles_per_item.load(); }
+int qsim_batch_get_tuning(qsim_dtype dtype, qsim_batch_tuning *out) {
+    const uint32_t elem = elem_of(dtype);
+    if (!elem) return fail(QSIM_ERR_INVALID, "dtype must be QSIM_C64 or QSIM_C128");
+    if (!out) return fail(QSIM_ERR_INVALID, "out is NULL");
+    BatchWorkspace &w = batch_ws();
+    std::lock_guard<std::mutex> lk(w.mu);
+    export_batch_tune(w.tune[elem == 8 ? 0 : 1], elem, out);
+    return QSIM_OK;
+}
+
+int qsim_batch_set_tiles_per_item(uint32_t tiles) {
+    if (tiles == 0) tiles = BatchTune{}.tiles_per_item;
+    if (tiles > kBatchTilesMax) return fail(QSIM_ERR_INVALID, "tiles_per_item above 256");
+    BatchWorkspace &w = batch_ws();
+    std::lock_guard<std::mutex> lk(w.mu);
+    for (BatchTune &t : w.tune) t.tiles_per_item = tiles;
+    return QSIM_OK;
+}
+
+uint32_t qsim_batch_tiles_per_item(void) {
+    BatchWorkspace &w = batch_ws();
+    std::lock_guard<std::mutex> lk(w.mu);
+    return w.tune[0].tiles_per_item;
+}
+
+int qsim_batch_last_info(qsim_batch_info *out) {
+    if (!out) return fail(QSIM_ERR_INVALID, "out is NULL");
+    BatchWorkspace &w = batch_ws();
+    std::lock_guard<std::mutex> lk(w.mu);
+    if (w.last < 0) return fail(QSIM_ERR_INVALID, "no batch has run");
+    batch_collect(w, w.slot[w.last]);
+    *out = w.slot[w.last].info;
+    return QSIM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// ---- tuning cache of qsim_batch_autotune (QSIM_TUNING_CACHE): a JSON
+// object {"qsim_batch_tuning": {"<key>": {"<field>": <number>, ...}, ...}}
+// that this library writes and reads back.
+
+using CacheMap = std::map<std::string, std::map<std::string, double>>;
+
+struct JsonIn {
+    const char *p, *end;
+    void ws() {
+        while (p < end && (*p == ' ' || *p == '\n' || *p == '\r' || *p == '\t')) ++p;
+    }
+    bool lit(char c) {
+        ws();
+        if (p < end && *p == c) {
+            ++p;
+            return true;
+        }
+        return false;
+    }
+    bool str(std::string &out) {
+        if (!lit('"')) return false;
+        out.clear();
+        while (p < end && *p != '"') {
+            if (*p == '\\') return false;   // keys and fields this library writes need no escapes
+            out.push_back(*p++);
+        }
+        return lit('"');
+    }
+    bool num(double &out) {
+        ws();
+        char *e = nullptr;
+        out = std::strtod(p, &e);
+        if (e == p || e > end) return false;
+        p = e;
+        return true;
+    }
+};
+
+bool parse_cache(const std::string &text, CacheMap &out) {
+    JsonIn in{text.data(), text.data() + text.size()};
+    std::string top, key, field;
+    if (!in.lit('{')) return false;
+    if (in.lit('}')) return true;
+    do {
+        if (!in.str(top) || !in.lit(':') || top != "qsim_batch_tuning" || !in.lit('{')) return false;
+        if (in.lit('}')) continue;
+        do {
+            if (!in.str(key) || !in.lit(':') || !in.lit('{')) return false;
+            auto &entry = out[key];
+            if (in.lit('}')) continue;
+            do {
+                double v = 0;
+                if (!in.str(field) || !in.lit(':') || !in.num(v)) return false;
+                entry[field] = v;
+            } while (in.lit(','));
+            if (!in.lit('}')) return false;
+        } while (in.lit(','));
+        if (!in.lit('}')) return false;
+    } while (in.lit(','));
+    return in.lit('}');
+}
+
+std::string write_cache(const CacheMap &m) {
+    std::string o = "{\n  \"qsim_batch_tuning\": {";
+    bool first = true;
+    char buf[64];
+    for (const auto &kv : m) {
+        o += first ? "\n    \"" : ",\n    \"";
+        first = false;
+        o += kv.first + "\": {";
+        bool f2 = true;
+        for (const auto &fv : kv.second) {
+            std::snprintf(buf, sizeof buf, "%.6g", fv.second);
+            o += (f2 ? "\"" : ", \"") + fv.first + "\": " + buf;
+            f2 = false;
+        }
+        o += "}";
+    }
+    return o + "\n  }\n}\n";
+}
+
+bool read_file(const char *path, std::string &out) {
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return false;
+    char buf[4096];
+    size_t k;
+    out.clear();
+    while ((k = std::fread(buf, 1, sizeof buf, f)) > 0) out.append(buf, k);
+    std::fclose(f);
+    return true;
+}
+
+bool write_file(const char *path, const std::string &text) {
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return false;
+    const bool ok = std::fwrite(text.data(), 1, text.size(), f) == text.size();
+    if (std::fclose(f) != 0 || !ok) return false;
+    return std::rename(tmp.c_str(), path) == 0;
+}
+
+// Cache key of a batch: device architecture, dtype, range of M and range
+// of L rounded out to powers of two.
+std::string batch_cache_key(int device, uint32_t elem, qsim_state *const *states, const uint64_t *Ls, uint32_t n) {
+    hipDeviceProp_t prop{};
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        arch = prop.gcnArchName;
+        arch = arch.substr(0, arch.find(':'));
+    }
+    uint32_t mlo = 64, mhi = 0;
+    uint64_t llo = ~0ull, lhi = 0;
+    for (uint32_t c = 0; c < n; ++c) {
+        mlo = std::min(mlo, states[c]->M);
+        mhi = std::max(mhi, states[c]->M);
+        llo = std::min(llo, Ls[c]);
+        lhi = std::max(lhi, Ls[c]);
+    }
+    uint64_t plo = 0, phi = 1;
+    if (llo > 0) for (plo = 1; plo * 2 <= llo; plo *= 2) {}
+    while (phi < lhi) phi *= 2;
+    return arch + ":" + (elem == 8 ? "c64" : "c128") + ":M" + std::to_string(mlo) + "-" + std::to_string(mhi) + ":L" +
+           std::to_string(plo) + "-" + std::to_string(phi);
+}
+
+}  // namespace
+
+extern "C" {
 
 int qsim_batch_autotune(qsim_state *const *states, const qsim_step *const *steps, const uint64_t *Ls, uint32_t n,
-                        void *hip_stream, uint32_t *tiles_out) {
-    if (n == 0) {
-        if (tiles_out) *tiles_out = qsim_batch_tiles_per_item();
-        return QSIM_OK;
-    }
+                        void *hip_stream, qsim_batch_tuning *out) {
+    if (n == 0) return out ? qsim_batch_get_tuning(QSIM_C64, out) : QSIM_OK;
     if (!states || !steps || !Ls) return fail(QSIM_ERR_INVALID, "NULL array");
+    for (uint32_t c = 0; c < n; ++c) {
+        int rc = check_state(states[c]);
+        if (rc) return rc;
+        if (Ls[c] > 0 && !steps[c]) return fail(QSIM_ERR_INVALID, "circuit " + std::to_string(c) + ": steps is NULL");
+    }
+    const uint32_t elem = states[0]->elem;
+    const int di = elem == 8 ? 0 : 1;
+    BatchWorkspace &w = batch_ws();
+    auto set = [&](const BatchTune &t) {
+        std::lock_guard<std::mutex> lk(w.mu);
+        w.tune[di] = t;
+    };
+    const char *cache_path = std::getenv("QSIM_TUNING_CACHE");
+    const std::string key = batch_cache_key(states[0]->device, elem, states, Ls, n);
+    CacheMap cache;
+    bool cache_ok = false;
+    if (cache_path && *cache_path) {
+        std::string text;
+        cache_ok = !read_file(cache_path, text) || parse_cache(text, cache);   // no file yet: start one
+        auto it = cache.find(key);
+        if (cache_ok && it != cache.end()) {
+            qsim_batch_tuning in{};
+            auto get = [&](const char *f) { auto x = it->second.find(f); return x == it->second.end() ? 0u : (uint32_t)x->second; };
+            in.tiles_per_item = get("tiles_per_item");
+            in.tile_bits = get("tile_bits");
+            in.circuit_tiles = get("circuit_tiles");
+            in.plan_search = get("plan_search");
+            in.order = get("order");
+            BatchTune bt;
+            if (batch_tune_from(&in, &bt) == QSIM_OK) {
+                set(bt);
+                if (out) {
+                    export_batch_tune(bt, elem, out);
+                    out->from_cache = 1;
+                }
+                return QSIM_OK;
+            }
+        }
+    }
     // Each trial applies the batch and then the batch of reversed diagrams,
     // which undoes it (every step is its own inverse), so the states end as
-    // they began.
+    // they began: one such pair to settle, then two timed back to back.
     std::vector<std::vector<qsim_step>> rev(n);
     std::vector<const qsim_step *> rev_ptr(n);
     for (uint32_t c = 0; c < n; ++c) {
-        if (Ls[c] > 0 && !steps[c]) return fail(QSIM_ERR_INVALID, "circuit " + std::to_string(c) + ": steps is NULL");
         rev[c].assign(steps[c], steps[c] + Ls[c]);
         std::reverse(rev[c].begin(), rev[c].end());
         rev_ptr[c] = rev[c].data();
     }
-    const uint32_t keep = qsim_batch_tiles_per_item();
-    const uint32_t cands[] = {4, 8, 16, 32, 64};
-    auto trial = [&](double *ms) {
-        const auto t0 = std::chrono::steady_clock::now();
+    BatchTune keep;
+    {
+        std::lock_guard<std::mutex> lk(w.mu);
+        keep = w.tune[di];
+    }
+    // A trial's cost is the time per batch of a long run of batches: the
+    // host plans the next batch while the device runs the current one, so
+    // it is the larger of the kernel's device time and the host's enqueue
+    // time (each the mean over a batch and its reverse, after a settling
+    // pair).
+    auto trial = [&](const BatchTune &t, double *ms) {
+        set(t);
         int rc = qsim_apply_batch(states, steps, Ls, n, hip_stream);
         if (!rc) rc = qsim_apply_batch(states, rev_ptr.data(), Ls, n, hip_stream);
         if (!rc) rc = batch_status();
-        if (ms) *ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        double host = 0;
+        for (int k = 0; k < 2 && !rc; ++k) {
+            const auto t0 = std::chrono::steady_clock::now();   // nothing in flight: enqueue time only
+            rc = qsim_apply_batch(states, k ? rev_ptr.data() : steps, Ls, n, hip_stream);
+            host += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            if (!rc) rc = batch_status();
+        }
+        double kern = 0;
+        if (!rc) {
+            std::lock_guard<std::mutex> lk(w.mu);
+            kern = (w.slot[0].info.kernel_ms + w.slot[1].info.kernel_ms) / 2;
+        }
+        *ms = std::max(host / 2, kern);
         return rc;
     };
-    int rc = trial(nullptr);   // warm the workspace and the caches of the first candidate's shapes
-    double best_ms = 1e300;
-    uint32_t best = keep;
-    for (uint32_t c : cands) {
-        if (rc) break;
-        batch_ws().tiles_per_item.store(c);
-        double ms = 0;
-        if ((rc = trial(&ms))) break;
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = c;
+    BatchTune best;   // the defaults
+    double best_ms = 0, default_ms = 0;
+    int rc = trial(best, &best_ms);
+    default_ms = best_ms;
+    // one parameter at a time, each candidate against the best so far
+    const uint32_t kb = batch_tile_bits(BatchTune{}, elem);
+    const std::vector<std::pair<int, std::vector<uint32_t>>> space = {
+        {0, {1}},                  // order: level by level
+        {1, {kb - 1}},             // tile bits: one less
+        {2, {2}},                  // planning with the mask climb
+        {3, {1, 8, 16, 64, 128}},  // whole-circuit cut-off (1 = none)
+        {4, {8, 16, 64}},          // tiles per item
+    };
+    for (const auto &dim : space) {
+        for (uint32_t v : dim.second) {
+            if (rc) break;
+            BatchTune t = best;
+            uint32_t *f = dim.first == 0 ? &t.order : dim.first == 1 ? &t.tile_bits : dim.first == 2 ? &t.plan_search
+                          : dim.first == 3 ? &t.circuit_tiles : &t.tiles_per_item;
+            if (dim.first == 1 && !t.tile_bits) t.tile_bits = kb;
+            if (*f == v) continue;
+            *f = v;
+            double ms = 0;
+            if ((rc = trial(t, &ms))) break;
+            if (ms < 0.995 * best_ms) {   // a clear gain only
+                best = t;
+                best_ms = ms;
+            }
         }
     }
-    batch_ws().tiles_per_item.store(rc ? keep : best);
+    set(rc ? keep : best);
     if (rc) return rc;
-    if (tiles_out) *tiles_out = best;
+    if (cache_path && *cache_path && cache_ok) {
+        auto &e = cache[key];
+        e["tiles_per_item"] = best.tiles_per_item;
+        e["tile_bits"] = batch_tile_bits(best, elem);
+        e["circuit_tiles"] = best.circuit_tiles;
+        e["plan_search"] = best.plan_search;
+        e["order"] = best.order;
+        e["best_ms"] = best_ms;
+        e["default_ms"] = default_ms;
+        (void)write_file(cache_path, write_cache(cache));   // a cache that cannot be written is skipped
+    }
+    if (out) {
+        export_batch_tune(best, elem, out);
+        out->best_ms = (float)best_ms;
+        out->default_ms = (float)default_ms;
+    }
     return QSIM_OK;
 }
 

@@ -340,11 +340,11 @@ __global__ void __launch_bounds__(512) k_small(const vec16 *__restrict__ src, ve
 
 // Per-tile record of a pass: source tile address and the outside-control
 // flags of the inner steps, from a backward walk of the outer address.
-__device__ __forceinline__ void tilemap_one(const TileMapArgs &a, uint64_t tile) {
+// Written to `rec` (a.rec_words words).
+__device__ __forceinline__ void tilemap_record(const TileMapArgs &a, uint64_t tile, uint32_t *rec) {
     uint64_t A = 0;
     for (uint32_t q = 0; q < a.n_out; ++q)
         if ((tile >> q) & 1u) A |= 1ull << a.out_pos[q];
-    uint32_t *rec = a.rec + tile * a.rec_words;
     uint32_t word = 0, k = 0;
     // A is the logical outer address; the record holds its physical
     // address in the layout the pass reads.
@@ -371,6 +371,10 @@ __device__ __forceinline__ void tilemap_one(const TileMapArgs &a, uint64_t tile)
     }
     rec[0] = (uint32_t)P;
     rec[1] = (uint32_t)(P >> 32);
+}
+
+__device__ __forceinline__ void tilemap_one(const TileMapArgs &a, uint64_t tile) {
+    tilemap_record(a, tile, a.rec + tile * a.rec_words);
 }
 
 __global__ void __launch_bounds__(256) k_tilemap(TileMapArgs a) {
@@ -573,102 +577,93 @@ __device__ __forceinline__ void small_item(const BatchSmall &sm, vec16 *lds) {
     if (active) tile_emit<ELEM, 5, SIGN>(w, dst, off, a, lds);
 }
 
+// Records of tiles t0 .. t0 + nt - 1 of a pass into LDS (rec_stride words
+// apart), one tile per thread, then a barrier: the batched kernel forms
+// its records where it uses them instead of in a separate phase.
+__device__ __forceinline__ void batch_records(const TileMapArgs &tm, uint64_t t0, uint32_t nt, uint32_t *srec,
+                                              uint32_t rec_stride) {
+    for (uint32_t k = threadIdx.x; k < nt; k += blockDim.x) tilemap_record(tm, t0 + k, srec + k * rec_stride);
+    __syncthreads();
+}
+
+// Tiles t0 .. t1 - 1 of one pass, each tile's loads issued while the one
+// before it is gathered and stored; records from batch_records.
+template <int ELEM, bool SIGN>
+__device__ __forceinline__ void batch_tiles(const BatchPass &bp, uint64_t t0, uint64_t t1, const uint32_t *srec,
+                                            uint32_t rec_stride, vec16 *lds) {
+    constexpr uint32_t VPT = Shape<ELEM, 5>::VPT;
+    const TileArgs &a = bp.ta;
+    const vec16 *src = static_cast<const vec16 *>(bp.src);
+    vec16 *dst = static_cast<vec16 *>(bp.dst);
+    const uint32_t off_src = thread_offset<ELEM>(a.pos_src, a.tb, threadIdx.x);
+    const uint32_t off_dst = thread_offset<ELEM>(a.pos_dst, a.tb, threadIdx.x);
+    vec16 v[VPT];
+    load_tile<ELEM, 5>(v, src, rec_base(srec) + off_src, a);
+    for (uint64_t tile = t0; tile < t1; ++tile) {
+        const uint32_t *r = srec + (tile - t0) * rec_stride;
+        const uint64_t next_base = tile + 1 < t1 ? rec_base(r + rec_stride) + off_src : ~0ull;
+        tile_step<ELEM, 5, true, SIGN>(v, src, dst, outer_address(a, tile) + off_dst, next_base, a, r + 2, lds);
+        __syncthreads();
+    }
+}
+
+// Persistent batched launch.  Items are taken from the queue one per
+// atomic, in queue order; every item depends only on earlier items, so a
+// workgroup that waits never blocks the items its wait depends on.  The
+// dynamic LDS holds the tile, then the tile records of the current item
+// (rec_stride words per tile).
 template <int ELEM, bool SIGN>
 __global__ void __launch_bounds__(256) k_batch(const BatchPass *__restrict__ passes,
                                                const BatchSmall *__restrict__ smalls,
                                                const uint64_t *__restrict__ items, uint32_t n_items,
-                                               uint32_t *ctr, uint32_t n_rec_blocks, uint32_t spin_limit,
-                                               uint32_t tiles_per_item) {
+                                               uint32_t *ctr, uint32_t spin_limit, uint32_t tiles_per_item,
+                                               uint32_t rec_stride, uint32_t tile_entries) {
     extern __shared__ vec16 lds[];
     __shared__ uint32_t s_item;
-    constexpr uint32_t VPT = Shape<ELEM, 5>::VPT;
+    uint32_t *srec = reinterpret_cast<uint32_t *>(lds + tile_entries * ELEM / 16);
     const uint32_t tid = threadIdx.x;
-    // Items are taken from the queue kBatchGroup at a time (one atomic per
-    // group) and processed in queue order; every item depends only on
-    // earlier items, so holding a group cannot deadlock.
-    for (uint32_t it = 0, end = 0;; ++it) {
-        if (it >= end) {
-            __syncthreads();
-            if (tid == 0)
-                s_item = __hip_atomic_fetch_add(&ctr[0], kBatchGroup, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __syncthreads();
-            it = s_item;
-            end = it + kBatchGroup;
-        }
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) s_item = __hip_atomic_fetch_add(&ctr[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const uint32_t it = s_item;
         if (it >= n_items) break;   // the same value for the whole workgroup
         const uint64_t e = items[it];
         const uint32_t kind = (uint32_t)(e >> 62);
         const uint32_t idx = (uint32_t)(e >> 32) & 0x3FFFFFFFu;
         const uint32_t sub = (uint32_t)e;
-        if (kind == kItemRec) {
-            const BatchPass &bp = passes[idx];
-            const uint64_t tile = (uint64_t)sub * blockDim.x + tid;
-            if (tile < bp.n_tiles) tilemap_one(bp.tm, tile);
-            publish(&ctr[1], 1u);
-        } else if (kind == kItemSmall) {
+        if (kind == kItemSmall) {
             small_item<ELEM, SIGN>(smalls[idx], lds);
         } else if (kind == kItemCircuit) {
             // Every pass of one circuit (passes idx .. idx + sub - 1), all in
             // this workgroup: no other workgroup touches its buffers, so a
             // pass only has to see this workgroup's stores of the one before.
-            if (tid == 0) {
-                wait_at_least(&ctr[1], n_rec_blocks, &ctr[2], spin_limit);
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            }
-            __syncthreads();
             for (uint32_t p = 0; p < sub; ++p) {
                 const BatchPass &bp = passes[idx + p];
-                const TileArgs &a = bp.ta;
-                const vec16 *src = static_cast<const vec16 *>(bp.src);
-                vec16 *dst = static_cast<vec16 *>(bp.dst);
-                const uint32_t off_src = thread_offset<ELEM>(a.pos_src, a.tb, tid);
-                const uint32_t off_dst = thread_offset<ELEM>(a.pos_dst, a.tb, tid);
-                vec16 v[VPT];
-                load_tile<ELEM, 5>(v, src, rec_base(a.rec) + off_src, a);
-                for (uint64_t tile = 0; tile < bp.n_tiles; ++tile) {
-                    const uint64_t next_base =
-                        tile + 1 < bp.n_tiles ? rec_base(a.rec + (tile + 1) * a.rec_words) + off_src : ~0ull;
-                    tile_step<ELEM, 5, true, SIGN>(v, src, dst, outer_address(a, tile) + off_dst, next_base, a,
-                                                   a.rec + tile * a.rec_words + 2, lds);
-                    __syncthreads();
-                }
+                batch_records(bp.tm, 0, (uint32_t)bp.n_tiles, srec, rec_stride);
+                batch_tiles<ELEM, SIGN>(bp, 0, bp.n_tiles, srec, rec_stride, lds);
                 // this pass's stores done, then the CU's L1 dropped before
                 // the next pass reads what they wrote
                 __builtin_amdgcn_s_waitcnt(0);
                 __syncthreads();
                 if (tid == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                __syncthreads();
             }
         } else {
+            // a block of up to tiles_per_item tiles of one pass, after every
+            // tile of the circuit's previous pass
             const BatchPass &bp = passes[idx];
+            const uint64_t t0 = (uint64_t)sub * tiles_per_item;
+            const uint64_t t1 = t0 + tiles_per_item < bp.n_tiles ? t0 + tiles_per_item : bp.n_tiles;
+            batch_records(bp.tm, t0, (uint32_t)(t1 - t0), srec, rec_stride);
             if (tid == 0) {
-                wait_at_least(&ctr[1], n_rec_blocks, &ctr[2], spin_limit);
                 wait_at_least(&ctr[kBatchCtrHeader + bp.circuit], bp.level * (uint32_t)bp.n_tiles, &ctr[2],
                               spin_limit);
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
             __syncthreads();
-            // a block of up to tiles_per_item tiles of one pass, the loads of
-            // each tile issued while the previous one is gathered and stored
-            const TileArgs &a = bp.ta;
-            const uint64_t t0 = (uint64_t)sub * tiles_per_item;
-            const uint64_t t1 = t0 + tiles_per_item < bp.n_tiles ? t0 + tiles_per_item : bp.n_tiles;
-            const vec16 *src = static_cast<const vec16 *>(bp.src);
-            vec16 *dst = static_cast<vec16 *>(bp.dst);
-            const uint32_t off_src = thread_offset<ELEM>(a.pos_src, a.tb, tid);
-            const uint32_t off_dst = thread_offset<ELEM>(a.pos_dst, a.tb, tid);
-            vec16 v[VPT];
-            load_tile<ELEM, 5>(v, src, rec_base(a.rec + t0 * a.rec_words) + off_src, a);
-            for (uint64_t tile = t0; tile < t1; ++tile) {
-                const uint64_t next_base =
-                    tile + 1 < t1 ? rec_base(a.rec + (tile + 1) * a.rec_words) + off_src : ~0ull;
-                tile_step<ELEM, 5, true, SIGN>(v, src, dst, outer_address(a, tile) + off_dst, next_base, a,
-                                               a.rec + tile * a.rec_words + 2, lds);
-                __syncthreads();
-            }
+            batch_tiles<ELEM, SIGN>(bp, t0, t1, srec, rec_stride, lds);
             publish(&ctr[kBatchCtrHeader + bp.circuit], (uint32_t)(t1 - t0));
         }
-        __syncthreads();
     }
 }
 
@@ -1029,21 +1024,36 @@ hipError_t launch_plain_phase(uint32_t elem, void *buf, uint32_t M, uint64_t mas
     return hipGetLastError();
 }
 
-hipError_t launch_batch(uint32_t elem, uint32_t tb, bool sign, const BatchPass *passes, const BatchSmall *smalls,
-                        const uint64_t *items, uint32_t n_items, uint32_t *counters, uint32_t n_rec_blocks,
-                        uint32_t spin_limit, uint32_t tiles_per_item, hipStream_t st) {
+template <int ELEM, bool SIGN>
+hipError_t batch_kernel_grid(uint32_t tb, size_t lds, uint64_t *grid) {
     const uint32_t threads = 1u << tb;
-    const size_t lds = (size_t)elem << (tb + 5);
-    if (threads > 256) return hipErrorInvalidValue;
+    auto kern = k_batch<ELEM, SIGN>;
+    hipError_t e = allow_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    *grid = resident_blocks(kern, threads, lds);
+    if (*grid == 0) *grid = 256;
+    return hipSuccess;
+}
+
+hipError_t batch_grid(uint32_t elem, uint32_t tb, bool sign, size_t lds, uint64_t *grid) {
+    if (tb > 8 || lds > 160 * 1024) return hipErrorInvalidValue;
+    if (elem == 8) return sign ? batch_kernel_grid<8, true>(tb, lds, grid) : batch_kernel_grid<8, false>(tb, lds, grid);
+    return sign ? batch_kernel_grid<16, true>(tb, lds, grid) : batch_kernel_grid<16, false>(tb, lds, grid);
+}
+
+hipError_t launch_batch(uint32_t elem, uint32_t tb, bool sign, const BatchPass *passes, const BatchSmall *smalls,
+                        const uint64_t *items, uint32_t n_items, uint32_t *counters, uint32_t spin_limit,
+                        uint32_t tiles_per_item, uint32_t rec_stride, size_t lds, hipStream_t st) {
+    const uint32_t threads = 1u << tb;
+    const uint32_t tile_entries = 1u << (tb + 5);
+    uint64_t grid = 0;
+    hipError_t e = batch_grid(elem, tb, sign, lds, &grid);
+    if (e != hipSuccess) return e;
+    if (grid > n_items) grid = n_items;
+    if (grid == 0) return hipSuccess;
     auto go = [&](auto kern) {
-        hipError_t e = allow_lds(kern, lds);
-        if (e != hipSuccess) return e;
-        uint64_t grid = resident_blocks(kern, threads, lds);
-        if (grid == 0) grid = 256;
-        if (grid > n_items) grid = n_items;
-        if (grid == 0) return hipSuccess;
         hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(threads), lds, st, passes, smalls, items, n_items,
-                           counters, n_rec_blocks, spin_limit, tiles_per_item);
+                           counters, spin_limit, tiles_per_item, rec_stride, tile_entries);
         return hipGetLastError();
     };
     if (elem == 8) return sign ? go(k_batch<8, true>) : go(k_batch<8, false>);

@@ -94,12 +94,14 @@ struct TileMapArgs {
 };
 
 // Batched mode: many circuits in one persistent launch.  Work items are
-// read from a queue in order; each names a tile-map record block of a pass,
-// a whole small circuit, or one tile of one pass.  A tile of pass p of a
-// circuit waits until every tile of pass p-1 of that circuit is done.
+// read from a queue in order; each names a whole small circuit, a whole
+// mid-size circuit (all its passes in one workgroup) or a block of tiles of
+// one pass.  A tile of pass p of a circuit waits until every tile of pass
+// p-1 of that circuit is done.  Tile records are formed in LDS by the item
+// that uses them.
 struct BatchPass {
-    TileArgs ta;            // inner / rec pointers filled in
-    TileMapArgs tm;         // steps / rec pointers filled in
+    TileArgs ta;            // inner pointer filled in (rec unused)
+    TileMapArgs tm;         // steps pointer filled in (rec unused)
     const void *src;
     void *dst;
     uint64_t n_tiles;
@@ -118,22 +120,16 @@ struct BatchSmall {
     uint32_t pad;
 };
 
-enum : uint32_t { kItemRec = 0, kItemSmall = 1, kItemTile = 2, kItemCircuit = 3 };
-// Circuits whose passes have at most this many tiles run every pass in one
-// workgroup (one kItemCircuit item) instead of one item per pass.
-constexpr uint64_t kBatchCircuitTiles = 16;
+enum : uint32_t { kItemSmall = 1, kItemTile = 2, kItemCircuit = 3 };
 
 __host__ __device__ inline uint64_t batch_item(uint32_t kind, uint32_t index, uint32_t sub) {
     return ((uint64_t)kind << 62) | ((uint64_t)(index & 0x3FFFFFFFu) << 32) | sub;
 }
 
-// Counter words of a batched launch: [0] queue head, [1] finished record
-// blocks, [2] error flag (a dependency wait ran out), [3] reserved,
-// [4 + c] finished tiles of circuit c.
+// Counter words of a batched launch: [0] queue head, [1] reserved, [2]
+// error flag (a dependency wait ran out), [3] reserved, [4 + c] finished
+// tiles of circuit c.
 constexpr uint32_t kBatchCtrHeader = 4;
-constexpr uint32_t kBatchGroup = 1;   // queue items taken per atomic (4: 20.1 ms, 2: 19.3, 1: 18.6)
-constexpr uint32_t kBatchTiles = 32;  // default tiles of one pass per tile item (8: 20.7 ms, 16: 18.8, 24: 18.5,
-                                      // 32: 18.3 for 4096 circuits of M 8..20)
 constexpr uint32_t kBatchTilesMax = 256;
 
 }  // namespace qsim
@@ -176,8 +172,11 @@ hipError_t launch_tile_product(uint32_t elem, void *dst, uint64_t n_tiles, const
 hipError_t launch_iota(uint64_t *out, uint64_t n, hipStream_t st);
 hipError_t launch_narrow(const uint64_t *in, uint32_t *out, uint64_t n, hipStream_t st);
 hipError_t launch_gather(uint32_t elem, const void *src, void *dst, const uint32_t *x, uint64_t n, hipStream_t st);
+// Workgroups of a batched launch (those resident at once): the workers the
+// host's queue ordering plans for.  lds = dynamic LDS bytes per workgroup.
+hipError_t batch_grid(uint32_t elem, uint32_t tb, bool sign, size_t lds, uint64_t *grid);
 hipError_t launch_batch(uint32_t elem, uint32_t tb, bool sign, const BatchPass *passes, const BatchSmall *smalls,
-                        const uint64_t *items, uint32_t n_items, uint32_t *counters, uint32_t n_rec_blocks,
-                        uint32_t spin_limit, uint32_t tiles_per_item, hipStream_t st);
+                        const uint64_t *items, uint32_t n_items, uint32_t *counters, uint32_t spin_limit,
+                        uint32_t tiles_per_item, uint32_t rec_stride, size_t lds, hipStream_t st);
 
 }  // namespace qsim

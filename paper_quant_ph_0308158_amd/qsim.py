@@ -40,6 +40,7 @@ EXPORTS = (
     "qsim_server_request_info", "qsim_server_stats", "qsim_server_destroy", "qsim_state_set_product", "qsim_apply_steps_product",
     "qsim_rowmap_build", "qsim_rowmap_apply", "qsim_autotune", "qsim_batch_set_tiles_per_item",
     "qsim_batch_tiles_per_item", "qsim_batch_autotune", "qsim_apply_steps_noalloc",
+    "qsim_batch_set_tuning", "qsim_batch_get_tuning", "qsim_batch_last_info",
 )
 
 
@@ -82,6 +83,27 @@ class Tuning(ctypes.Structure):
                 ("remap", ctypes.c_uint32), ("mid_low_bits", ctypes.c_uint32),
                 ("min_overlap", ctypes.c_uint32), ("rows_per_thread", ctypes.c_uint32),
                 ("plan_search", ctypes.c_uint32), ("xcd_swizzle", ctypes.c_uint32)]
+
+
+class BatchTuning(ctypes.Structure):
+    _fields_ = [("tiles_per_item", ctypes.c_uint32), ("tile_bits", ctypes.c_uint32),
+                ("circuit_tiles", ctypes.c_uint32), ("plan_search", ctypes.c_uint32),
+                ("order", ctypes.c_uint32), ("from_cache", ctypes.c_uint32),
+                ("best_ms", ctypes.c_float), ("default_ms", ctypes.c_float)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("circuits", ctypes.c_uint32), ("items", ctypes.c_uint32), ("passes", ctypes.c_uint32),
+                ("workgroups", ctypes.c_uint32), ("algorithmic_bytes", ctypes.c_uint64),
+                ("kernel_ms", ctypes.c_double), ("tuning", BatchTuning)]
+
+    def as_dict(self) -> dict:
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "tuning"}
+        d["tuning"] = self.tuning.as_dict()
+        return d
 
 
 def _load() -> ctypes.CDLL:
@@ -135,6 +157,9 @@ def _load() -> ctypes.CDLL:
         "qsim_batch_tiles_per_item": (u32, []),
         "qsim_batch_autotune": (i32, [vp, vp, vp, u32, vp, vp]),
         "qsim_apply_steps_noalloc": (i32, [vp, vp, u64, vp]),
+        "qsim_batch_set_tuning": (i32, [i32, vp]),
+        "qsim_batch_get_tuning": (i32, [i32, vp]),
+        "qsim_batch_last_info": (i32, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -445,20 +470,51 @@ def batch_tiles_per_item() -> int:
     return int(_lib.qsim_batch_tiles_per_item())
 
 
-def batch_autotune(states: Sequence[State], steps, stream=None) -> int:
-    """Pick the tiles per queue item for this batch by measurement (the
-    states' contents are unchanged); returns the chosen value.  steps: a
-    PackedBatch or a list of (target, cmask[, kind])."""
+BATCH_TUNING_FIELDS = ("tiles_per_item", "tile_bits", "circuit_tiles", "plan_search", "order")
+
+
+def batch_set_tuning(dtype, tuning: Optional[dict]):
+    """Batched-mode parameters for states of `dtype` (None: defaults)."""
+    t = None
+    if tuning is not None:
+        t = BatchTuning()
+        for k, v in tuning.items():
+            if k not in BATCH_TUNING_FIELDS:
+                raise ValueError(f"unknown batch tuning field {k!r}")
+            setattr(t, k, int(v))
+    _check(_lib.qsim_batch_set_tuning(dtype_code(dtype), ctypes.byref(t) if t is not None else None))
+
+
+def batch_get_tuning(dtype) -> dict:
+    t = BatchTuning()
+    _check(_lib.qsim_batch_get_tuning(dtype_code(dtype), ctypes.byref(t)))
+    return {k: getattr(t, k) for k in BATCH_TUNING_FIELDS}
+
+
+def batch_autotune(states: Sequence[State], steps, stream=None) -> dict:
+    """Choose the batched-mode parameters for this batch by measurement (the
+    states' contents are unchanged) and keep them for its dtype; returns the
+    choice with the measured times (and from_cache = 1 when the tuning cache
+    named by QSIM_TUNING_CACHE supplied it).  steps: a PackedBatch or a list
+    of (target, cmask[, kind])."""
     n = len(states)
     pb = steps if isinstance(steps, PackedBatch) else PackedBatch(steps)
     if len(pb) != n:
         raise ValueError("one step list per state")
     hs = _handles(states)
-    out = ctypes.c_uint32(0)
+    out = BatchTuning()
     _check(_lib.qsim_batch_autotune(ctypes.c_void_p(hs.ctypes.data), ctypes.c_void_p(pb.ptrs.ctypes.data),
                                     ctypes.c_void_p(pb.lens.ctypes.data), n, ctypes.c_void_p(_stream_ptr(stream)),
                                     ctypes.byref(out)))
-    return int(out.value)
+    return out.as_dict()
+
+
+def batch_last_info() -> dict:
+    """What the last batched launch did: circuits, items, passes, workgroups,
+    algorithmic bytes, kernel time (ms) and its parameters."""
+    out = BatchInfo()
+    _check(_lib.qsim_batch_last_info(ctypes.byref(out)))
+    return out.as_dict()
 
 
 def batch_status():

@@ -396,3 +396,21 @@ def test_budget_rejects_state_creation(monkeypatch):
     with pytest.raises(qsim.QsimError):
         qsim.State(20, "c64")                 # 2 x 8 MiB > 1 MiB
     assert "QSIM_HBM_BUDGET_BYTES" in qsim.last_error()
+
+
+def test_batch_tuning_setting():
+    """qsim_batch_set_tuning validates its fields and keeps one setting per
+    dtype (host only)."""
+    default = qsim.batch_get_tuning("c64")
+    assert default == {"tiles_per_item": 32, "tile_bits": 13, "circuit_tiles": 32, "plan_search": 1, "order": 2}
+    assert qsim.batch_get_tuning("c128")["tile_bits"] == 12
+    qsim.batch_set_tuning("c128", {"tile_bits": 11, "order": 1})
+    assert qsim.batch_get_tuning("c128")["tile_bits"] == 11 and qsim.batch_get_tuning("c64") == default
+    for bad in ({"tile_bits": 9}, {"tile_bits": 14}, {"plan_search": 3}, {"order": 3}, {"tiles_per_item": 257},
+                {"circuit_tiles": 300}):
+        with pytest.raises(qsim.QsimError):
+            qsim.batch_set_tuning("c64", bad)
+    qsim.batch_set_tuning("c128", None)
+    assert qsim.batch_get_tuning("c64") == default
+    with pytest.raises(qsim.QsimError):
+        qsim.batch_last_info()            # no batch has run in this process

@@ -621,10 +621,11 @@ def test_m33_sampled_beyond_2_32_rows(q):
     assert same
 
 
-def test_batch_autotune_keeps_states(q):
-    """qsim_batch_autotune times candidate item sizes with forward and
-    reversed batches: the states are unchanged, the choice is one of the
-    candidates and a batch with it equals the oracle."""
+def test_batch_autotune_keeps_states(q, tmp_path, monkeypatch):
+    """qsim_batch_autotune times candidate settings with forward and reversed
+    batches: the states are unchanged, the choice is stored in the tuning
+    cache and read back from it by a second call, and a batch with it equals
+    the oracle."""
     rng = np.random.default_rng(150)
     circuits = W.batched_config(n=48, seed=151, m_range=(6, 17), l_range=(0, 120))
     states, ins = [], []
@@ -635,17 +636,72 @@ def test_batch_autotune_keeps_states(q):
         states.append(s)
         ins.append(k1)
     steps = [(c.target, c.cmask) for c in circuits]
+    cache = tmp_path / "tuning.json"
+    monkeypatch.setenv("QSIM_TUNING_CACHE", str(cache))
     say("batch autotune")
     try:
         t = q.batch_autotune(states, steps, stream=0)
-        assert t in (4, 8, 16, 32, 64) and q.batch_tiles_per_item() == t
+        assert t["from_cache"] == 0 and t["best_ms"] > 0 and t["best_ms"] <= t["default_ms"]
+        chosen = {k: t[k] for k in q.BATCH_TUNING_FIELDS}
+        assert q.batch_get_tuning("c64") == chosen
         for s, k1 in zip(states, ins):
             assert_same(s.read(), k1, "state after batch autotune")
+        import json
+        entries = json.loads(cache.read_text())["qsim_batch_tuning"]
+        (key, entry), = entries.items()
+        assert ":c64:M" in key and all(entry[k] == v for k, v in chosen.items())
+        q.batch_set_tuning("c64", None)
+        t2 = q.batch_autotune(states, steps, stream=0)
+        assert t2["from_cache"] == 1 and {k: t2[k] for k in q.BATCH_TUNING_FIELDS} == chosen
         q.apply_batch(states, steps, stream=0)
         q.batch_status()
         for c, s, k1 in zip(circuits, states, ins):
             assert_same(s.read(), oracle.apply(c.M, k1, c.target, c.cmask), f"tuned batch M={c.M} L={c.L}")
     finally:
-        q.batch_set_tiles_per_item(0)
+        q.batch_set_tuning("c64", None)
+        for s in states:
+            s.close()
+
+
+@pytest.mark.parametrize("dt,tuning", [
+    ("c64", {"order": 1}),
+    ("c64", {"order": 2, "tiles_per_item": 1}),
+    ("c64", {"tile_bits": 12, "tiles_per_item": 8}),
+    ("c64", {"tile_bits": 10, "circuit_tiles": 1}),
+    ("c64", {"circuit_tiles": 64, "plan_search": 2}),
+    ("c64", {"tile_bits": 11, "circuit_tiles": 4, "tiles_per_item": 64, "order": 1}),
+    ("c128", {"tile_bits": 11}),
+    ("c128", {"tile_bits": 12, "circuit_tiles": 1, "plan_search": 2, "tiles_per_item": 3}),
+])
+def test_batch_settings_match_oracle(q, dt, tuning):
+    """Every batched-mode setting (queue order, tile size, whole-circuit
+    cut-off, planning, item size) gives each circuit its oracle result,
+    with and without phase steps; the launch reports its passes and
+    algorithmic bytes."""
+    npd = np.complex64 if dt == "c64" else np.complex128
+    rng = np.random.default_rng(160 + len(str(tuning)))
+    circuits = W.batched_config(n=40, seed=161, m_range=(3, 19), l_range=(0, 150))
+    kinds = [(rng.random(c.L) < 0.15).astype(np.uint8) for c in circuits]
+    states, ins = [], []
+    for c in circuits:
+        k1 = W.gaussian_state(rng, c.M, npd)
+        s = q.State(c.M, dt)
+        s.write(k1)
+        states.append(s)
+        ins.append(k1)
+    say("batch settings", dt, tuning)
+    try:
+        q.batch_set_tuning(dt, tuning)
+        assert all(q.batch_get_tuning(dt)[k] == v for k, v in tuning.items())
+        q.apply_batch(states, [(c.target, c.cmask, kd) for c, kd in zip(circuits, kinds)], stream=0)
+        q.batch_status()
+        info = q.batch_last_info()
+        assert info["circuits"] == len(circuits) and info["kernel_ms"] > 0
+        assert all(info["tuning"][k] == v for k, v in tuning.items())
+        assert info["algorithmic_bytes"] >= sum(2 * (npd().itemsize << c.M) for c in circuits if c.L)
+        for c, s, k1, kd in zip(circuits, states, ins, kinds):
+            assert_same(s.read(), oracle.apply(c.M, k1, c.target, c.cmask, kind=kd), f"M={c.M} L={c.L} {tuning}")
+    finally:
+        q.batch_set_tuning(dt, None)
         for s in states:
             s.close()
