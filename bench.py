@@ -420,7 +420,8 @@ def main():
         t0 = time.perf_counter()
         tuned = st.autotune(tg, cm)
         autotune_s = round(time.perf_counter() - t0, 2)
-        tuning = {k: tuned[k] for k in ("tile_bits", "low_bits", "mid_low_bits", "kernel_variant", "rows_per_thread")}
+        tuning = {k: tuned[k] for k in ("tile_bits", "low_bits", "mid_low_bits", "kernel_variant", "rows_per_thread",
+                                        "plan_search")}
     masks, lens, _ = qsim.plan_describe(M, dt, tg, cm, tuning)
 
     for _ in range(args.warmup):

@@ -430,7 +430,7 @@ typedef struct {
     uint32_t kernel_variant; /* tile kernel: 1 = one tile per workgroup,
                                 2 = persistent workgroups with the next
                                 tile's loads in flight, 3 = persistent with
-                                loads two tiles ahead (QSIM_C64 only)       */
+                                loads two tiles ahead                       */
     uint32_t wg_per_cu;    /* persistent variant: workgroups per CU
                               (0 = as many as fit)                          */
     uint32_t outer_order;  /* order in which tiles are enumerated: 1 = the
@@ -460,8 +460,9 @@ typedef struct {
                               host time on up to 16 threads at M = 32,
                               L = 1000; diagrams with L x passes above 4e6
                               keep the climb's plan);
-                              0 = climb + beam for M >= 30 (climb alone for
-                              circuits of a batch)                         */
+                              0 = by size: climb + beam from M = 30; below
+                              it the greedy scan for QSIM_C64 and the climb
+                              for QSIM_C128                                */
     uint32_t xcd_swizzle;  /* 1 = off, 2 = on (default): the one-tile-per-
                               workgroup kernel maps 64 consecutive tiles to
                               one XCD (workgroups are dealt to the 8 XCDs in
@@ -488,7 +489,8 @@ int qsim_apply_tile_pass(qsim_state *state, uint64_t tile_mask,
 
 /* Choose the launch parameters of the fused path for this state and
  * diagram by measurement: every candidate (tile size, kernel shape, forced
- * low bits of the middle passes) applies the diagram once on the device,
+ * low bits of the middle passes, planner search) applies the diagram once
+ * on the device,
  * timed with events, then its reverse, which undoes it (each step matrix is
  * its own inverse, Sec. 2(a)); the state's contents are unchanged on
  * return.  The fastest candidate becomes the state's tuning and is copied

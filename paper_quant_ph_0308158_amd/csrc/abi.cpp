@@ -133,17 +133,22 @@ struct Tuning {
 };
 
 Tuning default_tuning(uint32_t elem) {
+    // 16-byte entries: 2^12-entry tiles (64 KiB, two one-tile workgroups
+    // per CU) planned with the mask climb and one forced low bit in the
+    // middle passes reach the pass count of 2^13-entry tiles with faster
+    // passes (M = 26, L = 200: 7 passes at 71.1 % of peak, 2.80 ms per
+    // apply, against 7 persistent passes of 2^13 entries at 68.9 %, 2.88 ms).
     Tuning t;
-    t.tile_bits = 13;                    // 64 KiB (8 B entries) / 128 KiB (16 B) of LDS per tile
+    t.tile_bits = elem == 8 ? 13 : 12;   // 64 KiB of LDS per tile
     t.low_bits = elem == 8 ? 5 : 4;      // >= 256 contiguous bytes per tile row run
     t.max_seg_steps = 1024;
     t.reorder = true;
     t.small_bits = elem == 8 ? 14 : 13;  // whole state in 128 KiB of LDS
-    t.variant = elem == 8 ? 0 : 1;       // 8 B: two one-tile workgroups per CU; 16 B: persistent
+    t.variant = 0;                       // two one-tile workgroups per CU
     t.wg_per_cu = 0;
     t.outer_order = 0;
     t.remap = true;
-    t.mid_low_bits = 2;
+    t.mid_low_bits = elem == 8 ? 2 : 1;
     t.min_overlap = 1;                   // no overlap requirement (measured best)
     t.rows_eb = 5;
     t.plan_search = -1;
@@ -181,7 +186,7 @@ int tuning_from(const qsim_tuning *in, uint32_t elem, Tuning *out) {
     }
     if (t.mid_low_bits < 1 || t.mid_low_bits > t.low_bits) t.mid_low_bits = t.low_bits;
     if (t.outer_order > 1) return fail(QSIM_ERR_INVALID, "outer_order out of range");
-    if (t.variant > 2 || (elem == 16 && t.variant > 1)) return fail(QSIM_ERR_INVALID, "kernel_variant out of range");
+    if (t.variant > 2) return fail(QSIM_ERR_INVALID, "kernel_variant out of range");
     if (t.wg_per_cu > 8) return fail(QSIM_ERR_INVALID, "wg_per_cu out of range");
     const int max_tile = elem == 8 ? kMaxTileBits : kMaxTileBits - 1;
     if (t.tile_bits < 5 || t.tile_bits > max_tile)
@@ -205,6 +210,7 @@ PlanConfig plan_config(const Tuning &t, uint32_t elem) {
     c.max_seg_steps = t.max_seg_steps;
     c.reorder = t.reorder;
     c.search = t.plan_search;
+    c.search_small = elem == 8 ? 0 : 1;   // by size, below M = 30: greedy (8 B), climb (16 B)
     c.remap = t.remap;
     return c;
 }
@@ -2104,12 +2110,16 @@ int qsim_autotune(qsim_state *s, const qsim_step *steps, uint64_t L, void *hip_s
     }
     // Candidates around the measured defaults: tile size, kernel shape and
     // the low bits of the middle passes.
-    struct Cand { int tile_bits; uint32_t variant; int mid_low; };
+    // -1 for plan_search keeps the state's planner setting; 1 is the mask
+    // climb, 2 the climb with the beam search over whole plans.
+    struct Cand { int tile_bits; uint32_t variant; int mid_low; int search; };
     std::vector<Cand> cands;
     if (s->elem == 8)
-        cands = {{13, 0, 2}, {13, 0, 3}, {13, 1, 2}, {14, 1, 2}, {14, 2, 2}, {12, 0, 2}};
+        cands = {{13, 0, 2, -1}, {13, 0, 3, -1}, {13, 1, 2, -1}, {14, 1, 2, -1}, {14, 2, 2, -1}, {12, 0, 2, -1},
+                 {13, 0, 2, 1}, {13, 0, 1, 2}};
     else
-        cands = {{13, 1, 2}, {13, 0, 2}, {12, 0, 2}, {12, 1, 2}, {13, 1, 3}};
+        cands = {{13, 1, 2, -1}, {13, 0, 2, -1}, {12, 0, 2, -1}, {12, 1, 2, -1}, {13, 1, 3, -1},
+                 {12, 0, 1, 1}, {12, 0, 1, 2}, {12, 0, 2, 1}, {13, 1, 1, 1}};
     std::vector<qsim_step> rev(steps, steps + L);
     std::reverse(rev.begin(), rev.end());
     DeviceGuard g(s->device);
@@ -2127,6 +2137,7 @@ int qsim_autotune(qsim_state *s, const qsim_step *steps, uint64_t L, void *hip_s
         t.tile_bits = std::min(c.tile_bits, s->elem == 8 ? kMaxTileBits : kMaxTileBits - 1);
         t.variant = c.variant;
         t.mid_low_bits = std::min(c.mid_low, t.low_bits);
+        if (c.search >= 0) t.plan_search = c.search;
         if ((uint32_t)t.tile_bits < t.rows_eb || (uint32_t)t.tile_bits - t.rows_eb > 10) continue;
         s->tune = t;
         if ((rc = qsim_apply_steps(s, rev.data(), L, st)) || (rc = qsim_apply_steps(s, steps, L, st))) break;

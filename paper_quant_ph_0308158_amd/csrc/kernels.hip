@@ -295,8 +295,18 @@ __device__ __forceinline__ uint64_t rec_base(const uint32_t *rec) {
 // gridDim.x, ...; the loads of each tile are issued DEPTH tiles ahead, into
 // one of DEPTH register buffers, so they overlap the gathers, stores and
 // walks of the tiles in between.
+// Most threads a tile workgroup can have: tiles hold at most 2^14 8-byte or
+// 2^13 16-byte entries, 2^EB per thread.  Bounding a kernel by its true
+// workgroup size lets the compiler give each thread the registers that
+// size leaves (a 256-thread workgroup of 16-byte entries has a whole SIMD's
+// register file per wave).
+template <int ELEM, int EB>
+constexpr int tile_threads_max() {
+    return std::min(1024, 1 << ((ELEM == 8 ? kMaxTileBits : kMaxTileBits - 1) - EB));
+}
+
 template <int ELEM, int DEPTH, int EB, bool SIGN>
-__global__ void __launch_bounds__(EB == 5 ? 512 : 1024) k_tile(const vec16 *__restrict__ src,
+__global__ void __launch_bounds__((tile_threads_max<ELEM, EB>())) k_tile(const vec16 *__restrict__ src,
                                                               vec16 *__restrict__ dst, TileArgs a,
                                                               uint64_t n_tiles) {
     extern __shared__ vec16 lds[];
@@ -304,22 +314,31 @@ __global__ void __launch_bounds__(EB == 5 ? 512 : 1024) k_tile(const vec16 *__re
     constexpr int NB = DEPTH > 0 ? DEPTH : 1;
     const uint32_t off_src = thread_offset<ELEM>(a.pos_src, a.tb, threadIdx.x);
     const uint32_t off_dst = thread_offset<ELEM>(a.pos_dst, a.tb, threadIdx.x);
+    // Workgroup b takes sequence numbers q = b, b + stride, ...; tile
+    // xcd_tile(q) is processed for q.  One tile per workgroup: runs of
+    // 2^a.xcd consecutive tiles go to one XCD.  Persistent workgroups keep
+    // tile q (the same mapping made them slower: 66.6 against 68.7 % of
+    // peak per pass for 16-byte entries at M = 26).
     const uint64_t stride = DEPTH > 0 ? gridDim.x : n_tiles;
-    const uint64_t b0 = DEPTH > 0 ? (uint64_t)blockIdx.x : xcd_tile(blockIdx.x, a.xcd);
+    const uint64_t q0 = blockIdx.x;
+    const uint32_t g = DEPTH > 0 ? 0u : a.xcd;
     vec16 v[NB][VPT];
 #pragma unroll
     for (int d = 0; d < NB; ++d) {
-        const uint64_t t = b0 + (uint64_t)d * stride;
-        if (t < n_tiles) load_tile<ELEM, EB>(v[d], src, rec_base(a.rec + t * a.rec_words) + off_src, a);
+        const uint64_t q = q0 + (uint64_t)d * stride;
+        if (q < n_tiles)
+            load_tile<ELEM, EB>(v[d], src, rec_base(a.rec + xcd_tile(q, g) * a.rec_words) + off_src, a);
     }
-    for (uint64_t first = b0;; first += (uint64_t)NB * stride) {
+    for (uint64_t first = q0;; first += (uint64_t)NB * stride) {
 #pragma unroll
         for (int d = 0; d < NB; ++d) {
-            const uint64_t tile = first + (uint64_t)d * stride;
-            if (tile >= n_tiles) return;   // uniform over the workgroup
-            const uint64_t next = tile + (uint64_t)NB * stride;
+            const uint64_t q = first + (uint64_t)d * stride;
+            if (q >= n_tiles) return;   // uniform over the workgroup
+            const uint64_t tile = xcd_tile(q, g);
+            const uint64_t next = q + (uint64_t)NB * stride;
             const uint64_t next_base =
-                (DEPTH > 0 && next < n_tiles) ? rec_base(a.rec + next * a.rec_words) + off_src : ~0ull;
+                (DEPTH > 0 && next < n_tiles) ? rec_base(a.rec + next * a.rec_words) + off_src
+                                              : ~0ull;
             tile_step<ELEM, EB, true, SIGN>(v[d], src, dst, outer_address(a, tile) + off_dst, next_base, a,
                                             a.rec + tile * a.rec_words + 2, lds);
             __syncthreads();
@@ -930,7 +949,7 @@ hipError_t launch_tile_t(const void *src, void *dst, uint64_t n_tiles, const Til
                          hipStream_t st) {
     const size_t lds = (size_t)ELEM << (a.tb + EB);
     const uint32_t threads = 1u << a.tb;
-    if (threads > (EB == 5 ? 512u : 1024u)) return hipErrorInvalidValue;
+    if (threads > (uint32_t)tile_threads_max<ELEM, EB>()) return hipErrorInvalidValue;
     hipError_t e;
     if ((e = allow_lds(k_tile<ELEM, DEPTH, EB, SIGN>, lds)) != hipSuccess) return e;
     uint64_t grid = n_tiles;
@@ -954,8 +973,7 @@ hipError_t launch_tile_t(const void *src, void *dst, uint64_t n_tiles, const Til
 template <int ELEM, int EB, bool SIGN>
 hipError_t launch_tile_s(const void *src, void *dst, uint64_t n_tiles, const TileArgs &a, uint32_t variant,
                          uint32_t wg_per_cu, hipStream_t st) {
-    if constexpr (ELEM == 8)
-        if (variant == 2) return launch_tile_t<ELEM, 2, EB, SIGN>(src, dst, n_tiles, a, wg_per_cu, st);
+    if (variant == 2) return launch_tile_t<ELEM, 2, EB, SIGN>(src, dst, n_tiles, a, wg_per_cu, st);
     if (variant >= 1) return launch_tile_t<ELEM, 1, EB, SIGN>(src, dst, n_tiles, a, wg_per_cu, st);
     return launch_tile_t<ELEM, 0, EB, SIGN>(src, dst, n_tiles, a, wg_per_cu, st);
 }
@@ -968,9 +986,8 @@ hipError_t launch_tile_e(const void *src, void *dst, uint64_t n_tiles, const Til
 }
 
 // variant 0: one tile per workgroup; 1: persistent, loads one tile ahead;
-// 2: persistent, loads two tiles ahead (8-byte entries only: the two
-// register buffers of 16-byte entries would not fit).  a.eb = log2 of the
-// rows per thread (3, 4 or 5).
+// 2: persistent, loads two tiles ahead.  a.eb = log2 of the rows per
+// thread (3, 4 or 5).
 hipError_t launch_tile(uint32_t elem, const void *src, void *dst, uint64_t n_tiles, const TileArgs &a,
                        uint32_t variant, uint32_t wg_per_cu, hipStream_t st) {
     if (elem == 8) {

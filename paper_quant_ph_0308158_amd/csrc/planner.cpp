@@ -500,7 +500,7 @@ std::vector<Pass> plan_passes(uint32_t M, const uint32_t *target, const uint64_t
     // commutation blocking, so its steps form a valid pass.  Level 2 adds a
     // beam search over whole plans (beam_plan); both are on by default from
     // M = 30, where a pass takes tens of milliseconds.
-    const int search = cfg.search >= 0 ? cfg.search : (M >= 30 ? 2 : 0);
+    const int search = cfg.search >= 0 ? cfg.search : (M >= 30 ? 2 : cfg.search_small);
 
     // One pass over the pending steps, starting from tile mask `start`.
     auto build_pass = [&](uint64_t start) {

@@ -26,7 +26,9 @@ struct PlanConfig {
     int max_seg_steps = 1024;
     bool reorder = true;
     int search = -1;        // tile-mask search: 0 off, 1 hill climb per pass, 2 climb + beam
-                            // search over whole plans, -1 climb + beam for M >= 30
+                            // search over whole plans, -1 by size: climb + beam for M >= 30,
+                            // search_small below
+    int search_small = 0;   // the search level of -1 below M = 30
     bool remap = true;      // permuted layouts between passes (middle tiles may use bits >= 32)
     int threads = 0;        // host threads of the beam search (0 = hardware threads, at most 16)
     int line_bits = 4;      // address bits a 128-byte line spans (4: 8-byte entries, 3: 16-byte)

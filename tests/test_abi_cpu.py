@@ -120,10 +120,11 @@ def _check_plan(M, dtype, tg, cm, tuning, kd=None):
     L = len(tg)
     assert sorted(order.tolist()) == list(range(L))
     assert int(lens.sum()) == L
-    K = min(tuning.get("tile_bits", 13), M)
-    low = min(tuning.get("low_bits", 5 if dtype == "c64" else 4), K)
+    K = min(tuning.get("tile_bits", 13 if dtype == "c64" else 12), M)
+    # the forced low bits leave a tile bit free when the state exceeds a tile
+    low = min(tuning.get("low_bits", 5 if dtype == "c64" else 4), K - 1 if M > K else K)
     cap = tuning.get("max_seg_steps", 1024)
-    mid = tuning.get("mid_low_bits", 2)
+    mid = tuning.get("mid_low_bits", 2 if dtype == "c64" else 1)
     mid = low if (tuning.get("remap", True) is False or mid > low) else mid
     pos = 0
     for p, (I, n) in enumerate(zip(masks.tolist(), lens.tolist())):
@@ -201,12 +202,13 @@ def test_beam_search_saves_passes(seed, M, tile_bits, dtype):
     original) and the same on every call (seeded draws, any thread count)."""
     rng = np.random.default_rng(seed)
     tg, cm = W.random_steps(rng, M, 150, (0, 3))
-    climb, _, _ = _check_plan(M, dtype, tg, cm, {"tile_bits": tile_bits, "plan_search": 2})
-    masks, lens, order = _check_plan(M, dtype, tg, cm, {"tile_bits": tile_bits, "plan_search": 3})
+    base = {"tile_bits": tile_bits, "mid_low_bits": 2}
+    climb, _, _ = _check_plan(M, dtype, tg, cm, {**base, "plan_search": 2})
+    masks, lens, order = _check_plan(M, dtype, tg, cm, {**base, "plan_search": 3})
     assert len(masks) < len(climb)
     k1 = W.tag_state(M)
     assert oracle.apply(M, k1, tg, cm).tobytes() == oracle.apply(M, k1, tg[order], cm[order]).tobytes()
-    again = qsim.plan_describe(M, dtype, tg, cm, {"tile_bits": tile_bits, "plan_search": 3})
+    again = qsim.plan_describe(M, dtype, tg, cm, {**base, "plan_search": 3})
     assert again[0].tolist() == masks.tolist() and again[2].tolist() == order.tolist()
 
 

@@ -109,6 +109,10 @@ def test_sizes_default_tuning(q, M, dt):
     (21, 20, np.complex64, {"tile_bits": 8, "plan_search": 3, "small_bits": 5}),
     (22, 18, np.complex128, {"tile_bits": 8, "plan_search": 3, "reorder": False, "small_bits": 5}),
     (23, 22, np.complex64, {"tile_bits": 10, "plan_search": 3, "mid_low_bits": 1}),
+    (24, 20, np.complex128, {"tile_bits": 13, "kernel_variant": 3}),
+    (25, 19, np.complex128, {"tile_bits": 12, "rows_per_thread": 16, "kernel_variant": 3}),
+    (26, 21, np.complex128, {"tile_bits": 13, "kernel_variant": 2, "xcd_swizzle": 1}),
+    (27, 22, np.complex64, {"tile_bits": 13, "kernel_variant": 2, "xcd_swizzle": 2}),
 ])
 def test_many_passes(q, seed, M, dt, tuning):
     """Small tiles force many passes, outer steps and tile relabelling."""
