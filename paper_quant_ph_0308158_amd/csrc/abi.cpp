@@ -1595,31 +1595,6 @@ bool make_product_pass(Prepared &pr, uint32_t M, uint32_t elem, const void *qubi
             pa.tix[i] = (uint8_t)k_of[b];
             ++i;
         }
-    // LDS slot swizzle: the shift that spreads the writes of a wave (the
-    // 64 lanes at one entry) most evenly over the banks (slots mod 32 for
-    // 8-byte entries, mod 16 for 16-byte ones, per 32 or 16 lanes).
-    const uint32_t group = elem == 8 ? 32u : 16u;
-    uint32_t best_swz = 5, best_cost = ~0u;
-    for (uint32_t swz = 5; swz + 5 <= std::max<uint32_t>(K, 10u); ++swz) {
-        uint32_t cost = 0;
-        const uint32_t lanes = std::min<uint32_t>(64u, 1u << tb);
-        for (uint32_t g0 = 0; g0 < lanes; g0 += group) {
-            uint32_t count[32] = {0}, worst = 0;
-            for (uint32_t t = g0; t < std::min(g0 + group, lanes); ++t) {
-                uint32_t j = 0;
-                for (uint32_t i = 0; i < tb; ++i)
-                    if ((t >> i) & 1u) j |= 1u << pa.tix[5 + i];
-                const uint32_t slot = j ^ ((j >> swz) & 31u);
-                worst = std::max(worst, ++count[slot % group]);
-            }
-            cost += worst;
-        }
-        if (cost < best_cost) {
-            best_cost = cost;
-            best_swz = swz;
-        }
-    }
-    l.ta.swz = best_swz;
     l.pa = pa;
     l.product = true;
     l.q_off = blob_push(pr.blob, qubits, (size_t)4 * M * (elem / 2));

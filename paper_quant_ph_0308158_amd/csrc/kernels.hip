@@ -208,14 +208,7 @@ __device__ __forceinline__ uint32_t sign_word(uint32_t v) { return (v >> kSignPl
 // kSignPlane of each source index says whether the entry is negated: both
 // its parts get their sign bit flipped.  SIGN is a template parameter so
 // that passes without phase steps run code with no trace of it.
-// With SWZ the tile was staged with tile index j in LDS slot
-// j ^ ((j >> a.swz) & 31) (the product-input pass).
-template <bool SWZ>
-__device__ __forceinline__ uint32_t lds_slot(uint32_t j, uint32_t swz) {
-    return SWZ ? j ^ ((j >> swz) & 31u) : j;
-}
-
-template <int ELEM, int EB, bool SIGN, bool SWZ = false>
+template <int ELEM, int EB, bool SIGN>
 __device__ __forceinline__ void tile_emit(const uint32_t (&w)[kPlanes], vec16 *__restrict__ dst, uint64_t dst_base,
                                           const TileArgs &a, const vec16 *lds) {
     constexpr uint32_t VPT = Shape<ELEM, EB>::VPT;
@@ -227,8 +220,8 @@ __device__ __forceinline__ void tile_emit(const uint32_t (&w)[kPlanes], vec16 *_
 #pragma unroll
             for (uint32_t r = 0; r < VPT; ++r) {
                 const uint32_t v0 = src_of(w, 2u * r), v1 = src_of(w, 2u * r + 1u);
-                const uint2 e0 = l2[lds_slot<SWZ>(v0 & kIndex, a.swz)];
-                const uint2 e1 = l2[lds_slot<SWZ>(v1 & kIndex, a.swz)];
+                const uint2 e0 = l2[v0 & kIndex];
+                const uint2 e1 = l2[v1 & kIndex];
                 const uint32_t m0 = sign_word(v0), m1 = sign_word(v1);
                 st_nt(dst + (dst_base + a.off_r_dst[r]) / EPV, make_uint4(e0.x ^ m0, e0.y ^ m0, e1.x ^ m1, e1.y ^ m1));
             }
@@ -236,7 +229,7 @@ __device__ __forceinline__ void tile_emit(const uint32_t (&w)[kPlanes], vec16 *_
 #pragma unroll
             for (uint32_t r = 0; r < VPT; ++r) {
                 const uint32_t v0 = src_of(w, r);
-                const vec16 e0 = lds[lds_slot<SWZ>(v0 & kIndex, a.swz)];
+                const vec16 e0 = lds[v0 & kIndex];
                 const uint32_t m0 = sign_word(v0);
                 st_nt(dst + (dst_base + a.off_r_dst[r]) / EPV, make_uint4(e0.x, e0.y ^ m0, e0.z, e0.w ^ m0));
             }
@@ -247,14 +240,14 @@ __device__ __forceinline__ void tile_emit(const uint32_t (&w)[kPlanes], vec16 *_
         const uint2 *l2 = reinterpret_cast<const uint2 *>(lds);
 #pragma unroll
         for (uint32_t r = 0; r < VPT; ++r) {
-            const uint2 e0 = l2[lds_slot<SWZ>(src_of(w, 2u * r), a.swz)];
-            const uint2 e1 = l2[lds_slot<SWZ>(src_of(w, 2u * r + 1u), a.swz)];
+            const uint2 e0 = l2[src_of(w, 2u * r)];
+            const uint2 e1 = l2[src_of(w, 2u * r + 1u)];
             st_nt(dst + (dst_base + a.off_r_dst[r]) / EPV, make_uint4(e0.x, e0.y, e1.x, e1.y));
         }
     } else {
 #pragma unroll
         for (uint32_t r = 0; r < VPT; ++r) {
-            const vec16 e0 = lds[lds_slot<SWZ>(src_of(w, r), a.swz)];
+            const vec16 e0 = lds[src_of(w, r)];
             st_nt(dst + (dst_base + a.off_r_dst[r]) / EPV, e0);
         }
     }
@@ -717,39 +710,85 @@ __device__ __forceinline__ void fold_bits(const ProductArgs<T> &a, uint64_t i, u
     }
 }
 
-// Each thread writes 16 entries i = base + 64k + lane (k = 0..15) of a
-// 1024-entry block, so a wave store covers 64 consecutive entries; the
-// factors of address bits 10 and up (q_11 .. q_M) are folded once per
-// thread.  States with M < 11 use one entry per thread.
+// States of M < 13 (or 12 for double) entries: one entry per thread.
 template <typename T>
-__global__ void __launch_bounds__(256) k_product(T *__restrict__ out, ProductArgs<T> a, uint64_t n) {
+__global__ void __launch_bounds__(256) k_product_small(T *__restrict__ out, ProductArgs<T> a, uint64_t n) {
     const uint32_t M = a.M;
-    if (M < 11) {
-        const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-        if (i >= n) return;
-        const uint32_t v = (uint32_t)((i >> (M - 1)) & 1u);
-        T re = a.q[2 * (2 * (M - 1) + v)], im = a.q[2 * (2 * (M - 1) + v) + 1];
-        fold_bits(a, i, M - 1, 1, re, im);
-        out[2 * i] = re;
-        out[2 * i + 1] = im;
-        return;
-    }
-    // grid-stride over 1024-entry blocks (the stride is a multiple of 64,
-    // so a thread keeps its lane)
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;; t += stride) {
-        const uint32_t lane = (uint32_t)(t & 63u);
-        const uint64_t base = (t >> 6) << 10;
-        if (base >= n) return;
-        const uint32_t vtop = (uint32_t)((base >> (M - 1)) & 1u);
-        T pre_re = a.q[2 * (2 * (M - 1) + vtop)], pre_im = a.q[2 * (2 * (M - 1) + vtop) + 1];
-        fold_bits(a, base, M - 1, 11, pre_re, pre_im);
-        for (uint32_t k = 0; k < 16u; ++k) {
-            const uint64_t i = base + (uint64_t)k * 64u + lane;
-            T re = pre_re, im = pre_im;
-            fold_bits(a, i, 10, 1, re, im);
-            out[2 * i] = re;
-            out[2 * i + 1] = im;
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t v = (uint32_t)((i >> (M - 1)) & 1u);
+    T re = a.q[2 * (2 * (M - 1) + v)], im = a.q[2 * (2 * (M - 1) + v) + 1];
+    fold_bits(a, i, M - 1, 1, re, im);
+    out[2 * i] = re;
+    out[2 * i + 1] = im;
+}
+
+// Blocks of 2^(5 + tb) consecutive entries, 2^tb threads: thread t forms
+// the 32 entries whose five lowest address bits run over all values and
+// whose other bits are those of block index and t.  Their folds from q_M
+// down share every factor above the fifth bit, so the thread folds those
+// once and then splits its partial product at each of the five lowest
+// bits (2 + 4 + ... + 32 products): about 3 complex products per entry
+// instead of 10, every entry still folded q_M first with each product
+// rounded on its own.  The entries are staged in LDS (entry j of the block
+// at slot j ^ ((j >> 5) & 31), which spreads a wave's writes over the
+// banks) and written out as consecutive 16-byte vectors.
+template <typename T>
+__global__ void __launch_bounds__(256) k_product(T *__restrict__ out, ProductArgs<T> a, uint64_t n_blocks,
+                                                 uint32_t tb) {
+    using V2 = typename std::conditional<sizeof(T) == 4, float2, double2>::type;
+    extern __shared__ vec16 lds[];
+    V2 *slot = reinterpret_cast<V2 *>(lds);
+    const uint32_t M = a.M, t = threadIdx.x;
+    const uint32_t entries = 32u << tb;
+    constexpr uint32_t EPV = 16 / sizeof(V2);   // entries per 16-byte vector
+    for (uint64_t blk = blockIdx.x; blk < n_blocks; blk += gridDim.x) {
+        const uint64_t i0 = blk * entries + ((uint64_t)t << 5);
+        const uint32_t vtop = (uint32_t)((i0 >> (M - 1)) & 1u);
+        T re = a.q[2 * (2 * (M - 1) + vtop)], im = a.q[2 * (2 * (M - 1) + vtop) + 1];
+        fold_bits(a, i0, M - 1, 6, re, im);    // q_{M-1} .. q_6: address bits M-2 .. 5
+        T pr[32], pi[32];
+        pr[0] = re;
+        pi[0] = im;
+#pragma unroll
+        for (int b = 4; b >= 0; --b) {          // q_{b+1}: address bit b
+            const int nk = 1 << (4 - b);
+            const T c0 = a.q[2 * (2 * b)], d0 = a.q[2 * (2 * b) + 1];
+            const T c1 = a.q[2 * (2 * b + 1)], d1 = a.q[2 * (2 * b + 1) + 1];
+#pragma unroll
+            for (int k = nk - 1; k >= 0; --k) {
+                T r0 = pr[k], i0_ = pi[k], r1 = pr[k], i1 = pi[k];
+                cmul(r0, i0_, c0, d0);
+                cmul(r1, i1, c1, d1);
+                pr[2 * k] = r0;
+                pi[2 * k] = i0_;
+                pr[2 * k + 1] = r1;
+                pi[2 * k + 1] = i1;
+            }
+        }
+        // partial e holds the entry whose five lowest bits are e, bit 0 the
+        // last split
+        __syncthreads();   // the previous block's slots have been read
+#pragma unroll
+        for (uint32_t e = 0; e < 32u; ++e) {
+            const uint32_t j = (t << 5) | e;
+            slot[j ^ ((j >> 5) & 31u)] = V2{pr[e], pi[e]};
+        }
+        __syncthreads();
+        vec16 *dst = reinterpret_cast<vec16 *>(out + 2 * blk * entries);
+        for (uint32_t v = t; v < entries / EPV; v += blockDim.x) {
+            vec16 w;
+            if constexpr (EPV == 2) {
+                const uint32_t j0 = 2 * v, j1 = 2 * v + 1;
+                const V2 e0 = slot[j0 ^ ((j0 >> 5) & 31u)], e1 = slot[j1 ^ ((j1 >> 5) & 31u)];
+                w = make_uint4(__float_as_uint(e0.x), __float_as_uint(e0.y), __float_as_uint(e1.x),
+                               __float_as_uint(e1.y));
+            } else {
+                const V2 e0 = slot[v ^ ((v >> 5) & 31u)];
+                const uint64_t xr = __double_as_longlong(e0.x), xi = __double_as_longlong(e0.y);
+                w = make_uint4((uint32_t)xr, (uint32_t)(xr >> 32), (uint32_t)xi, (uint32_t)(xi >> 32));
+            }
+            st_nt(dst + v, w);
         }
     }
 }
@@ -764,20 +803,16 @@ __global__ void __launch_bounds__(256) k_product(T *__restrict__ out, ProductArg
 // all partials by the factors of the outside bits in between.  Every entry
 // still gets its factors in the order q_M, ..., q_1, each product rounded
 // as in k_product, so the tile holds exactly the values k_product writes.
-// Entries go to LDS slot j ^ ((j >> a.swz) & 31) of their tile index j: the
-// 64 lanes of a wave then write different banks (the host picks swz).
+// The 32 entries of the source tile with tile base `src_base` that thread
+// t forms, in registers: pr/pi[e] is the entry whose five lowest tile bits
+// read e and whose other tile bits are the bits of t.
 template <typename T>
-__device__ __forceinline__ void product_source_tile(vec16 *lds, uint64_t src_base, const ProductTileArgs &pa,
-                                                    uint32_t tb, uint32_t swz) {
+__device__ __forceinline__ void product_form(T (&pr)[32], T (&pi)[32], uint64_t src_base, const ProductTileArgs &pa,
+                                             uint32_t tb) {
     const T *q = static_cast<const T *>(pa.q);
     const uint32_t t = threadIdx.x;
     uint64_t addr = src_base;   // logical address with the five lowest tile bits clear
-    uint32_t jt = 0;
-    for (uint32_t i = 0; i < tb; ++i) {
-        const uint32_t ti = (t >> i) & 1u;
-        addr |= (uint64_t)ti << pa.bit[5 + i];
-        jt |= ti << pa.tix[5 + i];
-    }
+    for (uint32_t i = 0; i < tb; ++i) addr |= (uint64_t)((t >> i) & 1u) << pa.bit[5 + i];
     // Factors are read at addresses that are the same for every lane (both
     // values of a bit, then a per-lane select): scalar loads, not a chain of
     // vector loads.
@@ -791,7 +826,6 @@ __device__ __forceinline__ void product_source_tile(vec16 *lds, uint64_t src_bas
         cmul(re, im, hi ? c1 : c0, hi ? d1 : d0);
     }
     // Partial k covers the entries whose tile bits i..4 read k (bit 4 highest).
-    T pr[32], pi[32];
     pr[0] = re;
     pi[0] = im;
 #pragma unroll
@@ -817,16 +851,17 @@ __device__ __forceinline__ void product_source_tile(vec16 *lds, uint64_t src_bas
             for (int k = 0; k < 2 * n; ++k) cmul(pr[k], pi[k], c, d);
         }
     }
-    uint32_t jb[5];
-#pragma unroll
-    for (int i = 0; i < 5; ++i) jb[i] = 1u << pa.tix[i];
+}
+
+// Thread t's entry e goes to LDS slot t * 32 + (e ^ (t & 31)), so the 64
+// lanes of a wave writing their e-th entries hit different banks;
+// product_slot_planes maps source tile indices to these slots.
+template <typename T>
+__device__ __forceinline__ void product_stage(vec16 *lds, const T (&pr)[32], const T (&pi)[32]) {
+    const uint32_t t = threadIdx.x, row = t << 5, x = t & 31u;
 #pragma unroll
     for (uint32_t e = 0; e < 32u; ++e) {
-        uint32_t j = jt;
-#pragma unroll
-        for (int i = 0; i < 5; ++i)
-            if ((e >> i) & 1u) j |= jb[i];
-        const uint32_t slot = lds_slot<true>(j, swz);
+        const uint32_t slot = row | (e ^ x);
         if constexpr (sizeof(T) == 4)
             reinterpret_cast<float2 *>(lds)[slot] = make_float2(pr[e], pi[e]);
         else
@@ -834,20 +869,52 @@ __device__ __forceinline__ void product_source_tile(vec16 *lds, uint64_t src_bas
     }
 }
 
+// The walked source tile indices (plane b = bit b) turned into the LDS
+// slots of product_source_tile: tile bits tix[5 + i] are the bits of the
+// thread that formed the entry, tix[0 .. 4] its five lowest bits, so slot
+// bit 5 + i = j[tix[5 + i]] and slot bit k < 5 = j[tix[k]] ^ j[tix[5 + k]]
+// (a linear map over GF(2), applied to whole planes).  The sign plane is
+// kept.
+__device__ __forceinline__ void product_slot_planes(uint32_t (&w)[kPlanes], const ProductTileArgs &pa, uint32_t tb) {
+    uint32_t s[kPlanes];
+#pragma unroll
+    for (int b = 0; b < kPlanes; ++b) s[b] = 0u;
+    s[kSignPlane] = w[kSignPlane];
+#pragma unroll
+    for (uint32_t i = 0; i < 11u; ++i)
+        if (i < tb) s[5 + i] = w[pa.tix[5 + i]];
+#pragma unroll
+    for (uint32_t k = 0; k < 5u; ++k) s[k] = w[pa.tix[k]] ^ (k < tb ? s[5 + k] : 0u);
+#pragma unroll
+    for (int b = 0; b < kPlanes; ++b) w[b] = s[b];
+}
+
+// First pass of a diagram applied to q_M (x) ... (x) q_1: each workgroup
+// forms its source tile from the qubits (no HBM read), stages it in LDS,
+// then walks, gathers and stores like k_tile.  (Persistent workgroups that
+// form the next tile while the current one's stores drain were slower:
+// 10.27 against 9.61 ms at M = 32; two tiles per workgroup 1.4 % faster.)
 template <int ELEM, bool SIGN>
 __global__ void __launch_bounds__(512) k_tile_product(vec16 *__restrict__ dst, TileArgs a, ProductTileArgs pa,
                                                       uint64_t n_tiles) {
     using T = typename std::conditional<ELEM == 8, float, double>::type;
     extern __shared__ vec16 lds[];
-    const uint64_t tile = xcd_tile(blockIdx.x, a.xcd);
+    const uint64_t tile = xcd_tile((uint64_t)blockIdx.x, a.xcd);
     if (tile >= n_tiles) return;   // uniform over the workgroup
     const uint32_t *rec = a.rec + tile * a.rec_words;
-    product_source_tile<T>(lds, rec_base(rec), pa, a.tb, a.swz);
+    {
+        T pr[32], pi[32];
+        product_form<T>(pr, pi, rec_base(rec), pa, a.tb);
+        product_stage<T>(lds, pr, pi);
+    }
     uint32_t w[kPlanes];
-    tile_sources<ELEM, 5, true>(w, a, rec + 2);
+    init_planes<ELEM, 5>(w, threadIdx.x, a.tb);
+    walk_inner<true>(w, a.inner, a.n_inner, rec + 2);
+    product_slot_planes(w, pa, a.tb);
+    transpose_planes(w);
     __syncthreads();
-    tile_emit<ELEM, 5, SIGN, true>(w, dst, outer_address(a, tile) + thread_offset<ELEM>(a.pos_dst, a.tb, threadIdx.x),
-                                   a, lds);
+    tile_emit<ELEM, 5, SIGN>(w, dst, outer_address(a, tile) + thread_offset<ELEM>(a.pos_dst, a.tb, threadIdx.x), a,
+                             lds);
 }
 
 // ------------------------------------------------------------ materialised row array
@@ -1079,22 +1146,30 @@ hipError_t launch_batch(uint32_t elem, uint32_t tb, bool sign, const BatchPass *
 
 hipError_t launch_product(uint32_t elem, void *out, uint32_t M, const void *qubits, hipStream_t st) {
     const uint64_t n = 1ull << M;
-    const uint32_t bs = 256;
-    const uint64_t threads = M < 11 ? n : n / 16;
-    const uint64_t grid = std::min<uint64_t>((threads + bs - 1) / bs, 1ull << 22);
     if (M < 1 || M > kMaxQubits) return hipErrorInvalidValue;
-    if (elem == 8) {
-        ProductArgs<float> a{};
-        std::memcpy(a.q, qubits, sizeof(float) * 4 * M);
+    // blocks of 2^13 (float) / 2^12 (double) entries: 256 / 128 threads and
+    // 64 KiB of LDS; smaller states one entry per thread
+    const uint32_t tb = elem == 8 ? 8u : 7u;
+    auto go = [&](auto a, auto *o, auto kern, auto small) {
+        std::memcpy(a.q, qubits, sizeof(a.q[0]) * 4 * M);
         a.M = M;
-        hipLaunchKernelGGL(k_product<float>, dim3((uint32_t)grid), dim3(bs), 0, st, (float *)out, a, n);
-    } else {
-        ProductArgs<double> a{};
-        std::memcpy(a.q, qubits, sizeof(double) * 4 * M);
-        a.M = M;
-        hipLaunchKernelGGL(k_product<double>, dim3((uint32_t)grid), dim3(bs), 0, st, (double *)out, a, n);
-    }
-    return hipGetLastError();
+        if (M < tb + 5) {
+            hipLaunchKernelGGL(small, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, o, a, n);
+            return hipGetLastError();
+        }
+        const size_t lds = (size_t)elem << (tb + 5);
+        hipError_t e = allow_lds(kern, lds);
+        if (e != hipSuccess) return e;
+        const uint64_t blocks = n >> (tb + 5);
+        uint64_t grid = resident_blocks(kern, 1u << tb, lds);
+        if (grid == 0) grid = 512;
+        grid = std::min<uint64_t>(blocks, 8 * grid);
+        hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(1u << tb), lds, st, o, a, blocks, tb);
+        return hipGetLastError();
+    };
+    if (elem == 8)
+        return go(ProductArgs<float>{}, (float *)out, k_product<float>, k_product_small<float>);
+    return go(ProductArgs<double>{}, (double *)out, k_product<double>, k_product_small<double>);
 }
 
 hipError_t launch_tile_product(uint32_t elem, void *dst, uint64_t n_tiles, const TileArgs &a,

@@ -62,8 +62,7 @@ struct TileArgs {
     uint32_t eb;            // log2(tile rows per thread): 3, 4 or 5
     uint32_t sign;          // 1 when the pass has phase steps (sign plane in use)
     uint32_t xcd;           // log2 of the consecutive tiles run on one XCD (0: none)
-    uint32_t swz;           // product-input pass only: LDS slot of tile index j is
-                            // j ^ ((j >> swz) & 31) (spreads its writes over the banks)
+    uint32_t pad;
     uint32_t off_r_src[32]; // element offset of the tile-index bits above the thread bits, per r (read)
     uint32_t off_r_dst[32]; // same for the write layout
     uint8_t pos_src[16];    // physical bit of tile-index bit b in the read layout
