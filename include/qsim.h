@@ -467,6 +467,14 @@ typedef struct {
                               workgroup kernel maps 64 consecutive tiles to
                               one XCD (workgroups are dealt to the 8 XCDs in
                               turn), so neighbouring tiles share an L2    */
+    uint32_t product_stage;/* first pass of qsim_apply_steps_product: what
+                              a workgroup forms in LDS.  1 = the whole
+                              source tile; 2 = the partial products down to
+                              address bit 1, each entry finished with one
+                              complex product as it is stored; 3 = down to
+                              bit 2, two products per entry (default: a
+                              quarter of the LDS, so more workgroups share
+                              a CU).  Same values whichever (Appendix 1). */
 } qsim_tuning;
 
 /* Set (tuning != NULL) or reset to defaults (NULL) the parameters used by

@@ -793,22 +793,31 @@ __global__ void __launch_bounds__(256) k_product(T *__restrict__ out, ProductArg
     }
 }
 
-// First pass of a diagram applied to q_M (x) ... (x) q_1: each workgroup
-// forms its source tile from the qubits in LDS (no HBM read), then walks,
-// gathers and stores like k_tile.  Thread t forms the 32 entries whose five
-// lowest tile bits run over all values and whose other tile bits are the
-// bits of t: their fold from q_M down shares every factor above the fifth
-// lowest tile bit, so a thread folds those once and then splits its partial
-// product at each of the five bits (2 + 4 + ... + 32 products), multiplying
-// all partials by the factors of the outside bits in between.  Every entry
-// still gets its factors in the order q_M, ..., q_1, each product rounded
-// as in k_product, so the tile holds exactly the values k_product writes.
-// The 32 entries of the source tile with tile base `src_base` that thread
-// t forms, in registers: pr/pi[e] is the entry whose five lowest tile bits
-// read e and whose other tile bits are the bits of t.
-template <typename T>
-__device__ __forceinline__ void product_form(T (&pr)[32], T (&pi)[32], uint64_t src_base, const ProductTileArgs &pa,
-                                             uint32_t tb) {
+// First pass of a diagram applied to q_M (x) ... (x) q_1.  No HBM read:
+// each workgroup forms, from the qubits, the partial products of its source
+// tile's entries, walks the pass's steps and stores the permuted entries.
+// The fold of an entry runs q_M, ..., q_1 (address bits from the top down),
+// so the entries of a tile that agree on every tile bit above bit[CUT - 1]
+// share the fold down to just above that bit.  Those 2^(K - CUT) partials
+// (the "table") are formed in LDS; at the store each output entry takes its
+// partial and folds in the factors of tile bits bit[CUT - 1], ..., bit[0],
+// which the first pass holds as address bits CUT - 1, ..., 0 (it keeps the
+// lowest bits in its tile).  CUT = 0 stages the whole tile; CUT = 1, 2
+// stage half or a quarter of it and finish each entry with one or two
+// complex products, which lets more workgroups share a CU (so one
+// workgroup's stores overlap the others' formation).  Every entry gets the
+// same products in the same order as k_product writes, whatever CUT.
+//
+// Thread t forms the 2^(5 - CUT) partials whose tile bits bit[CUT .. 4] run
+// over all values and whose other tile bits are the bits of t: their folds
+// share every factor above bit[4], so a thread folds those once and then
+// splits its partial product at each of bit[4], ..., bit[CUT]
+// (2 + 4 + ... products), multiplying all partials by the factors of the
+// outside bits in between, each product rounded as in k_product.
+// pr/pi[e] is the partial whose tile bits bit[CUT + k] read bit k of e.
+template <typename T, int CUT>
+__device__ __forceinline__ void product_form(T (&pr)[32 >> CUT], T (&pi)[32 >> CUT], uint64_t src_base,
+                                             const ProductTileArgs &pa, uint32_t tb) {
     const T *q = static_cast<const T *>(pa.q);
     const uint32_t t = threadIdx.x;
     uint64_t addr = src_base;   // logical address with the five lowest tile bits clear
@@ -829,7 +838,7 @@ __device__ __forceinline__ void product_form(T (&pr)[32], T (&pi)[32], uint64_t 
     pr[0] = re;
     pi[0] = im;
 #pragma unroll
-    for (int i = 4; i >= 0; --i) {
+    for (int i = 4; i >= CUT; --i) {
         const int n = 1 << (4 - i);
         const uint32_t b = pa.bit[i];
         const T c0 = q[4 * b], d0 = q[4 * b + 1], c1 = q[4 * b + 2], d1 = q[4 * b + 3];
@@ -853,14 +862,16 @@ __device__ __forceinline__ void product_form(T (&pr)[32], T (&pi)[32], uint64_t 
     }
 }
 
-// Thread t's entry e goes to LDS slot t * 32 + (e ^ (t & 31)), so the 64
-// lanes of a wave writing their e-th entries hit different banks;
-// product_slot_planes maps source tile indices to these slots.
-template <typename T>
-__device__ __forceinline__ void product_stage(vec16 *lds, const T (&pr)[32], const T (&pi)[32]) {
-    const uint32_t t = threadIdx.x, row = t << 5, x = t & 31u;
+// Thread t's partial e goes to LDS slot t * 2^X + (e ^ (t mod 2^X)),
+// X = 5 - CUT, so the lanes of a wave writing their e-th partials spread
+// over the banks; product_slot_planes maps source tile indices to these
+// slots.
+template <typename T, int CUT>
+__device__ __forceinline__ void product_stage(vec16 *lds, const T (&pr)[32 >> CUT], const T (&pi)[32 >> CUT]) {
+    constexpr uint32_t X = 5 - CUT, N = 1u << X;
+    const uint32_t t = threadIdx.x, row = t << X, x = t & (N - 1u);
 #pragma unroll
-    for (uint32_t e = 0; e < 32u; ++e) {
+    for (uint32_t e = 0; e < N; ++e) {
         const uint32_t slot = row | (e ^ x);
         if constexpr (sizeof(T) == 4)
             reinterpret_cast<float2 *>(lds)[slot] = make_float2(pr[e], pi[e]);
@@ -869,52 +880,112 @@ __device__ __forceinline__ void product_stage(vec16 *lds, const T (&pr)[32], con
     }
 }
 
-// The walked source tile indices (plane b = bit b) turned into the LDS
-// slots of product_source_tile: tile bits tix[5 + i] are the bits of the
-// thread that formed the entry, tix[0 .. 4] its five lowest bits, so slot
-// bit 5 + i = j[tix[5 + i]] and slot bit k < 5 = j[tix[k]] ^ j[tix[5 + k]]
-// (a linear map over GF(2), applied to whole planes).  The sign plane is
-// kept.
+// The walked source tile indices (plane b = tile-index bit b) turned into
+// LDS slots of product_stage plus the bits folded in at the store.  With
+// X = 5 - CUT: slot bit X + i = j[tix[5 + i]] (the bits of the thread that
+// formed the partial), slot bit k < X = j[tix[CUT + k]] ^ j[tix[5 + k]] (a
+// linear map over GF(2), applied to whole planes); plane 15 - CUT + i holds
+// j[tix[i]] for i < CUT (address bit i, folded in at the store); the sign
+// plane is kept.  Planes between the slot bits and those are zero.
+template <int CUT>
 __device__ __forceinline__ void product_slot_planes(uint32_t (&w)[kPlanes], const ProductTileArgs &pa, uint32_t tb) {
+    constexpr uint32_t X = 5 - CUT;
     uint32_t s[kPlanes];
 #pragma unroll
     for (int b = 0; b < kPlanes; ++b) s[b] = 0u;
     s[kSignPlane] = w[kSignPlane];
 #pragma unroll
-    for (uint32_t i = 0; i < 11u; ++i)
-        if (i < tb) s[5 + i] = w[pa.tix[5 + i]];
+    for (uint32_t i = 0; i < 10u; ++i)
+        if (i < tb) s[X + i] = w[pa.tix[5 + i]];
 #pragma unroll
-    for (uint32_t k = 0; k < 5u; ++k) s[k] = w[pa.tix[k]] ^ (k < tb ? s[5 + k] : 0u);
+    for (uint32_t k = 0; k < X; ++k) s[k] = w[pa.tix[CUT + k]] ^ (k < tb ? s[X + k] : 0u);
+#pragma unroll
+    for (uint32_t i = 0; i < (uint32_t)CUT; ++i) s[kSignPlane - CUT + i] = w[pa.tix[i]];
 #pragma unroll
     for (int b = 0; b < kPlanes; ++b) w[b] = s[b];
 }
 
-// First pass of a diagram applied to q_M (x) ... (x) q_1: each workgroup
-// forms its source tile from the qubits (no HBM read), stages it in LDS,
-// then walks, gathers and stores like k_tile.  (Persistent workgroups that
-// form the next tile while the current one's stores drain were slower:
-// 10.27 against 9.61 ms at M = 32; two tiles per workgroup 1.4 % faster.)
-template <int ELEM, bool SIGN>
-__global__ void __launch_bounds__(512) k_tile_product(vec16 *__restrict__ dst, TileArgs a, ProductTileArgs pa,
-                                                      uint64_t n_tiles) {
+// Store the calling thread's output entries of a CUT > 0 product pass: each
+// takes its partial from the table and folds in the factors of address bits
+// CUT - 1, ..., 0 that its source index carries, then gets the pass's sign.
+template <int ELEM, bool SIGN, int CUT>
+__device__ __forceinline__ void product_emit(const uint32_t (&w)[kPlanes], vec16 *__restrict__ dst, uint64_t dst_base,
+                                             const TileArgs &a, const ProductTileArgs &pa, const vec16 *lds) {
+    using T = typename std::conditional<ELEM == 8, float, double>::type;
+    using V2 = typename std::conditional<ELEM == 8, float2, double2>::type;
+    constexpr uint32_t VPT = Shape<ELEM, 5>::VPT;
+    constexpr uint32_t EPV = Shape<ELEM, 5>::EPV;
+    constexpr uint32_t kSlot = (1u << (kSignPlane - CUT)) - 1u;
+    const T *q = static_cast<const T *>(pa.q);
+    T f[CUT][4];   // q_{i+1}(0) and q_{i+1}(1) of address bit i
+#pragma unroll
+    for (int i = 0; i < CUT; ++i)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) f[i][k] = q[4 * i + k];
+    const V2 *tab = reinterpret_cast<const V2 *>(lds);
+    auto entry = [&](uint32_t v, T &re, T &im) {
+        const V2 e = tab[v & kSlot];
+        re = e.x;
+        im = e.y;
+#pragma unroll
+        for (int i = CUT - 1; i >= 0; --i) {
+            const bool h = (v >> (kSignPlane - CUT + i)) & 1u;
+            cmul(re, im, h ? f[i][2] : f[i][0], h ? f[i][3] : f[i][1]);
+        }
+    };
+#pragma unroll
+    for (uint32_t r = 0; r < VPT; ++r) {
+        if constexpr (ELEM == 8) {
+            const uint32_t v0 = src_of(w, 2u * r), v1 = src_of(w, 2u * r + 1u);
+            T r0, i0, r1, i1;
+            entry(v0, r0, i0);
+            entry(v1, r1, i1);
+            const uint32_t m0 = SIGN ? sign_word(v0) : 0u, m1 = SIGN ? sign_word(v1) : 0u;
+            st_nt(dst + (dst_base + a.off_r_dst[r]) / EPV,
+                  make_uint4(__float_as_uint(r0) ^ m0, __float_as_uint(i0) ^ m0, __float_as_uint(r1) ^ m1,
+                             __float_as_uint(i1) ^ m1));
+        } else {
+            const uint32_t v0 = src_of(w, r);
+            T r0, i0;
+            entry(v0, r0, i0);
+            const uint32_t m0 = SIGN ? sign_word(v0) : 0u;
+            const uint64_t xr = __double_as_longlong(r0), xi = __double_as_longlong(i0);
+            st_nt(dst + (dst_base + a.off_r_dst[r]) / EPV,
+                  make_uint4((uint32_t)xr, (uint32_t)(xr >> 32) ^ m0, (uint32_t)xi, (uint32_t)(xi >> 32) ^ m0));
+        }
+    }
+}
+
+// One source tile per workgroup: form the table (the whole tile for
+// CUT = 0), walk, gather and store like k_tile.  (Persistent workgroups
+// that formed the next whole tile while the current one's stores drained
+// were slower: 10.27 against 9.61 ms at M = 32.)  With CUT = 2 and no
+// phase steps the registers are held to what six waves per SIMD leave (six
+// 16 KiB tables per CU): 6.85 against 7.0 ms at M = 32.
+template <int ELEM, bool SIGN, int CUT>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CUT == 2 && !SIGN ? 6 : 1)))
+k_tile_product(vec16 *__restrict__ dst, TileArgs a, ProductTileArgs pa, uint64_t n_tiles) {
     using T = typename std::conditional<ELEM == 8, float, double>::type;
     extern __shared__ vec16 lds[];
     const uint64_t tile = xcd_tile((uint64_t)blockIdx.x, a.xcd);
     if (tile >= n_tiles) return;   // uniform over the workgroup
     const uint32_t *rec = a.rec + tile * a.rec_words;
     {
-        T pr[32], pi[32];
-        product_form<T>(pr, pi, rec_base(rec), pa, a.tb);
-        product_stage<T>(lds, pr, pi);
+        T pr[32 >> CUT], pi[32 >> CUT];
+        product_form<T, CUT>(pr, pi, rec_base(rec), pa, a.tb);
+        product_stage<T, CUT>(lds, pr, pi);
     }
     uint32_t w[kPlanes];
     init_planes<ELEM, 5>(w, threadIdx.x, a.tb);
     walk_inner<true>(w, a.inner, a.n_inner, rec + 2);
-    product_slot_planes(w, pa, a.tb);
+    product_slot_planes<CUT>(w, pa, a.tb);
     transpose_planes(w);
     __syncthreads();
-    tile_emit<ELEM, 5, SIGN>(w, dst, outer_address(a, tile) + thread_offset<ELEM>(a.pos_dst, a.tb, threadIdx.x), a,
-                             lds);
+    const uint64_t base = outer_address(a, tile) + thread_offset<ELEM>(a.pos_dst, a.tb, threadIdx.x);
+    if constexpr (CUT == 0)
+        tile_emit<ELEM, 5, SIGN>(w, dst, base, a, lds);
+    else
+        product_emit<ELEM, SIGN, CUT>(w, dst, base, a, pa, lds);
 }
 
 // ------------------------------------------------------------ materialised row array
@@ -1174,17 +1245,28 @@ hipError_t launch_product(uint32_t elem, void *out, uint32_t M, const void *qubi
 
 hipError_t launch_tile_product(uint32_t elem, void *dst, uint64_t n_tiles, const TileArgs &a,
                                const ProductTileArgs &pa, hipStream_t st) {
-    const size_t lds = (size_t)elem << (a.tb + 5);
     const uint32_t threads = 1u << a.tb;
-    if (a.eb != 5 || threads > 512u) return hipErrorInvalidValue;
+    if (a.eb != 5 || threads > 512u || pa.cut > 2u) return hipErrorInvalidValue;
+    const size_t lds = (size_t)elem << (a.tb + 5 - pa.cut);
     auto go = [&](auto kern) {
         hipError_t e = allow_lds(kern, lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(kern, dim3((uint32_t)n_tiles), dim3(threads), lds, st, (vec16 *)dst, a, pa, n_tiles);
         return hipGetLastError();
     };
-    if (elem == 8) return a.sign ? go(k_tile_product<8, true>) : go(k_tile_product<8, false>);
-    return a.sign ? go(k_tile_product<16, true>) : go(k_tile_product<16, false>);
+    auto by_cut = [&](auto e8, auto sign) {
+        constexpr int E = decltype(e8)::value;
+        constexpr bool S = decltype(sign)::value;
+        if (pa.cut == 1) return go(k_tile_product<E, S, 1>);
+        if (pa.cut == 2) return go(k_tile_product<E, S, 2>);
+        return go(k_tile_product<E, S, 0>);
+    };
+    using I8 = std::integral_constant<int, 8>;
+    using I16 = std::integral_constant<int, 16>;
+    using ST = std::true_type;
+    using SF = std::false_type;
+    if (elem == 8) return a.sign ? by_cut(I8{}, ST{}) : by_cut(I8{}, SF{});
+    return a.sign ? by_cut(I16{}, ST{}) : by_cut(I16{}, SF{});
 }
 
 hipError_t launch_iota(uint64_t *out, uint64_t n, hipStream_t st) {

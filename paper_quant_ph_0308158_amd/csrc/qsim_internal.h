@@ -75,7 +75,7 @@ struct TileArgs {
 struct ProductTileArgs {
     const void *q;          // q_b(v) at complex index 2(b-1) + v, in the entries' precision
     uint32_t M;
-    uint32_t pad;
+    uint32_t cut;           // partials staged down to just above address bit cut - 1 (0: whole tile)
     uint8_t bit[16];        // logical address bits of the tile, lowest first
     uint8_t tix[16];        // tile-index bit of bit[i]
 };

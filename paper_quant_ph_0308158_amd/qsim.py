@@ -82,7 +82,8 @@ class Tuning(ctypes.Structure):
                 ("wg_per_cu", ctypes.c_uint32), ("outer_order", ctypes.c_uint32),
                 ("remap", ctypes.c_uint32), ("mid_low_bits", ctypes.c_uint32),
                 ("min_overlap", ctypes.c_uint32), ("rows_per_thread", ctypes.c_uint32),
-                ("plan_search", ctypes.c_uint32), ("xcd_swizzle", ctypes.c_uint32)]
+                ("plan_search", ctypes.c_uint32), ("xcd_swizzle", ctypes.c_uint32),
+                ("product_stage", ctypes.c_uint32)]
 
 
 class BatchTuning(ctypes.Structure):

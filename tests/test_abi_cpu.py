@@ -92,6 +92,9 @@ def test_invalid_m_and_dtype():
         qsim.plan_describe(8, "c64", [0], [0], tuning={"tile_bits": 20})
     with pytest.raises(qsim.QsimError):
         qsim.plan_describe(8, "c64", [0], [0], tuning={"plan_search": 4})
+    with pytest.raises(qsim.QsimError):
+        qsim.plan_describe(8, "c64", [0], [0], tuning={"product_stage": 4})
+    qsim.plan_describe(8, "c64", [0], [0], tuning={"product_stage": 1})
 
 
 def test_unknown_step_kind_rejected():

@@ -74,6 +74,17 @@ def run_both(q, M, dt, qq, tg, cm, kd, tuning):
     (9, 16, np.complex64, {"tile_bits": 6, "low_bits": 3, "small_bits": 5}, False),
     (10, 19, np.complex128, {"tile_bits": 13, "kernel_variant": 2}, False),
     (11, 22, np.complex64, {}, False),
+    # what the first pass stages in LDS: the whole tile, partials down to
+    # bit 1 or to bit 2; tiles without address bit 1 fall back to the whole
+    # tile or the partials down to bit 1
+    (12, 17, np.complex64, {"tile_bits": 13, "product_stage": 1}, True),
+    (13, 18, np.complex128, {"tile_bits": 12, "product_stage": 2}, True),
+    (14, 20, np.complex64, {"tile_bits": 14, "product_stage": 2}, False),
+    (15, 19, np.complex64, {"tile_bits": 9, "low_bits": 2, "small_bits": 5, "product_stage": 3}, True),
+    (16, 18, np.complex64, {"tile_bits": 8, "low_bits": 1, "small_bits": 5, "product_stage": 3}, True),
+    (17, 17, np.complex128, {"tile_bits": 7, "low_bits": 1, "small_bits": 5, "product_stage": 3}, False),
+    (18, 21, np.complex128, {"tile_bits": 13, "kernel_variant": 2, "product_stage": 3}, True),
+    (19, 16, np.complex64, {"tile_bits": 14, "product_stage": 1}, False),
 ])
 def test_product_pass_matches_oracle(q, seed, M, dt, tuning, signed):
     rng = np.random.default_rng(900 + seed)
