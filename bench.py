@@ -69,9 +69,11 @@ def workload(name: str):
     raise ValueError(name)
 
 
-def stored_traffic(wl_name: str, kernel: str = "k_tile"):
+def stored_traffic(wl_name: str, kernel: str = "k_tile", alg_bytes=None):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source."""
+    summary, if it was taken on the current kernel source (and, given
+    `alg_bytes`, on a launch with the same algorithmic bytes: batched
+    mode's bytes depend on the parameters the autotuner picks)."""
     path = os.path.join(PROFILES, f"{kernel}_{wl_name}_pmc.md")
     if not os.path.exists(path):
         return None
@@ -81,6 +83,8 @@ def stored_traffic(wl_name: str, kernel: str = "k_tile"):
         return None
     d = json.loads(m.group(1))
     if d.get("kernel_sha") != kernel_hash():
+        return None
+    if alg_bytes is not None and d.get("algorithmic_bytes") != int(alg_bytes):
         return None
     return d.get("bytes_per_launch")
 
@@ -207,6 +211,18 @@ def bench_batched(reps: int = 3, plain_too: bool = True, autotune: bool = True):
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / k
         out[name] = {"ms": round(dt * 1e3, 3), "updates_per_s": updates / dt}
+    # steady state: device time per batch with a batch already in flight, so
+    # that every timed batch's host planning overlaps device work (the 20
+    # batches above include the first one's host time)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    batched()
+    e0.record()
+    for _ in range(10):
+        batched()
+    e1.record()
+    torch.cuda.synchronize()
+    out["batched"]["steady_ms"] = round(e0.elapsed_time(e1) / 10, 3)
     qsim.batch_status()
     # the kernel's own time, launch by launch (HIP events on its stream)
     infos = []
@@ -219,7 +235,7 @@ def bench_batched(reps: int = 3, plain_too: bool = True, autotune: bool = True):
     achieved = info["algorithmic_bytes"] / (kernel_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": "k_batch", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                "traffic": stored_traffic("batched_4096", kernel="k_batch"),
+                "traffic": stored_traffic("batched_4096", kernel="k_batch", alg_bytes=info["algorithmic_bytes"]),
                 "algorithmic_bytes_per_launch": int(info["algorithmic_bytes"]), "avg_launch_ms": round(kernel_ms, 4),
                 "launches": len(infos), "passes": info["passes"], "items": info["items"],
                 "workgroups": info["workgroups"]}

@@ -274,10 +274,10 @@ typedef struct {
     uint32_t circuit_tiles;  /* circuits whose passes have at most this many
                                 tiles run every pass in one workgroup (one
                                 queue item, no waits between passes);
-                                default 32; 1 = none                      */
+                                default 64; 1 = none                      */
     uint32_t plan_search;    /* pass planning of each circuit: 1 = greedy
-                                scan (default), 2 = with the mask climb
-                                (fewer passes, more host time)            */
+                                scan, 2 = with the mask climb (default:
+                                fewer passes, more host time)             */
     uint32_t order;          /* queue order: 1 = pass level by pass level,
                                 2 = critical path first (default): the host
                                 simulates the resident workgroups taking

@@ -12,7 +12,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
-#include <queue>
+#include <functional>
 #include <cmath>
 #include <new>
 #include <string>
@@ -811,8 +811,12 @@ namespace {
 struct BatchTune {
     uint32_t tiles_per_item = 32;
     uint32_t tile_bits = 0;        // 0: 13 for 8-byte entries, 12 for 16-byte ones
-    uint32_t circuit_tiles = 32;   // measured: 32 15.46 ms, 16 15.57, 8 15.67 per 4096-circuit batch
-    uint32_t plan_search = 1;      // 1 greedy scan, 2 with the mask climb
+    // measured per 4096-circuit batch (kernel): whole circuits up to 64
+    // tiles per pass 15.29 ms (32: 15.46, 16: 15.57, 8: 15.67); with the
+    // mask climb 14.94 ms (81.2 instead of 83.4 GB; host enqueue 11.5
+    // instead of 7.5 ms on 16 threads, still under the kernel)
+    uint32_t circuit_tiles = 64;
+    uint32_t plan_search = 2;      // 1 greedy scan, 2 with the mask climb
     uint32_t order = 2;            // 1 level by level, 2 critical path first
 };
 
@@ -935,58 +939,105 @@ struct SimItem {
 std::vector<uint64_t> order_critical_path(const std::vector<SimItem> &items, const std::vector<uint32_t> &pass_items,
                                           const std::vector<uint32_t> &pass_first, uint64_t workers, float slack) {
     // pass_items[p] = items of pass p, pass_first[p] = index of its first item
-    // (the items of a pass are consecutive)
+    // (the items of a pass are consecutive and share their priority)
     std::vector<uint32_t> left(pass_items);
-    auto cmp = [&](uint32_t a, uint32_t b) {   // max-heap on prio, then creation order
-        if (items[a].prio != items[b].prio) return items[a].prio < items[b].prio;
-        return a > b;
-    };
-    std::vector<uint32_t> ready;
+    // Heap keys: non-negative floats order like their bit patterns.  The
+    // ready heap holds runs of consecutive items of equal priority (a pass,
+    // or one independent item) as (prio bits, ~first index): highest
+    // priority first, then the lowest index, the order of taking the items
+    // one by one.  A run stays on top while it hands out its items.  The
+    // event heap holds (time bits, id), earliest first.
+    auto fbits = [](float f) { uint32_t u; std::memcpy(&u, &f, 4); return (uint64_t)u; };
+    auto ready_key = [&](uint32_t i) { return fbits(items[i].prio) << 32 | (uint64_t)(~i); };
+    std::vector<uint64_t> ready;
+    std::vector<uint32_t> run_end(items.size(), 0);   // for the first item of a run: one past its last
     ready.reserve(items.size());
     std::vector<uint8_t> has_pred(items.size(), 0);
     for (const SimItem &it : items)
         if (it.next_pass != ~0u) has_pred[it.next_pass] = 1;
-    for (uint32_t i = 0; i < items.size(); ++i) {
+    for (uint32_t i = 0; i < items.size();) {
         const uint32_t p = items[i].pass_id;
+        const uint32_t n = p == ~0u ? 1u : pass_items[p];
+        for (uint32_t j = i; j < i + n; ++j) run_end[j] = i + n;
         // ready at the start: independent items and the first pass of each chain
-        const bool dependent = p != ~0u && has_pred[pass_first[p]];
-        if (!dependent) ready.push_back(i);
+        if (p == ~0u || !has_pred[pass_first[p]]) ready.push_back(ready_key(i));
+        i += n;
     }
-    std::make_heap(ready.begin(), ready.end(), cmp);
-    using Ev = std::pair<float, uint32_t>;   // (time, item): item finishes, or (with the top bit) a pass becomes ready
-    std::priority_queue<Ev, std::vector<Ev>, std::greater<Ev>> events;
+    std::make_heap(ready.begin(), ready.end());
+    std::vector<uint64_t> events;
+    events.reserve(2 * std::max<uint64_t>(workers, 1) + pass_items.size());
+    auto later = std::greater<uint64_t>();
     std::vector<uint64_t> order;
     order.reserve(items.size());
     float now = 0;
     uint64_t free_w = std::max<uint64_t>(workers, 1);
     while (order.size() < items.size()) {
         while (free_w > 0 && !ready.empty()) {
-            std::pop_heap(ready.begin(), ready.end(), cmp);
-            const uint32_t i = ready.back();
-            ready.pop_back();
+            const uint32_t i = ~(uint32_t)ready.front();
+            if (i + 1 < run_end[i]) {
+                ready.front() = ready_key(i + 1);   // still the largest key
+            } else {
+                std::pop_heap(ready.begin(), ready.end());
+                ready.pop_back();
+            }
             order.push_back(items[i].word);
-            events.push({now + items[i].dur, i});
+            events.push_back(fbits(now + items[i].dur) << 32 | i);
+            std::push_heap(events.begin(), events.end(), later);
             --free_w;
         }
         if (events.empty()) break;   // cannot happen: every pass follows one that finishes
-        const Ev ev = events.top();
-        events.pop();
-        now = ev.first;
-        if (ev.second & 0x80000000u) {   // the next pass of a chain becomes ready
-            const uint32_t f = ev.second & 0x7FFFFFFFu, p = items[f].pass_id;
-            for (uint32_t j = f; j < f + pass_items[p]; ++j) {
-                ready.push_back(j);
-                std::push_heap(ready.begin(), ready.end(), cmp);
-            }
+        std::pop_heap(events.begin(), events.end(), later);
+        const uint64_t ev = events.back();
+        events.pop_back();
+        const uint32_t id = (uint32_t)ev;
+        const uint32_t tbits = (uint32_t)(ev >> 32);
+        std::memcpy(&now, &tbits, 4);
+        if (id & 0x80000000u) {   // the next pass of a chain becomes ready
+            ready.push_back(ready_key(id & 0x7FFFFFFFu));
+            std::push_heap(ready.begin(), ready.end());
             continue;
         }
         ++free_w;
-        const SimItem &it = items[ev.second];
-        if (it.pass_id != ~0u && --left[it.pass_id] == 0 && it.next_pass != ~0u)
-            events.push({now + slack, it.next_pass | 0x80000000u});
+        const SimItem &it = items[id];
+        if (it.pass_id != ~0u && --left[it.pass_id] == 0 && it.next_pass != ~0u) {
+            events.push_back(fbits(now + slack) << 32 | (it.next_pass | 0x80000000u));
+            std::push_heap(events.begin(), events.end(), later);
+        }
     }
     return order;
 }
+
+// fn(i) for i < n on up to 16 host threads, indices handed out one at a
+// time (n / grain threads at most).
+template <typename F>
+void host_parallel(uint32_t n, uint32_t grain, F &&fn) {
+    const uint32_t hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    const uint32_t nt = std::min<uint32_t>(hw, (n + grain - 1) / grain);
+    std::atomic<uint32_t> next{0};
+    auto worker = [&]() {
+        for (uint32_t i; (i = next.fetch_add(1)) < n;) fn(i);
+    };
+    std::vector<std::thread> pool;
+    for (uint32_t t = 1; t < nt; ++t) pool.emplace_back(worker);
+    worker();
+    for (auto &t : pool) t.join();
+}
+
+// Host-side buffers of batch_enqueue, kept per calling thread from one
+// batch to the next: a batch of thousands of circuits fills megabytes of
+// plans and descriptors, and fresh allocations of that size would be
+// page-faulted in again on every call.
+struct BatchHostScratch {
+    std::vector<BatchCircuitPlan> plans;
+    std::vector<BatchPass> bpass;
+    std::vector<BatchSmall> bsmall;
+    std::vector<size_t> small_blob_off, pass_blob_off, circuit_blob_off;
+    std::vector<uint32_t> small_circuit;
+    std::vector<std::pair<uint32_t, uint32_t>> circuit_first_pass;
+    std::vector<SimItem> sim;
+    std::vector<uint32_t> pass_items, pass_first;
+    std::vector<uint32_t> circ_pass0, circ_small;   // per circuit: its first pass / its small entry
+};
 
 int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, const uint64_t *Ls, uint32_t n,
                   hipStream_t st) {
@@ -1014,11 +1065,19 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
 
     // 1. validate and plan every circuit (host threads); nothing is
     // enqueued unless every circuit passes
-    std::vector<BatchCircuitPlan> plans(n);
+    static thread_local BatchHostScratch hs;
+    std::vector<BatchCircuitPlan> &plans = hs.plans;
+    if (plans.size() < n) plans.resize(n);
     auto plan_one = [&](uint32_t c) {
         qsim_state *s = states[c];
         const uint64_t L = Ls[c];
         BatchCircuitPlan &bp = plans[c];
+        bp.pr.blob.clear();
+        bp.pr.launches.clear();
+        bp.pr.rec_bytes = 0;
+        bp.small = bp.direct = false;
+        bp.rc = QSIM_OK;
+        bp.err.clear();
         if ((bp.rc = validate_steps(s->M, steps[c], L))) {
             bp.err = g_err;
             return;
@@ -1049,95 +1108,114 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
             }
         }
     };
-    {
-        const uint32_t hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-        const uint32_t nt = std::min<uint32_t>(hw, (n + 63) / 64);
-        std::atomic<uint32_t> next{0};
-        auto worker = [&]() {
-            for (uint32_t c; (c = next.fetch_add(1)) < n;) plan_one(c);
-        };
-        std::vector<std::thread> pool;
-        for (uint32_t t = 1; t < nt; ++t) pool.emplace_back(worker);
-        worker();
-        for (auto &t : pool) t.join();
-    }
+    host_parallel(n, 64, plan_one);
     for (uint32_t c = 0; c < n; ++c)
         if (plans[c].rc) return fail(plans[c].rc, "circuit " + std::to_string(c) + ": " + plans[c].err);
     lap("plan");
 
     // 2. descriptors: passes of the tiled circuits, the small circuits,
     // and where each circuit's blob goes
-    std::vector<BatchPass> bpass;
-    std::vector<BatchSmall> bsmall;
-    std::vector<size_t> small_blob_off, pass_blob_off;   // per entry: offset of its circuit blob
-    std::vector<uint32_t> small_circuit;
-    std::vector<std::pair<uint32_t, uint32_t>> circuit_first_pass;   // (circuit, index of its first pass)
-    std::vector<size_t> circuit_blob_off(n, 0);
+    std::vector<BatchPass> &bpass = hs.bpass;
+    std::vector<BatchSmall> &bsmall = hs.bsmall;
+    std::vector<size_t> &small_blob_off = hs.small_blob_off;   // per entry: offset of its circuit blob
+    std::vector<size_t> &pass_blob_off = hs.pass_blob_off;
+    std::vector<uint32_t> &small_circuit = hs.small_circuit;
+    std::vector<std::pair<uint32_t, uint32_t>> &circuit_first_pass = hs.circuit_first_pass;   // (circuit, its first pass)
+    std::vector<size_t> &circuit_blob_off = hs.circuit_blob_off;
+    circuit_blob_off.assign(n, 0);
     size_t blob_size = 0;
     uint32_t rec_stride = 2;
     uint64_t max_tiles = 0;
     bool any_sign = false;   // some tile or small item has phase steps
     uint64_t alg_bytes = 0;
     uint32_t n_passes = 0;
+    // Where each circuit's entries go, and the checks (a few fields of each
+    // launch); then the descriptors themselves, circuits in parallel.
+    std::vector<uint32_t> &circ_pass0 = hs.circ_pass0, &circ_small = hs.circ_small;
+    circ_pass0.assign(n, ~0u);
+    circ_small.assign(n, ~0u);
+    circuit_first_pass.clear();
+    uint32_t n_bpass = 0, n_bsmall = 0;
     for (uint32_t c = 0; c < n; ++c) {
+        const BatchCircuitPlan &bp = plans[c];
         circuit_blob_off[c] = blob_size;
-        blob_size += (plans[c].pr.blob.size() + 255) & ~size_t(255);
-    }
-    for (uint32_t c = 0; c < n; ++c) {
-        BatchCircuitPlan &bp = plans[c];
-        qsim_state *s = states[c];
+        blob_size += (bp.pr.blob.size() + 255) & ~size_t(255);
         if (bp.pr.launches.empty()) continue;
-        const uint64_t state_bytes = (uint64_t)elem << s->M;
+        const uint64_t state_bytes = (uint64_t)elem << states[c]->M;
         if (bp.direct || bp.small) {
+            circ_small[c] = n_bsmall++;
+            any_sign |= bp.pr.launches[0].ta.sign != 0;
+            alg_bytes += 2 * state_bytes;
+            ++n_passes;
+            continue;
+        }
+        const uint64_t n_tiles = 1ull << (states[c]->M - Kb);
+        uint32_t level = 0;
+        for (size_t i = 0; i + 1 < bp.pr.launches.size(); i += 2, ++level) {
+            const Launch &lt = bp.pr.launches[i + 1];
+            // every pass of a circuit has 2^(M - tile bits) tiles of one shape
+            if (lt.n_tiles != n_tiles || lt.ta.tb != tb || lt.ta.eb != 5)
+                return fail(QSIM_ERR_INVALID, "circuit " + std::to_string(c) + ": a pass has another tile shape");
+            any_sign |= lt.ta.sign != 0;
+            rec_stride = std::max(rec_stride, lt.ta.rec_words);
+        }
+        // the per-circuit counter counts every finished tile of the circuit
+        if ((uint64_t)level * n_tiles > 0xFFFFFFFFull)
+            return fail(QSIM_ERR_INVALID, "circuit " + std::to_string(c) + ": passes x tiles beyond 2^32 - 1");
+        circ_pass0[c] = n_bpass;
+        circuit_first_pass.push_back({c, n_bpass});
+        n_bpass += level;
+        alg_bytes += 2 * state_bytes * level;
+        n_passes += level;
+        max_tiles = std::max(max_tiles, n_tiles);
+    }
+    // (every entry is overwritten below: no clearing of the kept capacity)
+    bpass.resize(n_bpass);
+    pass_blob_off.resize(n_bpass);
+    bsmall.resize(n_bsmall);
+    small_blob_off.resize(n_bsmall);
+    small_circuit.resize(n_bsmall);
+    host_parallel(n, 256, [&](uint32_t c) {
+        const BatchCircuitPlan &bp = plans[c];
+        const qsim_state *s = states[c];
+        if (circ_small[c] != ~0u) {
+            const uint32_t k = circ_small[c];
             const Launch &l = bp.pr.launches[0];
             BatchSmall sm{};
             sm.ta = l.ta;
-            any_sign |= sm.ta.sign != 0;
             sm.src = s->buf[s->cur];
             sm.dst = s->buf[s->cur ^ 1];
             sm.L = l.n;
             sm.M = s->M;
             sm.direct = bp.direct ? 1u : 0u;
-            bsmall.push_back(sm);
-            small_blob_off.push_back(circuit_blob_off[c] + (bp.direct ? l.steps_off : l.inner_off));
-            small_circuit.push_back(c);
-            alg_bytes += 2 * state_bytes;
-            ++n_passes;
-            continue;
+            bsmall[k] = sm;
+            small_blob_off[k] = circuit_blob_off[c] + (bp.direct ? l.steps_off : l.inner_off);
+            small_circuit[k] = c;
+            return;
         }
-        uint32_t level = 0;
-        circuit_first_pass.push_back({c, (uint32_t)bpass.size()});
-        const uint64_t n_tiles = 1ull << (s->M - Kb);
-        for (size_t i = 0; i + 1 < bp.pr.launches.size(); i += 2, ++level) {
+        if (circ_pass0[c] == ~0u) return;
+        uint32_t g = circ_pass0[c], level = 0;
+        for (size_t i = 0; i + 1 < bp.pr.launches.size(); i += 2, ++level, ++g) {
             const Launch &lm = bp.pr.launches[i], &lt = bp.pr.launches[i + 1];
-            // every pass of a circuit has 2^(M - tile bits) tiles of one shape
-            if (lt.n_tiles != n_tiles || lt.ta.tb != tb || lt.ta.eb != 5)
-                return fail(QSIM_ERR_INVALID, "circuit " + std::to_string(c) + ": a pass has another tile shape");
-            BatchPass p{};
+            BatchPass &p = bpass[g];
+            p = BatchPass{};
             p.ta = lt.ta;
-            any_sign |= p.ta.sign != 0;
             p.tm = lm.tm;
             p.src = s->buf[s->cur ^ (level & 1u)];
             p.dst = s->buf[s->cur ^ ((level + 1) & 1u)];
             p.n_tiles = lt.n_tiles;
             p.circuit = c;
             p.level = level;
-            bpass.push_back(p);
-            pass_blob_off.push_back(circuit_blob_off[c]);
             // remember both step-array offsets inside the circuit blob
-            bpass.back().ta.inner = reinterpret_cast<const uint32_t *>(lt.inner_off);
-            bpass.back().ta.rec = nullptr;
-            bpass.back().tm.steps = reinterpret_cast<const TmStep *>(lm.steps_off);
-            bpass.back().tm.rec = nullptr;
-            rec_stride = std::max(rec_stride, lt.ta.rec_words);
-            alg_bytes += 2 * state_bytes;
-            ++n_passes;
+            p.ta.inner = reinterpret_cast<const uint32_t *>(lt.inner_off);
+            p.ta.rec = nullptr;
+            p.tm.steps = reinterpret_cast<const TmStep *>(lm.steps_off);
+            p.tm.rec = nullptr;
+            pass_blob_off[g] = circuit_blob_off[c];
         }
-        // the per-circuit counter counts every finished tile of the circuit
-        if ((uint64_t)level * n_tiles > 0xFFFFFFFFull)
-            return fail(QSIM_ERR_INVALID, "circuit " + std::to_string(c) + ": passes x tiles beyond 2^32 - 1");
-        max_tiles = std::max(max_tiles, n_tiles);
-    }
+    });
+
+    lap("describe");
 
     // 3. the items: one per small circuit, one per mid-size circuit (every
     // pass in one workgroup: no waits between its passes), and blocks of
@@ -1157,11 +1235,16 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
     hipError_t e = batch_grid(elem, tb, any_sign, lds, &workers);
     if (e != hipSuccess) return fail(QSIM_ERR_DEVICE, std::string("batch occupancy: ") + hipGetErrorString(e));
 
+    lap("occupancy");
+
     std::vector<uint64_t> items;
     const size_t n_small = bsmall.size();
     if (tune.order == 2) {
-        std::vector<SimItem> sim;
-        std::vector<uint32_t> pass_items, pass_first;
+        std::vector<SimItem> &sim = hs.sim;
+        std::vector<uint32_t> &pass_items = hs.pass_items, &pass_first = hs.pass_first;
+        sim.clear();
+        pass_items.clear();
+        pass_first.clear();
         const float kItemCost = 0.25f;   // per-item cost in tiles (wait, drain, first load)
         const float kSlack = 2.0f;       // a pass's successors become ready this many tiles after it ends
         for (size_t k = 0; k < n_small; ++k) {
@@ -1194,6 +1277,7 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
                 prev_first = first;
             }
         }
+        lap("items");
         items = order_critical_path(sim, pass_items, pass_first, workers, kSlack);
         if (items.size() != sim.size()) return fail(QSIM_ERR_INVALID, "batch: queue ordering failed");
     } else {
@@ -2034,8 +2118,8 @@ int qsim_batch_autotune(qsim_state *const *states, const qsim_step *const *steps
     const std::vector<std::pair<int, std::vector<uint32_t>>> space = {
         {0, {1}},                  // order: level by level
         {1, {kb - 1}},             // tile bits: one less
-        {2, {2}},                  // planning with the mask climb
-        {3, {1, 8, 16, 64, 128}},  // whole-circuit cut-off (1 = none)
+        {2, {1}},                  // planning with the greedy scan alone
+        {3, {1, 8, 16, 32, 128}},  // whole-circuit cut-off (1 = none)
         {4, {8, 16, 64}},          // tiles per item
     };
     for (const auto &dim : space) {

@@ -407,7 +407,7 @@ def test_batch_tuning_setting():
     """qsim_batch_set_tuning validates its fields and keeps one setting per
     dtype (host only)."""
     default = qsim.batch_get_tuning("c64")
-    assert default == {"tiles_per_item": 32, "tile_bits": 13, "circuit_tiles": 32, "plan_search": 1, "order": 2}
+    assert default == {"tiles_per_item": 32, "tile_bits": 13, "circuit_tiles": 64, "plan_search": 2, "order": 2}
     assert qsim.batch_get_tuning("c128")["tile_bits"] == 12
     qsim.batch_set_tuning("c128", {"tile_bits": 11, "order": 1})
     assert qsim.batch_get_tuning("c128")["tile_bits"] == 11 and qsim.batch_get_tuning("c64") == default
