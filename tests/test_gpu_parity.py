@@ -560,6 +560,49 @@ def test_batches_back_to_back(q):
         s.close()
 
 
+def test_batches_of_changing_size(q):
+    """The host keeps its batch buffers (plans, pass and small-circuit
+    descriptors, queue) from one call to the next: a large batch, then a
+    batch of a few other circuits (fewer passes and descriptors than the
+    buffers hold), then a batch with phase steps, then a subset of the
+    first circuits again, queued back to back.  Every state equals the
+    oracle's result of the diagrams applied to it, in order."""
+    rng = np.random.default_rng(150)
+    big = W.batched_config(n=80, seed=151, m_range=(3, 19), l_range=(0, 200))
+    few = W.batched_config(n=5, seed=152, m_range=(14, 17), l_range=(1, 60))
+    signed = W.batched_config(n=12, seed=153, m_range=(4, 16), l_range=(1, 90))
+    groups = [big, few, signed, big[10:30]]
+    states, ins, expect = {}, {}, {}
+    for gi, g in enumerate(groups[:3]):
+        for ci, c in enumerate(g):
+            k1 = W.gaussian_state(rng, c.M, np.complex64)
+            s = q.State(c.M, "c64")
+            s.write(k1)
+            states[(gi, ci)] = s
+            ins[(gi, ci)] = k1
+            expect[(gi, ci)] = k1
+    kinds = [(rng.random(c.L) < 0.3).astype(np.uint8) for c in signed]
+    say("batches of changing size")
+    for gi, g in enumerate(groups):
+        key_g = gi if gi < 3 else 0
+        off = 10 if gi == 3 else 0
+        sts, steps = [], []
+        for ci, c in enumerate(g):
+            key = (key_g, ci + off)
+            sts.append(states[key])
+            if gi == 2:
+                steps.append((c.target, c.cmask, kinds[ci]))
+                expect[key] = oracle.apply(c.M, expect[key], c.target, c.cmask, kind=kinds[ci])
+            else:
+                steps.append((c.target, c.cmask))
+                expect[key] = oracle.apply(c.M, expect[key], c.target, c.cmask)
+        q.apply_batch(sts, steps, stream=0)
+    q.batch_status()
+    for key, s in states.items():
+        assert_same(s.read(), expect[key], f"circuit {key}")
+        s.close()
+
+
 def test_batch_invalid_step_runs_nothing(q):
     """A bad step in any circuit rejects the whole batch before anything is
     enqueued: every state keeps its contents."""
