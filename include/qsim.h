@@ -207,9 +207,13 @@ int qsim_apply_steps_noalloc(qsim_state *state, const qsim_step *steps, uint64_t
 int qsim_rowmap_build(uint32_t M, const qsim_step *steps, uint64_t L,
                       uint32_t *x_dev, void *hip_stream);
 
-/* current <- k1(x(i)) for the row array x_dev of qsim_rowmap_build: the
- * same result as applying the diagram again, as one gather (a read of x,
- * a read of the state at the rows x names, a write of the state). */
+/* current <- k1(x(i)) for the row array x_dev of qsim_rowmap_build (the
+ * gather form k2(i) = k1(x(i)) of Sec. 2(b), end): the same result as
+ * applying the diagram again, as one gather (a read of x, a read of the
+ * state at the rows x names, a write of the state).  x_dev: 2^M uint32 on
+ * the state's device, caller-owned; asynchronous on hip_stream.
+ * QSIM_ERR_INVALID for a NULL x_dev or a state above M = 32, QSIM_ERR_DEVICE
+ * (state poisoned) on a HIP error. */
 int qsim_rowmap_apply(qsim_state *state, const uint32_t *x_dev, void *hip_stream);
 
 /* Same result as qsim_apply_steps, computed the plain way: one in-place
@@ -294,13 +298,15 @@ typedef struct {
 } qsim_batch_tuning;
 
 /* Set (t != NULL) or reset (NULL) the batched-mode parameters used by
- * later qsim_apply_batch calls on states of `dtype`.  Process-wide.
- * QSIM_ERR_INVALID on out-of-range values. */
+ * later qsim_apply_batch calls on states of `dtype`, or read them back.
+ * Process-wide.  QSIM_ERR_INVALID on out-of-range values.  (Launch
+ * parameters; no passage of the paper.) */
 int qsim_batch_set_tuning(qsim_dtype dtype, const qsim_batch_tuning *t);
 int qsim_batch_get_tuning(qsim_dtype dtype, qsim_batch_tuning *out);
 
 /* Shorthands for the tiles_per_item field, for both dtypes (0 restores the
- * default).  QSIM_ERR_INVALID above 256. */
+ * default).  QSIM_ERR_INVALID above 256.  (Launch parameters; no passage
+ * of the paper.) */
 int qsim_batch_set_tiles_per_item(uint32_t tiles);
 uint32_t qsim_batch_tiles_per_item(void);
 
@@ -327,7 +333,7 @@ int qsim_batch_autotune(qsim_state *const *states, const qsim_step *const *steps
  * the algorithmic bytes (one read and one write of a circuit's state per
  * pass, summed), the kernel's device time from HIP events recorded on its
  * stream, and the parameters it ran with.  QSIM_ERR_INVALID if no batch
- * has run. */
+ * has run.  (Measurement; no passage of the paper.) */
 typedef struct {
     uint32_t circuits;
     uint32_t items;
