@@ -317,9 +317,11 @@ def bench_served(n: int, rate: float, slots: int = 4, budget: float = 200e9, cal
     requests arrive at t = 0 (measures service capacity)."""
     import workloads as W
     from paper_quant_ph_0308158_amd import qsim
+    import torch
     trace = W.served_trace(n, rate)
     packed = [qsim.pack_steps(r.circuit.target, r.circuit.cmask) for r in trace]
     updates = float(sum((1 << r.circuit.M) * r.circuit.L for r in trace))
+    readback = float(sum((1 << r.circuit.M) * 8 for r in trace))   # bytes of results sent to the host
 
     def run(fcfs: bool, digest: int = 0, at_once: bool = calibrate, only=None):
         srv = qsim.Server(budget_bytes=int(budget), max_slots=slots, fcfs=fcfs, digest=digest)
@@ -347,7 +349,26 @@ def bench_served(n: int, rate: float, slots: int = 4, budget: float = 200e9, cal
         pct = lambda p: lat[min(len(lat) - 1, int(round(p / 100.0 * (len(lat) - 1))))]
         return {"p50_ms": round(pct(50), 2), "p99_ms": round(pct(99), 2), "mean_ms": round(sum(lat) / len(lat), 2),
                 "span_s": round(span, 3), "requests_per_s": round(len(infos) / span, 2),
-                "updates_per_s": updates / span}
+                "updates_per_s": updates / span, "readback_GBps": round(readback / span / 1e9, 2)}
+
+    def link_GBps():
+        """Device-to-host rate of back-to-back 2^20-row (8 MiB) portion
+        copies into pinned memory on one stream: the ceiling of the
+        read-back every request ends with."""
+        portion = 1 << 20
+        src = torch.empty(256 * portion, dtype=torch.complex64, device="cuda")
+        dst = [torch.empty(portion, dtype=torch.complex64, pin_memory=True) for _ in range(2)]
+        for k in range(4):
+            dst[k % 2].copy_(src[k * portion:(k + 1) * portion], non_blocking=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(256):
+            dst[k % 2].copy_(src[k * portion:(k + 1) * portion], non_blocking=True)
+        torch.cuda.synchronize()
+        rate = 256 * portion * 8 / (time.perf_counter() - t0) / 1e9
+        del src, dst
+        torch.cuda.empty_cache()
+        return round(rate, 1)
 
     cont = run(False)
     plain = run(True)
@@ -365,9 +386,15 @@ def bench_served(n: int, rate: float, slots: int = 4, budget: float = 200e9, cal
     check = {"requests_checked": len(picked), "mismatches": 0,
              "how": f"every {stride}th request of the trace: digest of its read-back portions with continuous "
                     f"batching equals its digest served alone"}
+    link = link_GBps()
     return {"workload": f"served_poisson_{n}req_rate{rate:g}_M12-28_L50-2000_c64", "requests": n, "check": check,
             "rate_per_s": rate, "calibration": calibrate, "slots": slots, "budget_bytes": budget,
-            "amplitude_step_updates": updates, "continuous": cont, "plain_fcfs": plain,
+            "amplitude_step_updates": updates, "readback_bytes": readback,
+            "link": {"bound": "pcie-d2h", "peak_GBps": link,
+                     "frac": round(cont["readback_GBps"] / link, 3),
+                     "how": "results read back per second of the continuous run over the device-to-host rate of "
+                            "back-to-back 8 MiB portion copies into pinned memory"},
+            "continuous": cont, "plain_fcfs": plain,
             "throughput_speedup_vs_plain": round(cont["updates_per_s"] / plain["updates_per_s"], 2),
             "p99_speedup_vs_plain": round(plain["p99_ms"] / cont["p99_ms"], 2)}
 
