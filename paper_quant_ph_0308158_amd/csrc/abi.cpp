@@ -1699,6 +1699,10 @@ bool make_product_pass(Prepared &pr, uint32_t M, uint32_t elem, const void *qubi
         if (low) break;
         --pa.cut;
     }
+    // The kernel folds the factors above the fifth lowest tile bit before
+    // splitting at the five: the top address bit must lie above it (not so
+    // only for a 2^5-entry tile that holds bit M - 1).
+    if (pa.bit[4] + 1u >= M) return false;
     l.pa = pa;
     l.product = true;
     l.q_off = blob_push(pr.blob, qubits, (size_t)4 * M * (elem / 2));

@@ -815,25 +815,54 @@ __global__ void __launch_bounds__(256) k_product(T *__restrict__ out, ProductArg
 // (2 + 4 + ... products), multiplying all partials by the factors of the
 // outside bits in between, each product rounded as in k_product.
 // pr/pi[e] is the partial whose tile bits bit[CUT + k] read bit k of e.
-template <typename T, int CUT>
-__device__ __forceinline__ void product_form(T (&pr)[32 >> CUT], T (&pi)[32 >> CUT], uint64_t src_base,
-                                             const ProductTileArgs &pa, uint32_t tb) {
-    const T *q = static_cast<const T *>(pa.q);
-    const uint32_t t = threadIdx.x;
-    uint64_t addr = src_base;   // logical address with the five lowest tile bits clear
-    for (uint32_t i = 0; i < tb; ++i) addr |= (uint64_t)((t >> i) & 1u) << pa.bit[5 + i];
+// The fold of the top address bits is shared by many threads: threads
+// whose top h = min(tb, 6) thread bits (tile bits bit[5 + tb - h] and up)
+// read u share it down to just above tile bit bit[4 + tb - h] (bit[4] when
+// h = tb).  Thread u < 2^h of the workgroup folds that prefix into LDS
+// slot u (one wave instead of all of them); every thread then continues
+// from its slot through its lower thread bits.
+__device__ __forceinline__ uint32_t prefix_bits(uint32_t tb) { return tb < 6u ? tb : 6u; }
+
+template <typename T>
+__device__ __forceinline__ void fold_down(T &re, T &im, const T *q, uint64_t addr, int hi, int lo) {
     // Factors are read at addresses that are the same for every lane (both
     // values of a bit, then a per-lane select): scalar loads, not a chain of
     // vector loads.
-    int lv = (int)pa.M - 1;
-    bool hi = (addr >> lv) & 1u;
-    T re = hi ? q[4 * lv + 2] : q[4 * lv], im = hi ? q[4 * lv + 3] : q[4 * lv + 1];
 #pragma unroll 4
-    for (--lv; lv > (int)pa.bit[4]; --lv) {
+    for (int lv = hi; lv >= lo; --lv) {
         const T c0 = q[4 * lv], d0 = q[4 * lv + 1], c1 = q[4 * lv + 2], d1 = q[4 * lv + 3];
-        hi = (addr >> lv) & 1u;
-        cmul(re, im, hi ? c1 : c0, hi ? d1 : d0);
+        const bool h = (addr >> lv) & 1u;
+        cmul(re, im, h ? c1 : c0, h ? d1 : d0);
     }
+}
+
+template <typename T>
+__device__ __forceinline__ void product_prefix(T *slots, uint64_t src_base, const ProductTileArgs &pa, uint32_t tb) {
+    const uint32_t h = prefix_bits(tb), u = threadIdx.x;
+    if (u >= (1u << h)) return;
+    const T *q = static_cast<const T *>(pa.q);
+    uint64_t addr = src_base;
+    for (uint32_t i = 0; i < h; ++i) addr |= (uint64_t)((u >> i) & 1u) << pa.bit[5 + tb - h + i];
+    const int top = (int)pa.M - 1;
+    const int lo = (int)pa.bit[4 + tb - h] + 1;   // bit[4] when h = tb
+    const bool b = (addr >> top) & 1u;
+    T re = b ? q[4 * top + 2] : q[4 * top], im = b ? q[4 * top + 3] : q[4 * top + 1];
+    fold_down(re, im, q, addr, top - 1, lo);
+    slots[2 * u] = re;
+    slots[2 * u + 1] = im;
+}
+
+template <typename T, int CUT>
+__device__ __forceinline__ void product_form(T (&pr)[32 >> CUT], T (&pi)[32 >> CUT], const T *slots,
+                                             uint64_t src_base, const ProductTileArgs &pa, uint32_t tb) {
+    const T *q = static_cast<const T *>(pa.q);
+    const uint32_t t = threadIdx.x, h = prefix_bits(tb);
+    uint64_t addr = src_base;   // logical address with the five lowest tile bits clear
+    for (uint32_t i = 0; i < tb; ++i) addr |= (uint64_t)((t >> i) & 1u) << pa.bit[5 + i];
+    const uint32_t u = t >> (tb - h);
+    T re = slots[2 * u], im = slots[2 * u + 1];
+    // the thread bits below the shared ones, and the outside bits among them
+    fold_down(re, im, q, addr, (int)pa.bit[4 + tb - h], (int)pa.bit[4] + 1);
     // Partial k covers the entries whose tile bits i..4 read k (bit 4 highest).
     pr[0] = re;
     pi[0] = im;
@@ -905,6 +934,29 @@ __device__ __forceinline__ void product_slot_planes(uint32_t (&w)[kPlanes], cons
     for (int b = 0; b < kPlanes; ++b) w[b] = s[b];
 }
 
+// The factors a CUT > 0 product pass folds in at the store, in LDS after
+// the partials: for each value c of the CUT residual bits (bit i of c =
+// address bit i), the CUT factors in fold order, q_CUT(bit CUT - 1) first.
+// One lookup by c replaces a select per factor (the pass is bound by its
+// vector instructions).
+template <int ELEM, int CUT>
+__device__ __forceinline__ size_t product_factor_offset(uint32_t tb) {
+    return (size_t)ELEM << (tb + 5 - CUT);   // bytes of the partials before it
+}
+
+template <int ELEM, int CUT>
+__device__ __forceinline__ void product_factors(vec16 *lds, const ProductTileArgs &pa, uint32_t tb) {
+    using T = typename std::conditional<ELEM == 8, float, double>::type;
+    const T *q = static_cast<const T *>(pa.q);
+    using V2 = typename std::conditional<ELEM == 8, float2, double2>::type;
+    V2 *fac = reinterpret_cast<V2 *>(reinterpret_cast<uint8_t *>(lds) + product_factor_offset<ELEM, CUT>(tb));
+    for (uint32_t t = threadIdx.x; t < (CUT << CUT); t += blockDim.x) {   // tiles may have 2 threads
+        const uint32_t c = t / CUT, j = t % CUT, bit = CUT - 1 - j, h = (c >> bit) & 1u;
+        fac[t].x = q[4 * bit + 2 * h];
+        fac[t].y = q[4 * bit + 2 * h + 1];
+    }
+}
+
 // Store the calling thread's output entries of a CUT > 0 product pass: each
 // takes its partial from the table and folds in the factors of address bits
 // CUT - 1, ..., 0 that its source index carries, then gets the pass's sign.
@@ -916,22 +968,16 @@ __device__ __forceinline__ void product_emit(const uint32_t (&w)[kPlanes], vec16
     constexpr uint32_t VPT = Shape<ELEM, 5>::VPT;
     constexpr uint32_t EPV = Shape<ELEM, 5>::EPV;
     constexpr uint32_t kSlot = (1u << (kSignPlane - CUT)) - 1u;
-    const T *q = static_cast<const T *>(pa.q);
-    T f[CUT][4];   // q_{i+1}(0) and q_{i+1}(1) of address bit i
-#pragma unroll
-    for (int i = 0; i < CUT; ++i)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) f[i][k] = q[4 * i + k];
     const V2 *tab = reinterpret_cast<const V2 *>(lds);
+    const V2 *fac =
+        reinterpret_cast<const V2 *>(reinterpret_cast<const uint8_t *>(lds) + product_factor_offset<ELEM, CUT>(a.tb));
     auto entry = [&](uint32_t v, T &re, T &im) {
         const V2 e = tab[v & kSlot];
+        const V2 *g = fac + ((v >> (kSignPlane - CUT)) & ((1u << CUT) - 1u)) * CUT;
         re = e.x;
         im = e.y;
 #pragma unroll
-        for (int i = CUT - 1; i >= 0; --i) {
-            const bool h = (v >> (kSignPlane - CUT + i)) & 1u;
-            cmul(re, im, h ? f[i][2] : f[i][0], h ? f[i][3] : f[i][1]);
-        }
+        for (int j = 0; j < CUT; ++j) cmul(re, im, g[j].x, g[j].y);
     };
 #pragma unroll
     for (uint32_t r = 0; r < VPT; ++r) {
@@ -956,12 +1002,14 @@ __device__ __forceinline__ void product_emit(const uint32_t (&w)[kPlanes], vec16
     }
 }
 
-// One source tile per workgroup: form the table (the whole tile for
-// CUT = 0), walk, gather and store like k_tile.  (Persistent workgroups
-// that formed the next whole tile while the current one's stores drained
-// were slower: 10.27 against 9.61 ms at M = 32.)  With CUT = 2 and no
-// phase steps the registers are held to what six waves per SIMD leave (six
-// 16 KiB tables per CU): 6.85 against 7.0 ms at M = 32.
+// One source tile per workgroup: the first wave folds the shared prefixes
+// while every wave walks the pass's steps; then the table (the whole tile
+// for CUT = 0) is formed and the entries gathered and stored like k_tile.
+// (Persistent workgroups that formed the next whole tile while the current
+// one's stores drained were slower: 10.27 against 9.61 ms at M = 32.)  The
+// pass is bound by its vector instructions: at M = 32 the factor lookup at
+// the store and the shared prefixes took it from 6.67 to 6.25 ms, the rate
+// of the product kernel's plain writes.
 template <int ELEM, bool SIGN, int CUT>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CUT == 2 && !SIGN ? 6 : 1)))
 k_tile_product(vec16 *__restrict__ dst, TileArgs a, ProductTileArgs pa, uint64_t n_tiles) {
@@ -970,14 +1018,20 @@ k_tile_product(vec16 *__restrict__ dst, TileArgs a, ProductTileArgs pa, uint64_t
     const uint64_t tile = xcd_tile((uint64_t)blockIdx.x, a.xcd);
     if (tile >= n_tiles) return;   // uniform over the workgroup
     const uint32_t *rec = a.rec + tile * a.rec_words;
-    {
-        T pr[32 >> CUT], pi[32 >> CUT];
-        product_form<T, CUT>(pr, pi, rec_base(rec), pa, a.tb);
-        product_stage<T, CUT>(lds, pr, pi);
-    }
+    const uint64_t src_base = rec_base(rec);
+    // LDS: the partials, 256 bytes for the factor table, the prefix slots
+    T *slots = reinterpret_cast<T *>(reinterpret_cast<uint8_t *>(lds) + product_factor_offset<ELEM, CUT>(a.tb) + 256);
+    product_prefix<T>(slots, src_base, pa, a.tb);
     uint32_t w[kPlanes];
     init_planes<ELEM, 5>(w, threadIdx.x, a.tb);
-    walk_inner<true>(w, a.inner, a.n_inner, rec + 2);
+    walk_inner<true>(w, a.inner, a.n_inner, rec + 2);   // while the first wave folds the prefixes
+    __syncthreads();
+    {
+        T pr[32 >> CUT], pi[32 >> CUT];
+        product_form<T, CUT>(pr, pi, slots, src_base, pa, a.tb);
+        product_stage<T, CUT>(lds, pr, pi);
+    }
+    if constexpr (CUT > 0) product_factors<ELEM, CUT>(lds, pa, a.tb);
     product_slot_planes<CUT>(w, pa, a.tb);
     transpose_planes(w);
     __syncthreads();
@@ -1252,7 +1306,9 @@ hipError_t launch_tile_product(uint32_t elem, void *dst, uint64_t n_tiles, const
                                const ProductTileArgs &pa, hipStream_t st) {
     const uint32_t threads = 1u << a.tb;
     if (a.eb != 5 || threads > 512u || pa.cut > 2u) return hipErrorInvalidValue;
-    const size_t lds = (size_t)elem << (a.tb + 5 - pa.cut);
+    // the partials, 256 bytes for the table of folded-in factors (CUT > 0),
+    // 64 shared prefixes
+    const size_t lds = ((size_t)elem << (a.tb + 5 - pa.cut)) + 256u + 64u * elem;
     auto go = [&](auto kern) {
         hipError_t e = allow_lds(kern, lds);
         if (e != hipSuccess) return e;
