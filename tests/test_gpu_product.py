@@ -85,6 +85,12 @@ def run_both(q, M, dt, qq, tg, cm, kd, tuning):
     (17, 17, np.complex128, {"tile_bits": 7, "low_bits": 1, "small_bits": 5, "product_stage": 3}, False),
     (18, 21, np.complex128, {"tile_bits": 13, "kernel_variant": 2, "product_stage": 3}, True),
     (19, 16, np.complex64, {"tile_bits": 14, "product_stage": 1}, False),
+    # 2^5-entry tiles (one thread): first tiles that hold the top address bit
+    # (seeds 20-22: the product kernel runs first) and one that does not
+    (20, 7, np.complex128, {"tile_bits": 5, "low_bits": 1, "small_bits": 5}, False),
+    (21, 12, np.complex128, {"tile_bits": 5, "low_bits": 1, "small_bits": 5}, True),
+    (22, 11, np.complex64, {"tile_bits": 5, "low_bits": 1, "small_bits": 5}, False),
+    (23, 6, np.complex64, {"tile_bits": 5, "low_bits": 1, "small_bits": 4}, True),
 ])
 def test_product_pass_matches_oracle(q, seed, M, dt, tuning, signed):
     rng = np.random.default_rng(900 + seed)
