@@ -2,7 +2,8 @@
 device memory) against qsim_apply_steps: the same result bit for bit, on
 two calls in a row (the second on a smaller state, so it reuses scratch the
 first one filled), on the small-state and direct paths, and a diagram whose
-plan and tile records exceed the scratch is rejected with nothing run."""
+plan and tile records exceed the scratch is rejected with nothing run; and
+the allocation-free apply captured into a HIP graph and replayed."""
 import sys
 
 import numpy as np
@@ -106,3 +107,46 @@ def test_noalloc_rejects_plan_beyond_scratch(q):
     assert s.current_ptr() == k1.data_ptr()
     assert torch.equal(k1.view(torch.int64), keep.view(torch.int64))
     s.close()
+
+
+def test_noalloc_apply_replays_in_a_graph(q):
+    """The allocation-free apply enqueues kernels only (the plan travels in
+    kernel arguments into the scratch array; no copy, fill or wait), so it
+    can be captured into a HIP graph and replayed.  Each replay applies the
+    diagram again to the buffers the capture saw; with an even number of
+    passes the result lands in the buffer the first pass reads, so replay r
+    gives U^r k1.  Every replay is checked against the eager applies, with
+    eager work and a synchronisation between replays."""
+    import torch
+    M = 20
+    tg = cm = None
+    for seed in range(100):
+        t_, c_ = W.random_steps(np.random.default_rng(3000 + seed), M, 300, (0, 3))
+        if len(q.plan_describe(M, "c64", t_, c_)[0]) % 2 == 0:
+            tg, cm = t_, c_
+            break
+    assert tg is not None
+    k1 = W.gaussian_state(np.random.default_rng(2020), M, np.complex64)
+    with q.State(M, "c64") as s:
+        s.write(k1)
+        refs = []
+        for _ in range(3):                      # eager (also resolves the scratch address)
+            s.apply_noalloc(tg, cm, stream=0)
+            refs.append(s.read())
+        assert refs[0].tobytes() == oracle.apply(M, k1, tg, cm).tobytes()
+        s.write(k1)
+        torch.cuda.synchronize()
+        say("graph capture")
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            s.apply_noalloc(tg, cm)             # on the capture stream; nothing runs yet
+        torch.cuda.synchronize()
+        for r in range(3):
+            say("graph replay", r)
+            g.replay()
+            torch.cuda.synchronize()
+            assert s.read().tobytes() == refs[r].tobytes(), f"replay {r} differs from eager apply {r + 1}"
+            x = torch.randn(1 << 16, device="cuda")   # eager work between replays
+            assert torch.isfinite(x.sum()).item()
+            torch.cuda.synchronize()
+        del g
