@@ -43,7 +43,11 @@
  * Arguments are validated completely before any device work is enqueued: on
  * QSIM_ERR_INVALID or QSIM_ERR_RANGE nothing has run and the state is
  * unchanged.  After QSIM_ERR_DEVICE the state is poisoned and every later
- * call on it returns QSIM_ERR_DEVICE.
+ * call on it returns QSIM_ERR_DEVICE.  No C++ exception leaves the
+ * library: host memory, threads or locks that cannot be had give
+ * QSIM_ERR_NOMEM (nothing enqueued, the state unchanged), or
+ * QSIM_ERR_DEVICE with the state poisoned if part of the call's device
+ * work had already been enqueued.
  *
  * Threads: one state must not be used from two threads at once; distinct
  * states are independent.
@@ -63,7 +67,7 @@ typedef enum { QSIM_C64 = 0, QSIM_C128 = 1 } qsim_dtype;
 typedef enum {
     QSIM_OK = 0,
     QSIM_ERR_INVALID = -1, /* bad argument: M, dtype, step, NULL pointer    */
-    QSIM_ERR_NOMEM = -2,   /* device allocation failed or budget exceeded   */
+    QSIM_ERR_NOMEM = -2,   /* device or host allocation failed, or budget   */
     QSIM_ERR_DEVICE = -3,  /* a HIP call failed; the state is poisoned      */
     QSIM_ERR_RANGE = -4    /* offset + count beyond 2^M                     */
 } qsim_status;

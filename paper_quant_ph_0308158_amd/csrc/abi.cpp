@@ -16,11 +16,16 @@
 #include <cmath>
 #include <new>
 #include <string>
+#include <stdexcept>
+#include <system_error>
 #include <vector>
 #include <unordered_set>
+#include <exception>
+#include <memory>
 #include <thread>
 
 #include "../../include/qsim.h"
+#include "host_threads.h"
 #include "qsim_internal.h"
 
 using namespace qsim;
@@ -40,7 +45,7 @@ int fail(int code, const std::string &msg) {
 // has succeeded, so the error handling runs while the device sees nothing
 // unusual.  Sites: "launch" (each kernel launch of an apply), "upload" (the
 // plan upload of an apply), "read" (a portion read), "batch" (a batched
-// launch).
+// launch).  A site is matched by its whole name.
 hipError_t injected(const char *site) {
     const char *v = std::getenv("QSIM_FAULT_INJECT");
     if (!v || !*v) return hipSuccess;
@@ -56,6 +61,14 @@ hipError_t injected(const char *site) {
     if (!colon || (size_t)(colon - v) != std::strlen(site) || std::strncmp(v, site, colon - v) != 0) return hipSuccess;
     const uint64_t n = std::strtoull(colon + 1, nullptr, 10);
     return ++count == n ? hipErrorUnknown : hipSuccess;
+}
+
+// The same for host exceptions: throws std::bad_alloc, as an allocation that
+// fails would, at the n-th check of `site`.  Sites: "host" (each planning of
+// a diagram, on the planning threads of a batch too), "host-launch" (after
+// each kernel launch of an apply, where a timing record would be stored).
+void injected_throw(const char *site) {
+    if (injected(site) != hipSuccess) throw std::bad_alloc();
 }
 
 std::atomic<uint64_t> g_allocated{0};
@@ -98,6 +111,7 @@ struct StepLists {
 };
 
 StepLists split_steps(const qsim_step *steps, uint64_t L) {
+    injected_throw("host");
     StepLists o;
     o.tg.resize(L);
     o.cm.resize(L);
@@ -639,7 +653,7 @@ int prepare(qsim_state *s, const qsim_step *steps, uint64_t L, Prepared &pr) {
     std::vector<Pass> passes;
     try {
         passes = plan_passes(M, sl.tg.data(), sl.cm.data(), sl.kd.data(), L, plan_config(s->tune, s->elem));
-    } catch (const std::exception &e) {
+    } catch (const std::logic_error &e) {   // (host memory and threads: host_exception)
         return fail(QSIM_ERR_INVALID, std::string("planner: ") + e.what());
     }
     return prepare_passes(M, s->elem, passes, sl.tg.data(), sl.cm.data(), sl.kd.data(), s->tune.outer_order,
@@ -695,6 +709,15 @@ hipError_t prof_collect(qsim_state *s) {
 // room for the tile records of one pass.  With `timed` the launches are
 // bracketed by profiling events when the state's profiling is on.
 int enqueue_launches(qsim_state *s, Prepared &pr, hipStream_t st, uint8_t *dev, uint32_t *rec, bool timed) {
+    // An exception from here on (a timing record that cannot be stored)
+    // leaves some of the launches enqueued: the state is poisoned.
+    struct PoisonOnThrow {
+        qsim_state *s;
+        int before = std::uncaught_exceptions();
+        ~PoisonOnThrow() {
+            if (std::uncaught_exceptions() > before) s->poisoned = true;
+        }
+    } poison_on_throw{s};
     hipError_t e;
     const bool prof = timed && s->profiling;
     const uint64_t n = 1ull << s->M;
@@ -738,6 +761,7 @@ int enqueue_launches(qsim_state *s, Prepared &pr, hipStream_t st, uint8_t *dev, 
         }
         if (e == hipSuccess) e = injected("launch");
         if (e != hipSuccess) return device_fail(s, e, "kernel launch");
+        injected_throw("host-launch");
         if (prof && (e = prof_end(s, st, kind, ev_a, kind == 1 ? 0 : pass_bytes)) != hipSuccess)
             return device_fail(s, e, "profiling event");
     }
@@ -770,6 +794,29 @@ int check_state(const qsim_state *s) {
 }
 
 }  // namespace
+
+int qsim::host_exception(qsim_state *s) noexcept {
+    int code = QSIM_ERR_INVALID;
+    char what[160] = "unknown exception";
+    try {
+        throw;
+    } catch (const std::bad_alloc &) {
+        code = QSIM_ERR_NOMEM;
+        std::snprintf(what, sizeof what, "host memory allocation failed");
+    } catch (const std::system_error &e) {   // a thread or a lock that could not be had
+        code = QSIM_ERR_NOMEM;
+        std::snprintf(what, sizeof what, "host resource: %s", e.what());
+    } catch (const std::exception &e) {
+        std::snprintf(what, sizeof what, "host: %s", e.what());
+    } catch (...) {
+    }
+    if (s && s->poisoned) code = QSIM_ERR_DEVICE;   // poisoned during this call (checked on entry)
+    try {
+        g_err = what;
+    } catch (...) {
+    }
+    return code;
+}
 
 // ------------------------------------------------------------ allocation-free apply
 
@@ -1013,14 +1060,7 @@ template <typename F>
 void host_parallel(uint32_t n, uint32_t grain, F &&fn) {
     const uint32_t hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
     const uint32_t nt = std::min<uint32_t>(hw, (n + grain - 1) / grain);
-    std::atomic<uint32_t> next{0};
-    auto worker = [&]() {
-        for (uint32_t i; (i = next.fetch_add(1)) < n;) fn(i);
-    };
-    std::vector<std::thread> pool;
-    for (uint32_t t = 1; t < nt; ++t) pool.emplace_back(worker);
-    worker();
-    for (auto &t : pool) t.join();
+    parallel_for(n, (int)nt, [&](size_t i) { fn((uint32_t)i); });
 }
 
 // Host-side buffers of batch_enqueue, kept per calling thread from one
@@ -1102,7 +1142,7 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
                 bp.rc = prepare_passes(s->M, elem, passes, sl.tg.data(), sl.cm.data(), sl.kd.data(),
                                        s->tune.outer_order, s->tune.remap, 5u, bp.pr);
                 if (bp.rc) bp.err = g_err;
-            } catch (const std::exception &e) {
+            } catch (const std::logic_error &e) {
                 bp.rc = QSIM_ERR_INVALID;
                 bp.err = std::string("planner: ") + e.what();
             }
@@ -1356,6 +1396,11 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
     if (!b.k1 && (e = hipEventCreate(&b.k1)) != hipSuccess) return fail(QSIM_ERR_DEVICE, "batch event");
     if ((e = b.ws.ensure(total)) != hipSuccess) return fail(QSIM_ERR_NOMEM, "batch workspace");
     if ((e = b.stage.ensure(total)) != hipSuccess) return fail(QSIM_ERR_DEVICE, "batch staging");
+    // passes per circuit (odd: the result is in the other buffer), counted
+    // before anything is enqueued so nothing after the launch can fail
+    std::vector<uint32_t> flips(n, 0);
+    for (size_t k = 0; k < bsmall.size(); ++k) flips[small_circuit[k]] = 1;
+    for (const BatchPass &p : bpass) flips[p.circuit] = p.level + 1;
     uint8_t *dev = static_cast<uint8_t *>(b.ws.p);
     // device pointers inside the descriptors
     for (size_t g = 0; g < bpass.size(); ++g) {
@@ -1383,16 +1428,11 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
         add(h + pass_off, bpass.data(), bpass.size() * sizeof(BatchPass));
         add(h + small_off, bsmall.data(), bsmall.size() * sizeof(BatchSmall));
         for (uint32_t c = 0; c < n; ++c) add(h + blob_off + circuit_blob_off[c], plans[c].pr.blob.data(), plans[c].pr.blob.size());
-        std::atomic<size_t> next{0};
-        auto worker = [&]() {
-            for (size_t k; (k = next.fetch_add(64)) < pieces.size();)
-                for (size_t q = k; q < std::min(k + 64, pieces.size()); ++q) std::memcpy(pieces[q].dst, pieces[q].src, pieces[q].n);
-        };
         const size_t nt = std::min<size_t>(8, std::max<size_t>(1, total >> 22));   // a thread per 4 MiB, at most 8
-        std::vector<std::thread> pool;
-        for (size_t t = 1; t < nt; ++t) pool.emplace_back(worker);
-        worker();
-        for (auto &t : pool) t.join();
+        parallel_for((pieces.size() + 63) / 64, (int)nt, [&](size_t k) {
+            for (size_t q = 64 * k; q < std::min(64 * k + 64, pieces.size()); ++q)
+                std::memcpy(pieces[q].dst, pieces[q].src, pieces[q].n);
+        });
     }
     lap("stage");
     // Upload on the side stream (after the slot's previous kernel, which
@@ -1406,6 +1446,14 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
     if ((e = hipEventRecord(b.uploaded, w.upload)) != hipSuccess) return fail(QSIM_ERR_DEVICE, "batch event");
     if ((e = hipStreamWaitEvent(st, b.uploaded, 0)) != hipSuccess) return fail(QSIM_ERR_DEVICE, "batch event");
     uint32_t *ctr_dev = reinterpret_cast<uint32_t *>(dev);
+    // From the launch on, a failure leaves the states part-way: they are
+    // poisoned, after whatever did launch has finished (so the slot can be
+    // reused).
+    auto launched_fail = [&](const char *what, hipError_t err) {
+        (void)hipStreamSynchronize(st);
+        for (uint32_t c = 0; c < n; ++c) states[c]->poisoned = true;
+        return fail(QSIM_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(err));
+    };
     b.timed = false;
     if (!items.empty()) {
         b.timed = hipEventRecord(b.k0, st) == hipSuccess;
@@ -1414,17 +1462,12 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
                          reinterpret_cast<const uint64_t *>(dev + items_off), (uint32_t)items.size(), ctr_dev,
                          1u << 24, tpi, rec_stride, lds, st);
         if (e == hipSuccess) e = injected("batch");
-        if (e != hipSuccess) {
-            // whatever did launch finishes before the slot can be reused
-            (void)hipStreamSynchronize(st);
-            for (uint32_t c = 0; c < n; ++c) states[c]->poisoned = true;
-            return fail(QSIM_ERR_DEVICE, std::string("batch launch: ") + hipGetErrorString(e));
-        }
+        if (e != hipSuccess) return launched_fail("batch launch", e);
         b.timed = b.timed && hipEventRecord(b.k1, st) == hipSuccess;
     }
     if ((e = hipMemcpyAsync(b.hdr, ctr_dev, kBatchCtrHeader * 4, hipMemcpyDeviceToHost, st)) != hipSuccess)
-        return fail(QSIM_ERR_DEVICE, std::string("batch status copy: ") + hipGetErrorString(e));
-    if ((e = hipEventRecord(b.done, st)) != hipSuccess) return fail(QSIM_ERR_DEVICE, "batch event");
+        return launched_fail("batch status copy", e);
+    if ((e = hipEventRecord(b.done, st)) != hipSuccess) return launched_fail("batch event", e);
     b.pending = true;
     b.info = qsim_batch_info{};
     b.info.circuits = n;
@@ -1437,9 +1480,6 @@ int batch_enqueue(qsim_state *const *states, const qsim_step *const *steps, cons
     w.next ^= 1;
     lap("launch");
     // every circuit's result sits in the buffer its last pass wrote
-    std::vector<uint32_t> flips(n, 0);
-    for (size_t k = 0; k < bsmall.size(); ++k) flips[small_circuit[k]] = 1;
-    for (const BatchPass &p : bpass) flips[p.circuit] = p.level + 1;
     for (uint32_t c = 0; c < n; ++c) {
         states[c]->cur ^= (int)(flips[c] & 1u);
         states[c]->last_stream = st;
@@ -1469,7 +1509,7 @@ int qsim::state_rebind(qsim_state *s, uint32_t M, int dtype, void *buf0, void *b
 
 extern "C" {
 
-qsim_state *qsim_state_create(uint32_t M, qsim_dtype dtype) {
+qsim_state *qsim_state_create(uint32_t M, qsim_dtype dtype) try {
     const uint32_t elem = elem_of(dtype);
     if (elem == 0) { fail(QSIM_ERR_INVALID, "dtype must be QSIM_C64 or QSIM_C128"); return nullptr; }
     if (M < 1 || M > QSIM_MAX_M) { fail(QSIM_ERR_INVALID, "M out of range [1, 36]"); return nullptr; }
@@ -1503,9 +1543,12 @@ qsim_state *qsim_state_create(uint32_t M, qsim_dtype dtype) {
     s->owned = true;
     g_allocated += 2 * bytes;
     return s;
+} catch (...) {
+    (void)host_exception(nullptr);
+    return nullptr;
 }
 
-qsim_state *qsim_state_wrap(uint32_t M, qsim_dtype dtype, void *buf0, void *buf1) {
+qsim_state *qsim_state_wrap(uint32_t M, qsim_dtype dtype, void *buf0, void *buf1) try {
     const uint32_t elem = elem_of(dtype);
     if (elem == 0) { fail(QSIM_ERR_INVALID, "dtype must be QSIM_C64 or QSIM_C128"); return nullptr; }
     if (M < 1 || M > QSIM_MAX_M) { fail(QSIM_ERR_INVALID, "M out of range [1, 36]"); return nullptr; }
@@ -1529,9 +1572,12 @@ qsim_state *qsim_state_wrap(uint32_t M, qsim_dtype dtype, void *buf0, void *buf1
     s->buf[1] = buf1;
     s->owned = false;
     return s;
+} catch (...) {
+    (void)host_exception(nullptr);
+    return nullptr;
 }
 
-void qsim_state_destroy(qsim_state *s) {
+void qsim_state_destroy(qsim_state *s) try {
     if (!s) return;
     DeviceGuard g(s->device);
     (void)hipStreamSynchronize(s->last_stream);
@@ -1547,6 +1593,8 @@ void qsim_state_destroy(qsim_state *s) {
         g_allocated -= 2 * ((uint64_t)s->elem << s->M);
     }
     delete s;
+} catch (...) {
+    (void)host_exception(nullptr);
 }
 
 uint32_t qsim_state_qubits(const qsim_state *s) { return s ? s->M : 0; }
@@ -1554,7 +1602,7 @@ uint32_t qsim_state_elem_bytes(const qsim_state *s) { return s ? s->elem : 0; }
 
 const void *qsim_state_current(const qsim_state *s) { return s ? s->buf[s->cur] : nullptr; }
 
-int qsim_write_portion(qsim_state *s, uint64_t offset, uint64_t count, const void *host_src) {
+int qsim_write_portion(qsim_state *s, uint64_t offset, uint64_t count, const void *host_src) try {
     int rc = check_state(s);
     if (rc) return rc;
     const uint64_t n = 1ull << s->M;
@@ -1568,9 +1616,11 @@ int qsim_write_portion(qsim_state *s, uint64_t offset, uint64_t count, const voi
                   hipMemcpyHostToDevice);
     if (e != hipSuccess) return device_fail(s, e, "write portion");
     return QSIM_OK;
+} catch (...) {
+    return host_exception(s);
 }
 
-int qsim_state_set_product(qsim_state *s, const void *qubits, void *hip_stream) {
+int qsim_state_set_product(qsim_state *s, const void *qubits, void *hip_stream) try {
     int rc = check_state(s);
     if (rc) return rc;
     if (!qubits) return fail(QSIM_ERR_INVALID, "qubits is NULL");
@@ -1580,9 +1630,11 @@ int qsim_state_set_product(qsim_state *s, const void *qubits, void *hip_stream) 
     if (e != hipSuccess) return device_fail(s, e, "product-state launch");
     s->last_stream = st;
     return QSIM_OK;
+} catch (...) {
+    return host_exception(s);
 }
 
-int qsim_rowmap_build(uint32_t M, const qsim_step *steps, uint64_t L, uint32_t *x_dev, void *hip_stream) {
+int qsim_rowmap_build(uint32_t M, const qsim_step *steps, uint64_t L, uint32_t *x_dev, void *hip_stream) try {
     if (M < 1 || M > 32) return fail(QSIM_ERR_INVALID, "qsim_rowmap_build needs 1 <= M <= 32");
     if (!x_dev) return fail(QSIM_ERR_INVALID, "x_dev is NULL");
     int rc = validate_steps(M, steps, L);
@@ -1593,6 +1645,7 @@ int qsim_rowmap_build(uint32_t M, const qsim_step *steps, uint64_t L, uint32_t *
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     qsim_state *tmp = qsim_state_create(M, QSIM_C64);
     if (!tmp) return QSIM_ERR_NOMEM;
+    std::unique_ptr<qsim_state, void (*)(qsim_state *)> hold(tmp, qsim_state_destroy);
     const uint64_t n = 1ull << M;
     hipError_t e = launch_iota(static_cast<uint64_t *>(tmp->buf[0]), n, st);
     if (e != hipSuccess) rc = device_fail(tmp, e, "rowmap iota");
@@ -1602,13 +1655,17 @@ int qsim_rowmap_build(uint32_t M, const qsim_step *steps, uint64_t L, uint32_t *
         if (e != hipSuccess) rc = device_fail(tmp, e, "rowmap narrow");
     }
     if (!rc && (e = hipStreamSynchronize(st)) != hipSuccess) rc = device_fail(tmp, e, "rowmap synchronize");
-    const std::string msg = g_err;
-    qsim_state_destroy(tmp);
-    if (rc) g_err = msg;
+    if (rc) {
+        const std::string msg = g_err;   // (kept across the destroy)
+        hold.reset();
+        g_err = msg;
+    }
     return rc;
+} catch (...) {
+    return host_exception(nullptr);
 }
 
-int qsim_rowmap_apply(qsim_state *s, const uint32_t *x_dev, void *hip_stream) {
+int qsim_rowmap_apply(qsim_state *s, const uint32_t *x_dev, void *hip_stream) try {
     int rc = check_state(s);
     if (rc) return rc;
     if (!x_dev) return fail(QSIM_ERR_INVALID, "x_dev is NULL");
@@ -1620,9 +1677,11 @@ int qsim_rowmap_apply(qsim_state *s, const uint32_t *x_dev, void *hip_stream) {
     s->cur ^= 1;
     s->last_stream = st;
     return QSIM_OK;
+} catch (...) {
+    return host_exception(s);
 }
 
-int qsim_apply_steps(qsim_state *s, const qsim_step *steps, uint64_t L, void *hip_stream) {
+int qsim_apply_steps(qsim_state *s, const qsim_step *steps, uint64_t L, void *hip_stream) try {
     int rc = check_state(s);
     if (rc) return rc;
     if ((rc = validate_steps(s->M, steps, L))) return rc;
@@ -1632,9 +1691,11 @@ int qsim_apply_steps(qsim_state *s, const qsim_step *steps, uint64_t L, void *hi
     DeviceGuard g(s->device);
     if (!g.ok) return device_fail(s, hipErrorInvalidDevice, "set device");
     return enqueue(s, pr, static_cast<hipStream_t>(hip_stream));
+} catch (...) {
+    return host_exception(s);
 }
 
-int qsim_apply_steps_noalloc(qsim_state *s, const qsim_step *steps, uint64_t L, void *hip_stream) {
+int qsim_apply_steps_noalloc(qsim_state *s, const qsim_step *steps, uint64_t L, void *hip_stream) try {
     int rc = check_state(s);
     if (rc) return rc;
     if ((rc = validate_steps(s->M, steps, L))) return rc;
@@ -1659,6 +1720,8 @@ int qsim_apply_steps_noalloc(qsim_state *s, const qsim_step *steps, uint64_t L, 
         return device_fail(s, e, "plan upload");
     uint8_t *dev = static_cast<uint8_t *>(base);
     return enqueue_launches(s, pr, st, dev, reinterpret_cast<uint32_t *>(dev + pr.blob.size()), false);
+} catch (...) {
+    return host_exception(s);
 }
 
 namespace {
@@ -1712,7 +1775,7 @@ bool make_product_pass(Prepared &pr, uint32_t M, uint32_t elem, const void *qubi
 }  // namespace
 
 int qsim_apply_steps_product(qsim_state *s, const void *qubits, const qsim_step *steps, uint64_t L,
-                             void *hip_stream) {
+                             void *hip_stream) try {
     int rc = check_state(s);
     if (rc) return rc;
     if (!qubits) return fail(QSIM_ERR_INVALID, "qubits is NULL");
@@ -1726,9 +1789,11 @@ int qsim_apply_steps_product(qsim_state *s, const void *qubits, const qsim_step 
     // Small states and plans that start otherwise: the product kernel, then the diagram.
     if ((rc = qsim_state_set_product(s, qubits, hip_stream))) return rc;
     return L > 0 ? enqueue(s, pr, st) : QSIM_OK;
+} catch (...) {
+    return host_exception(s);
 }
 
-int qsim_apply_tile_pass(qsim_state *s, uint64_t tile_mask, const qsim_step *steps, uint64_t L, void *hip_stream) {
+int qsim_apply_tile_pass(qsim_state *s, uint64_t tile_mask, const qsim_step *steps, uint64_t L, void *hip_stream) try {
     int rc = check_state(s);
     if (rc) return rc;
     if ((rc = validate_steps(s->M, steps, L))) return rc;
@@ -1752,9 +1817,11 @@ int qsim_apply_tile_pass(qsim_state *s, uint64_t tile_mask, const qsim_step *ste
     DeviceGuard g(s->device);
     if (!g.ok) return device_fail(s, hipErrorInvalidDevice, "set device");
     return enqueue(s, pr, static_cast<hipStream_t>(hip_stream));
+} catch (...) {
+    return host_exception(s);
 }
 
-int qsim_apply_steps_plain(qsim_state *s, const qsim_step *steps, uint64_t L, void *hip_stream) {
+int qsim_apply_steps_plain(qsim_state *s, const qsim_step *steps, uint64_t L, void *hip_stream) try {
     int rc = check_state(s);
     if (rc) return rc;
     if ((rc = validate_steps(s->M, steps, L))) return rc;
@@ -1787,9 +1854,11 @@ int qsim_apply_steps_plain(qsim_state *s, const qsim_step *steps, uint64_t L, vo
     }
     s->last_stream = st;
     return QSIM_OK;
+} catch (...) {
+    return host_exception(s);
 }
 
-int qsim_read_portion(const qsim_state *cs, uint64_t offset, uint64_t count, void *host_dst) {
+int qsim_read_portion(const qsim_state *cs, uint64_t offset, uint64_t count, void *host_dst) try {
     qsim_state *s = const_cast<qsim_state *>(cs);
     int rc = check_state(s);
     if (rc) return rc;
@@ -1805,10 +1874,12 @@ int qsim_read_portion(const qsim_state *cs, uint64_t offset, uint64_t count, voi
     if (e == hipSuccess) e = injected("read");
     if (e != hipSuccess) return device_fail(s, e, "read portion");
     return QSIM_OK;
+} catch (...) {
+    return host_exception(nullptr);
 }
 
 int qsim_read_portion_async(const qsim_state *cs, uint64_t offset, uint64_t count, void *host_dst,
-                            void *hip_stream) {
+                            void *hip_stream) try {
     qsim_state *s = const_cast<qsim_state *>(cs);
     int rc = check_state(s);
     if (rc) return rc;
@@ -1822,10 +1893,12 @@ int qsim_read_portion_async(const qsim_state *cs, uint64_t offset, uint64_t coun
                                   count * s->elem, hipMemcpyDeviceToHost, st);
     if (e != hipSuccess) return device_fail(s, e, "read portion");
     return QSIM_OK;
+} catch (...) {
+    return host_exception(nullptr);
 }
 
 int qsim_apply_batch(qsim_state *const *states, const qsim_step *const *steps, const uint64_t *Ls, uint32_t n,
-                     void *hip_stream) {
+                     void *hip_stream) try {
     if (n == 0) return QSIM_OK;
     if (!states || !steps || !Ls) return fail(QSIM_ERR_INVALID, "NULL array");
     std::unordered_set<const qsim_state *> seen;
@@ -1842,13 +1915,17 @@ int qsim_apply_batch(qsim_state *const *states, const qsim_step *const *steps, c
     DeviceGuard g(states[0]->device);
     if (!g.ok) return fail(QSIM_ERR_DEVICE, "set device");
     return batch_enqueue(states, steps, Ls, n, static_cast<hipStream_t>(hip_stream));
+} catch (...) {
+    return host_exception(nullptr);
 }
 
-int qsim_batch_last_status(void) {
+int qsim_batch_last_status(void) try {
     return batch_status();
+} catch (...) {
+    return host_exception(nullptr);
 }
 
-int qsim_batch_set_tuning(qsim_dtype dtype, const qsim_batch_tuning *t) {
+int qsim_batch_set_tuning(qsim_dtype dtype, const qsim_batch_tuning *t) try {
     const uint32_t elem = elem_of(dtype);
     if (!elem) return fail(QSIM_ERR_INVALID, "dtype must be QSIM_C64 or QSIM_C128");
     BatchTune bt;
@@ -1860,9 +1937,11 @@ int qsim_batch_set_tuning(qsim_dtype dtype, const qsim_batch_tuning *t) {
     std::lock_guard<std::mutex> lk(w.mu);
     w.tune[elem == 8 ? 0 : 1] = bt;
     return QSIM_OK;
+} catch (...) {
+    return host_exception(nullptr);
 }
 
-int qsim_batch_get_tuning(qsim_dtype dtype, qsim_batch_tuning *out) {
+int qsim_batch_get_tuning(qsim_dtype dtype, qsim_batch_tuning *out) try {
     const uint32_t elem = elem_of(dtype);
     if (!elem) return fail(QSIM_ERR_INVALID, "dtype must be QSIM_C64 or QSIM_C128");
     if (!out) return fail(QSIM_ERR_INVALID, "out is NULL");
@@ -1870,15 +1949,19 @@ int qsim_batch_get_tuning(qsim_dtype dtype, qsim_batch_tuning *out) {
     std::lock_guard<std::mutex> lk(w.mu);
     export_batch_tune(w.tune[elem == 8 ? 0 : 1], elem, out);
     return QSIM_OK;
+} catch (...) {
+    return host_exception(nullptr);
 }
 
-int qsim_batch_set_tiles_per_item(uint32_t tiles) {
+int qsim_batch_set_tiles_per_item(uint32_t tiles) try {
     if (tiles == 0) tiles = BatchTune{}.tiles_per_item;
     if (tiles > kBatchTilesMax) return fail(QSIM_ERR_INVALID, "tiles_per_item above 256");
     BatchWorkspace &w = batch_ws();
     std::lock_guard<std::mutex> lk(w.mu);
     for (BatchTune &t : w.tune) t.tiles_per_item = tiles;
     return QSIM_OK;
+} catch (...) {
+    return host_exception(nullptr);
 }
 
 uint32_t qsim_batch_tiles_per_item(void) {
@@ -1887,7 +1970,7 @@ uint32_t qsim_batch_tiles_per_item(void) {
     return w.tune[0].tiles_per_item;
 }
 
-int qsim_batch_last_info(qsim_batch_info *out) {
+int qsim_batch_last_info(qsim_batch_info *out) try {
     if (!out) return fail(QSIM_ERR_INVALID, "out is NULL");
     BatchWorkspace &w = batch_ws();
     std::lock_guard<std::mutex> lk(w.mu);
@@ -1895,6 +1978,8 @@ int qsim_batch_last_info(qsim_batch_info *out) {
     batch_collect(w, w.slot[w.last]);
     *out = w.slot[w.last].info;
     return QSIM_OK;
+} catch (...) {
+    return host_exception(nullptr);
 }
 
 }  // extern "C"
@@ -2031,7 +2116,7 @@ std::string batch_cache_key(int device, uint32_t elem, qsim_state *const *states
 extern "C" {
 
 int qsim_batch_autotune(qsim_state *const *states, const qsim_step *const *steps, const uint64_t *Ls, uint32_t n,
-                        void *hip_stream, qsim_batch_tuning *out) {
+                        void *hip_stream, qsim_batch_tuning *out) try {
     if (n == 0) return out ? qsim_batch_get_tuning(QSIM_C64, out) : QSIM_OK;
     if (!states || !steps || !Ls) return fail(QSIM_ERR_INVALID, "NULL array");
     for (uint32_t c = 0; c < n; ++c) {
@@ -2162,9 +2247,11 @@ int qsim_batch_autotune(qsim_state *const *states, const qsim_step *const *steps
         out->default_ms = (float)default_ms;
     }
     return QSIM_OK;
+} catch (...) {
+    return host_exception(nullptr);
 }
 
-int qsim_autotune(qsim_state *s, const qsim_step *steps, uint64_t L, void *hip_stream, qsim_tuning *out) {
+int qsim_autotune(qsim_state *s, const qsim_step *steps, uint64_t L, void *hip_stream, qsim_tuning *out) try {
     int rc = check_state(s);
     if (rc) return rc;
     if ((rc = validate_steps(s->M, steps, L))) return rc;
@@ -2248,20 +2335,24 @@ int qsim_autotune(qsim_state *s, const qsim_step *steps, uint64_t L, void *hip_s
     if (rc) return rc;
     export_tuning(best);
     return QSIM_OK;
+} catch (...) {
+    return host_exception(s);
 }
 
-int qsim_state_set_tuning(qsim_state *s, const qsim_tuning *tuning) {
+int qsim_state_set_tuning(qsim_state *s, const qsim_tuning *tuning) try {
     int rc = check_state(s);
     if (rc) return rc;
     Tuning t;
     if ((rc = tuning_from(tuning, s->elem, &t))) return rc;
     s->tune = t;
     return QSIM_OK;
+} catch (...) {
+    return host_exception(s);
 }
 
 int qsim_plan_describe(uint32_t M, qsim_dtype dtype, const qsim_step *steps, uint64_t L,
                        const qsim_tuning *tuning, uint32_t *n_passes, uint64_t *pass_mask, uint32_t *pass_len,
-                       uint32_t cap, uint32_t *order) {
+                       uint32_t cap, uint32_t *order) try {
     const uint32_t elem = elem_of(dtype);
     if (elem == 0) return fail(QSIM_ERR_INVALID, "dtype must be QSIM_C64 or QSIM_C128");
     if (M < 1 || M > QSIM_MAX_M) return fail(QSIM_ERR_INVALID, "M out of range [1, 36]");
@@ -2273,7 +2364,7 @@ int qsim_plan_describe(uint32_t M, qsim_dtype dtype, const qsim_step *steps, uin
     std::vector<Pass> passes;
     try {
         passes = plan_passes(M, sl.tg.data(), sl.cm.data(), sl.kd.data(), L, plan_config(t, elem));
-    } catch (const std::exception &e) {
+    } catch (const std::logic_error &e) {   // (host memory and threads: host_exception)
         return fail(QSIM_ERR_INVALID, std::string("planner: ") + e.what());
     }
     if (n_passes) *n_passes = (uint32_t)passes.size();
@@ -2287,9 +2378,11 @@ int qsim_plan_describe(uint32_t M, qsim_dtype dtype, const qsim_step *steps, uin
             if (order) order[k++] = s;
     }
     return QSIM_OK;
+} catch (...) {
+    return host_exception(nullptr);
 }
 
-int qsim_state_profile(qsim_state *s, int enable) {
+int qsim_state_profile(qsim_state *s, int enable) try {
     int rc = check_state(s);
     if (rc) return rc;
     DeviceGuard g(s->device);
@@ -2298,9 +2391,11 @@ int qsim_state_profile(qsim_state *s, int enable) {
     s->profiling = enable != 0;
     if (enable) s->prof = qsim_profile{};
     return QSIM_OK;
+} catch (...) {
+    return host_exception(s);
 }
 
-int qsim_state_profile_read(qsim_state *s, qsim_profile *out) {
+int qsim_state_profile_read(qsim_state *s, qsim_profile *out) try {
     int rc = check_state(s);
     if (rc) return rc;
     if (!out) return fail(QSIM_ERR_INVALID, "out is NULL");
@@ -2309,15 +2404,19 @@ int qsim_state_profile_read(qsim_state *s, qsim_profile *out) {
     if (e != hipSuccess) return device_fail(s, e, "profiling");
     *out = s->prof;
     return QSIM_OK;
+} catch (...) {
+    return host_exception(s);
 }
 
-int qsim_copy_bytes(void *dst, const void *src, uint64_t bytes, void *hip_stream) {
+int qsim_copy_bytes(void *dst, const void *src, uint64_t bytes, void *hip_stream) try {
     if (!dst || !src) return fail(QSIM_ERR_INVALID, "NULL pointer");
     if ((bytes & 15u) || (((uintptr_t)dst | (uintptr_t)src) & 15u))
         return fail(QSIM_ERR_INVALID, "size and pointers must be multiples of 16");
     hipError_t e = launch_copy(dst, src, bytes, static_cast<hipStream_t>(hip_stream));
     if (e != hipSuccess) return fail(QSIM_ERR_DEVICE, std::string("copy launch: ") + hipGetErrorString(e));
     return QSIM_OK;
+} catch (...) {
+    return host_exception(nullptr);
 }
 
 const char *qsim_last_error(void) { return g_err.c_str(); }

@@ -33,6 +33,7 @@
 #include <stdexcept>
 #include <thread>
 
+#include "host_threads.h"
 #include "planner.h"
 
 namespace qsim {
@@ -305,25 +306,6 @@ uint64_t splitmix64(uint64_t &x) {
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     return z ^ (z >> 31);
-}
-
-// f(0) .. f(n-1) on up to `threads` threads (the calling one included),
-// each taking the next index as it becomes free.
-template <typename F>
-void parallel_for(size_t n, int threads, F &&f) {
-    const size_t nt = std::min<size_t>(n, (size_t)std::max(threads, 1));
-    if (nt <= 1) {
-        for (size_t k = 0; k < n; ++k) f(k);
-        return;
-    }
-    std::atomic<size_t> next{0};
-    auto run = [&] {
-        for (size_t k; (k = next.fetch_add(1)) < n;) f(k);
-    };
-    std::vector<std::thread> pool;
-    for (size_t t = 1; t < nt; ++t) pool.emplace_back(run);
-    run();
-    for (auto &th : pool) th.join();
 }
 
 }  // namespace

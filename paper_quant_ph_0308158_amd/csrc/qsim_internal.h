@@ -142,6 +142,13 @@ namespace qsim {
 // earlier work.  For the serving workers, which reuse one state per slot.
 int state_rebind(qsim_state *s, uint32_t M, int dtype, void *buf0, void *buf1);
 
+// Called in a catch (...) of an exported function: the error code for the
+// exception being handled (QSIM_ERR_NOMEM for host memory, threads or
+// locks that could not be had, QSIM_ERR_INVALID for any other, and
+// QSIM_ERR_DEVICE if `s` was poisoned part-way through the call), with its
+// message stored for qsim_last_error.  No exception crosses the C boundary.
+int host_exception(qsim_state *s) noexcept;
+
 // Kernel launchers (kernels.hip).  All return hipSuccess or the launch error.
 hipError_t launch_direct(uint32_t elem, const void *src, void *dst, uint64_t n,
                          const TmStep *steps_rev, uint32_t L, hipStream_t st);

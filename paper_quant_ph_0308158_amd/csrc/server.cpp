@@ -333,12 +333,26 @@ qsim_server *qsim_server_create(const qsim_server_config *cfg) {
         return nullptr;
     }
     const uint32_t nworkers = c.fcfs ? 1u : c.max_slots;
-    for (uint32_t i = 0; i < nworkers; ++i) s->workers.emplace_back(&qsim_server::worker_main, s, i);
+    try {
+        s->workers.reserve(nworkers);
+        for (uint32_t i = 0; i < nworkers; ++i) s->workers.emplace_back(&qsim_server::worker_main, s, i);
+    } catch (...) {
+        // a worker that cannot be started: stop the ones that did
+        (void)qsim::host_exception(nullptr);
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->stopping = true;
+        }
+        s->cv_work.notify_all();
+        for (auto &t : s->workers) t.join();
+        delete s;
+        return nullptr;
+    }
     return s;
 }
 
 int64_t qsim_server_submit(qsim_server *srv, uint32_t M, qsim_dtype dtype, const void *host_k1,
-                           const qsim_step *steps, uint64_t L) {
+                           const qsim_step *steps, uint64_t L) try {
     if (!srv) return QSIM_ERR_INVALID;
     const uint32_t elem = dtype == QSIM_C64 ? 8u : (dtype == QSIM_C128 ? 16u : 0u);
     if (!elem || M < 1 || M > QSIM_MAX_M) return QSIM_ERR_INVALID;
@@ -361,32 +375,44 @@ int64_t qsim_server_submit(qsim_server *srv, uint32_t M, qsim_dtype dtype, const
     r->steps.assign(steps, steps + L);
     r->info.t_submit_ns = now_ns();
     std::lock_guard<std::mutex> lk(srv->mu);
-    r->id = srv->next_id++;
-    srv->all[r->id] = r;
+    r->id = srv->next_id;
     srv->queue.push_back(r);
+    try {
+        srv->all[r->id] = r;
+    } catch (...) {
+        srv->queue.pop_back();   // (a request that cannot be recorded is not queued)
+        throw;
+    }
+    ++srv->next_id;
     ++srv->outstanding;
     srv->admit_locked();
     return r->id;
+} catch (...) {
+    return qsim::host_exception(nullptr);
 }
 
-int qsim_server_drain(qsim_server *srv) {
+int qsim_server_drain(qsim_server *srv) try {
     if (!srv) return QSIM_ERR_INVALID;
     std::unique_lock<std::mutex> lk(srv->mu);
     srv->cv_done.wait(lk, [&] { return srv->outstanding == 0; });
     return QSIM_OK;
+} catch (...) {
+    return qsim::host_exception(nullptr);
 }
 
-int qsim_server_request_info(qsim_server *srv, int64_t id, qsim_request_info *out) {
+int qsim_server_request_info(qsim_server *srv, int64_t id, qsim_request_info *out) try {
     if (!srv || !out) return QSIM_ERR_INVALID;
     std::lock_guard<std::mutex> lk(srv->mu);
     auto it = srv->all.find(id);
     if (it == srv->all.end()) return QSIM_ERR_RANGE;
     *out = it->second->info;
     return QSIM_OK;
+} catch (...) {
+    return qsim::host_exception(nullptr);
 }
 
 int qsim_server_stats(qsim_server *srv, uint64_t *arena_bytes, uint64_t *arena_used, uint32_t *queued,
-                      uint32_t *running) {
+                      uint32_t *running) try {
     if (!srv) return QSIM_ERR_INVALID;
     std::lock_guard<std::mutex> lk(srv->mu);
     if (arena_bytes) *arena_bytes = srv->arena.size();
@@ -394,9 +420,11 @@ int qsim_server_stats(qsim_server *srv, uint64_t *arena_bytes, uint64_t *arena_u
     if (queued) *queued = (uint32_t)srv->queue.size();
     if (running) *running = srv->busy_slots + (uint32_t)srv->admitted.size();
     return QSIM_OK;
+} catch (...) {
+    return qsim::host_exception(nullptr);
 }
 
-void qsim_server_destroy(qsim_server *srv) {
+void qsim_server_destroy(qsim_server *srv) try {
     if (!srv) return;
     {
         std::unique_lock<std::mutex> lk(srv->mu);
@@ -406,6 +434,8 @@ void qsim_server_destroy(qsim_server *srv) {
     srv->cv_work.notify_all();
     for (auto &t : srv->workers) t.join();
     delete srv;
+} catch (...) {
+    (void)qsim::host_exception(nullptr);
 }
 
 }  // extern "C"

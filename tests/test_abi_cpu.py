@@ -419,3 +419,21 @@ def test_batch_tuning_setting():
     assert qsim.batch_get_tuning("c64") == default
     with pytest.raises(qsim.QsimError):
         qsim.batch_last_info()            # no batch has run in this process
+
+
+def test_host_exception_becomes_an_error_code(monkeypatch):
+    """A C++ exception on the host (here a failed allocation, forced with
+    QSIM_FAULT_INJECT) ends at the C boundary as QSIM_ERR_NOMEM with a
+    message, and the next call runs normally."""
+    rng = np.random.default_rng(8200)
+    tg, cm = W.random_steps(rng, 20, 300, (0, 3))
+    want = qsim.plan_describe(20, "c64", tg, cm, {"tile_bits": 10, "small_bits": 5})
+    monkeypatch.setenv("QSIM_FAULT_INJECT", "host:1")
+    with pytest.raises(qsim.QsimError) as ei:
+        qsim.plan_describe(20, "c64", tg, cm, {"tile_bits": 10, "small_bits": 5})
+    assert ei.value.code == qsim.ERR_NOMEM
+    assert "host memory allocation failed" in qsim.last_error()
+    monkeypatch.delenv("QSIM_FAULT_INJECT")
+    got = qsim.plan_describe(20, "c64", tg, cm, {"tile_bits": 10, "small_bits": 5})
+    for a, b in zip(want, got):
+        assert np.array_equal(a, b)

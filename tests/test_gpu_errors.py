@@ -2,7 +2,10 @@
 the HBM budget turns state creation into QSIM_ERR_NOMEM, and
 QSIM_FAULT_INJECT makes a chosen HIP call report an error after it has
 succeeded, which must poison the state so every later call on it returns
-QSIM_ERR_DEVICE while other states keep working."""
+QSIM_ERR_DEVICE while other states keep working.  The same variable makes
+the host throw as a failed allocation would: before anything is enqueued
+that is QSIM_ERR_NOMEM with the states untouched, after a launch of the
+call it poisons the state like a device error."""
 import sys
 
 import numpy as np
@@ -54,7 +57,7 @@ def _poisoned(q, s, tg, cm):
     _expect(q, q.ERR_DEVICE, s.write, np.zeros(s.n, dtype=np.complex64))
 
 
-@pytest.mark.parametrize("site", ["launch:3", "upload:1"])
+@pytest.mark.parametrize("site", ["launch:3", "upload:1", "host-launch:2"])
 def test_injected_apply_error_poisons_state(q, monkeypatch, site):
     rng = np.random.default_rng(8100)
     M = 19
@@ -114,5 +117,46 @@ def test_injected_batch_error_poisons_its_states(q, monkeypatch):
     q.apply_batch(fresh, steps, stream=0)
     q.batch_status()
     for c, s, k1 in zip(circuits, fresh, ins):
+        assert s.read().tobytes() == oracle.apply(c.M, k1, c.target, c.cmask).tobytes()
+        s.close()
+
+
+def test_host_exception_before_enqueue_leaves_states(q, monkeypatch):
+    """A host exception while planning (on the calling thread for an apply,
+    on a planning thread for a batch) returns QSIM_ERR_NOMEM with nothing
+    enqueued: the states keep their contents and work afterwards."""
+    rng = np.random.default_rng(8104)
+    M = 17
+    tg, cm = W.random_steps(rng, M, 150, (0, 3))
+    k1 = W.gaussian_state(rng, M, np.complex64)
+    with q.State(M, "c64") as s:
+        s.set_tuning({"tile_bits": 10, "small_bits": 5})
+        s.write(k1)
+        say("inject host:1 (apply)")
+        monkeypatch.setenv("QSIM_FAULT_INJECT", "host:1")
+        _expect(q, q.ERR_NOMEM, s.apply, tg, cm, stream=0)
+        monkeypatch.delenv("QSIM_FAULT_INJECT")
+        assert s.read().tobytes() == k1.tobytes()
+        s.apply(tg, cm, stream=0)
+        assert s.read().tobytes() == oracle.apply(M, k1, tg, cm).tobytes()
+
+    circuits = W.batched_config(n=200, seed=8105, m_range=(14, 16), l_range=(20, 60))
+    ins = [W.gaussian_state(rng, c.M, np.complex64) for c in circuits]
+    states = []
+    for c, k1 in zip(circuits, ins):
+        s = q.State(c.M, "c64")
+        s.write(k1)
+        states.append(s)
+    steps = [(c.target, c.cmask) for c in circuits]
+    say("inject host:7 (batch planning thread)")
+    monkeypatch.setenv("QSIM_FAULT_INJECT", "host:7")
+    _expect(q, q.ERR_NOMEM, q.apply_batch, states, steps, stream=0)
+    monkeypatch.delenv("QSIM_FAULT_INJECT")
+    q.batch_status()
+    for s, k1 in zip(states, ins):
+        assert s.read().tobytes() == k1.tobytes()
+    q.apply_batch(states, steps, stream=0)
+    q.batch_status()
+    for c, s, k1 in zip(circuits, states, ins):
         assert s.read().tobytes() == oracle.apply(c.M, k1, c.target, c.cmask).tobytes()
         s.close()
