@@ -513,7 +513,11 @@ int qsim_apply_tile_pass(qsim_state *state, uint64_t tile_mask,
  * its own inverse, Sec. 2(a)); the state's contents are unchanged on
  * return.  The fastest candidate becomes the state's tuning and is copied
  * to *out (may be NULL).  States small enough for one workgroup have
- * nothing to choose.  Synchronous. */
+ * nothing to choose.  When the environment variable QSIM_TUNING_CACHE
+ * names a file, the choice is looked up there first under (device
+ * architecture, dtype, M, band of L between powers of two) and, if found
+ * and valid, taken without measuring; a measured choice is stored there
+ * (the file is shared with qsim_batch_autotune).  Synchronous. */
 int qsim_autotune(qsim_state *state, const qsim_step *steps, uint64_t L,
                   void *hip_stream, qsim_tuning *out);
 

@@ -175,6 +175,26 @@ Tuning default_tuning(uint32_t elem) {
     return t;
 }
 
+// The external form of a tuning (every field set).
+void export_tuning_to(const Tuning &t, qsim_tuning *out) {
+    std::memset(out, 0, sizeof(*out));
+    out->tile_bits = (uint32_t)t.tile_bits;
+    out->low_bits = (uint32_t)t.low_bits;
+    out->max_seg_steps = (uint32_t)t.max_seg_steps;
+    out->reorder = t.reorder ? 1u : 2u;
+    out->small_bits = (uint32_t)t.small_bits;
+    out->kernel_variant = t.variant + 1;
+    out->wg_per_cu = t.wg_per_cu;
+    out->outer_order = t.outer_order + 1;
+    out->remap = t.remap ? 1u : 2u;
+    out->mid_low_bits = (uint32_t)t.mid_low_bits;
+    out->min_overlap = (uint32_t)t.min_overlap;
+    out->rows_per_thread = 1u << t.rows_eb;
+    out->plan_search = t.plan_search < 0 ? 0u : (uint32_t)t.plan_search + 1u;
+    out->xcd_swizzle = t.xcd_swizzle ? 2u : 1u;
+    out->product_stage = t.product_cut + 1u;
+}
+
 int tuning_from(const qsim_tuning *in, uint32_t elem, Tuning *out) {
     Tuning t = default_tuning(elem);
     if (in) {
@@ -1986,11 +2006,13 @@ int qsim_batch_last_info(qsim_batch_info *out) try {
 
 namespace {
 
-// ---- tuning cache of qsim_batch_autotune (QSIM_TUNING_CACHE): a JSON
-// object {"qsim_batch_tuning": {"<key>": {"<field>": <number>, ...}, ...}}
-// that this library writes and reads back.
+// ---- tuning cache of qsim_autotune and qsim_batch_autotune
+// (QSIM_TUNING_CACHE): a JSON object {"<section>": {"<key>": {"<field>":
+// <number>, ...}, ...}, ...} that this library writes and reads back, with
+// the sections "qsim_tuning" (one state) and "qsim_batch_tuning".
 
 using CacheMap = std::map<std::string, std::map<std::string, double>>;
+using CacheFile = std::map<std::string, CacheMap>;
 
 struct JsonIn {
     const char *p, *end;
@@ -2024,17 +2046,18 @@ struct JsonIn {
     }
 };
 
-bool parse_cache(const std::string &text, CacheMap &out) {
+bool parse_cache(const std::string &text, CacheFile &out) {
     JsonIn in{text.data(), text.data() + text.size()};
     std::string top, key, field;
     if (!in.lit('{')) return false;
     if (in.lit('}')) return true;
     do {
-        if (!in.str(top) || !in.lit(':') || top != "qsim_batch_tuning" || !in.lit('{')) return false;
+        if (!in.str(top) || !in.lit(':') || !in.lit('{')) return false;
+        CacheMap &section = out[top];
         if (in.lit('}')) continue;
         do {
             if (!in.str(key) || !in.lit(':') || !in.lit('{')) return false;
-            auto &entry = out[key];
+            auto &entry = section[key];
             if (in.lit('}')) continue;
             do {
                 double v = 0;
@@ -2048,23 +2071,29 @@ bool parse_cache(const std::string &text, CacheMap &out) {
     return in.lit('}');
 }
 
-std::string write_cache(const CacheMap &m) {
-    std::string o = "{\n  \"qsim_batch_tuning\": {";
-    bool first = true;
+std::string write_cache(const CacheFile &file) {
+    std::string o = "{";
     char buf[64];
-    for (const auto &kv : m) {
-        o += first ? "\n    \"" : ",\n    \"";
-        first = false;
-        o += kv.first + "\": {";
-        bool f2 = true;
-        for (const auto &fv : kv.second) {
-            std::snprintf(buf, sizeof buf, "%.6g", fv.second);
-            o += (f2 ? "\"" : ", \"") + fv.first + "\": " + buf;
-            f2 = false;
+    bool first_section = true;
+    for (const auto &sec : file) {
+        o += (first_section ? "\n  \"" : ",\n  \"") + sec.first + "\": {";
+        first_section = false;
+        bool first = true;
+        for (const auto &kv : sec.second) {
+            o += first ? "\n    \"" : ",\n    \"";
+            first = false;
+            o += kv.first + "\": {";
+            bool f2 = true;
+            for (const auto &fv : kv.second) {
+                std::snprintf(buf, sizeof buf, "%.6g", fv.second);
+                o += (f2 ? "\"" : ", \"") + fv.first + "\": " + buf;
+                f2 = false;
+            }
+            o += "}";
         }
-        o += "}";
+        o += "\n  }";
     }
-    return o + "\n  }\n}\n";
+    return o + "\n}\n";
 }
 
 bool read_file(const char *path, std::string &out) {
@@ -2087,15 +2116,35 @@ bool write_file(const char *path, const std::string &text) {
     return std::rename(tmp.c_str(), path) == 0;
 }
 
-// Cache key of a batch: device architecture, dtype, range of M and range
-// of L rounded out to powers of two.
-std::string batch_cache_key(int device, uint32_t elem, qsim_state *const *states, const uint64_t *Ls, uint32_t n) {
+// The cache file named by QSIM_TUNING_CACHE, if any: false (and nothing
+// read) when it is set but unreadable as a cache; a missing file is an
+// empty cache, to be written.
+bool load_cache(const char *path, CacheFile &out) {
+    std::string text;
+    return !read_file(path, text) || parse_cache(text, out);
+}
+
+std::string device_arch(int device) {
     hipDeviceProp_t prop{};
     std::string arch = "unknown";
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
         arch = prop.gcnArchName;
         arch = arch.substr(0, arch.find(':'));
     }
+    return arch;
+}
+
+// Powers of two around [lo, hi]: "L<p>-<q>" with p <= lo (0 for lo = 0) and q >= hi.
+std::string l_band(uint64_t lo, uint64_t hi) {
+    uint64_t plo = 0, phi = 1;
+    if (lo > 0) for (plo = 1; plo * 2 <= lo; plo *= 2) {}
+    while (phi < hi) phi *= 2;
+    return "L" + std::to_string(plo) + "-" + std::to_string(phi);
+}
+
+// Cache key of a batch: device architecture, dtype, range of M and range
+// of L rounded out to powers of two.
+std::string batch_cache_key(int device, uint32_t elem, qsim_state *const *states, const uint64_t *Ls, uint32_t n) {
     uint32_t mlo = 64, mhi = 0;
     uint64_t llo = ~0ull, lhi = 0;
     for (uint32_t c = 0; c < n; ++c) {
@@ -2104,11 +2153,8 @@ std::string batch_cache_key(int device, uint32_t elem, qsim_state *const *states
         llo = std::min(llo, Ls[c]);
         lhi = std::max(lhi, Ls[c]);
     }
-    uint64_t plo = 0, phi = 1;
-    if (llo > 0) for (plo = 1; plo * 2 <= llo; plo *= 2) {}
-    while (phi < lhi) phi *= 2;
-    return arch + ":" + (elem == 8 ? "c64" : "c128") + ":M" + std::to_string(mlo) + "-" + std::to_string(mhi) + ":L" +
-           std::to_string(plo) + "-" + std::to_string(phi);
+    return device_arch(device) + ":" + (elem == 8 ? "c64" : "c128") + ":M" + std::to_string(mlo) + "-" +
+           std::to_string(mhi) + ":" + l_band(llo, lhi);
 }
 
 }  // namespace
@@ -2133,11 +2179,11 @@ int qsim_batch_autotune(qsim_state *const *states, const qsim_step *const *steps
     };
     const char *cache_path = std::getenv("QSIM_TUNING_CACHE");
     const std::string key = batch_cache_key(states[0]->device, elem, states, Ls, n);
-    CacheMap cache;
+    CacheFile cache_file;
+    CacheMap &cache = cache_file["qsim_batch_tuning"];
     bool cache_ok = false;
     if (cache_path && *cache_path) {
-        std::string text;
-        cache_ok = !read_file(cache_path, text) || parse_cache(text, cache);   // no file yet: start one
+        cache_ok = load_cache(cache_path, cache_file);
         auto it = cache.find(key);
         if (cache_ok && it != cache.end()) {
             qsim_batch_tuning in{};
@@ -2239,7 +2285,7 @@ int qsim_batch_autotune(qsim_state *const *states, const qsim_step *const *steps
         e["order"] = best.order;
         e["best_ms"] = best_ms;
         e["default_ms"] = default_ms;
-        (void)write_file(cache_path, write_cache(cache));   // a cache that cannot be written is skipped
+        (void)write_file(cache_path, write_cache(cache_file));   // a cache that cannot be written is skipped
     }
     if (out) {
         export_batch_tune(best, elem, out);
@@ -2257,27 +2303,40 @@ int qsim_autotune(qsim_state *s, const qsim_step *steps, uint64_t L, void *hip_s
     if ((rc = validate_steps(s->M, steps, L))) return rc;
     const Tuning keep = s->tune;
     auto export_tuning = [&](const Tuning &t) {
-        if (!out) return;
-        std::memset(out, 0, sizeof(*out));
-        out->tile_bits = (uint32_t)t.tile_bits;
-        out->low_bits = (uint32_t)t.low_bits;
-        out->max_seg_steps = (uint32_t)t.max_seg_steps;
-        out->reorder = t.reorder ? 1u : 2u;
-        out->small_bits = (uint32_t)t.small_bits;
-        out->kernel_variant = t.variant + 1;
-        out->wg_per_cu = t.wg_per_cu;
-        out->outer_order = t.outer_order + 1;
-        out->remap = t.remap ? 1u : 2u;
-        out->mid_low_bits = (uint32_t)t.mid_low_bits;
-        out->min_overlap = (uint32_t)t.min_overlap;
-        out->rows_per_thread = 1u << t.rows_eb;
-        out->plan_search = t.plan_search < 0 ? 0u : (uint32_t)t.plan_search + 1u;
-        out->xcd_swizzle = t.xcd_swizzle ? 2u : 1u;
-        out->product_stage = t.product_cut + 1u;
+        if (out) export_tuning_to(t, out);
     };
     if (L == 0 || (int)s->M <= s->tune.small_bits) {   // one launch: nothing to choose
         export_tuning(s->tune);
         return QSIM_OK;
+    }
+    // A choice stored for this architecture, dtype, M and band of L (the
+    // fields the candidates below vary, on top of the state's tuning).
+    const char *cache_path = std::getenv("QSIM_TUNING_CACHE");
+    const std::string key = device_arch(s->device) + ":" + (s->elem == 8 ? "c64" : "c128") + ":M" +
+                            std::to_string(s->M) + ":" + l_band(L, L);
+    CacheFile cache_file;
+    CacheMap &cache = cache_file["qsim_tuning"];
+    const bool cache_ok = cache_path && *cache_path && load_cache(cache_path, cache_file);
+    if (cache_ok) {
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            qsim_tuning in{};
+            export_tuning_to(keep, &in);
+            auto get = [&](const char *f, uint32_t dflt) {
+                auto x = it->second.find(f);
+                return x == it->second.end() ? dflt : (uint32_t)x->second;
+            };
+            in.tile_bits = get("tile_bits", in.tile_bits);
+            in.kernel_variant = get("kernel_variant", in.kernel_variant);
+            in.mid_low_bits = get("mid_low_bits", in.mid_low_bits);
+            in.plan_search = get("plan_search", in.plan_search);
+            Tuning t;
+            if (tuning_from(&in, s->elem, &t) == QSIM_OK) {   // (an entry out of range is measured again)
+                s->tune = t;
+                export_tuning(t);
+                return QSIM_OK;
+            }
+        }
     }
     // Candidates around the measured defaults: tile size, kernel shape and
     // the low bits of the middle passes.
@@ -2300,7 +2359,7 @@ int qsim_autotune(qsim_state *s, const qsim_step *steps, uint64_t L, void *hip_s
         return device_fail(s, hipErrorOutOfMemory, "autotune events");
     // Each candidate applies the diagram (timed) and then its reverse, which
     // undoes it (every step is its own inverse), so the state is unchanged.
-    float best_ms = 0.f;
+    float best_ms = 0.f, first_ms = 0.f;
     Tuning best = keep;
     bool first = true;
     for (const Cand &c : cands) {
@@ -2322,6 +2381,7 @@ int qsim_autotune(qsim_state *s, const qsim_step *steps, uint64_t L, void *hip_s
         (void)hipEventElapsedTime(&ms, e0, e1);
         // the state now holds U k1; applying the reversed list undoes it
         if ((rc = qsim_apply_steps(s, rev.data(), L, st))) break;
+        if (first) first_ms = ms;
         if (first || ms < best_ms) {
             best_ms = ms;
             best = t;
@@ -2333,6 +2393,18 @@ int qsim_autotune(qsim_state *s, const qsim_step *steps, uint64_t L, void *hip_s
     (void)hipEventDestroy(e1);
     s->tune = rc ? keep : best;
     if (rc) return rc;
+    if (cache_ok) {
+        qsim_tuning ext{};
+        export_tuning_to(best, &ext);
+        auto &e = cache[key];
+        e["tile_bits"] = ext.tile_bits;
+        e["kernel_variant"] = ext.kernel_variant;
+        e["mid_low_bits"] = ext.mid_low_bits;
+        e["plan_search"] = ext.plan_search;
+        e["best_ms"] = best_ms;
+        e["default_ms"] = first_ms;
+        (void)write_file(cache_path, write_cache(cache_file));   // a cache that cannot be written is skipped
+    }
     export_tuning(best);
     return QSIM_OK;
 } catch (...) {

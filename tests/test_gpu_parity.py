@@ -514,6 +514,49 @@ def test_autotune_keeps_state_and_result(q):
             assert_same(s.read(), oracle.apply(M, k1, tg, cm), "apply with the tuned parameters")
 
 
+def test_autotune_cache(q, tmp_path, monkeypatch):
+    """With QSIM_TUNING_CACHE set, qsim_autotune stores its choice under
+    (architecture, dtype, M, band of L) and a later call takes it from
+    there without measuring; an entry the library would reject is measured
+    again and overwritten.  Every tuning gives the oracle's result."""
+    import json
+    rng = np.random.default_rng(52)
+    M = 18
+    tg, cm = W.random_steps(rng, M, 150, (0, 3))
+    k1 = W.gaussian_state(rng, M, np.complex64)
+    cache = tmp_path / "tuning.json"
+    monkeypatch.setenv("QSIM_TUNING_CACHE", str(cache))
+    with q.State(M, "c64") as s:
+        s.write(k1)
+        say("autotune with cache")
+        t = s.autotune(tg, cm, stream=0)
+        assert_same(s.read(), k1, "state after autotune")
+        entries = json.loads(cache.read_text())["qsim_tuning"]
+        (key, entry), = entries.items()
+        assert key.endswith(":c64:M18:L128-256"), key
+        assert all(entry[f] == t[f] for f in ("tile_bits", "kernel_variant", "mid_low_bits", "plan_search"))
+        assert entry["best_ms"] > 0 and entry["best_ms"] <= entry["default_ms"]
+    # a stored choice the measurement would not have made is taken as it is
+    entry.update({"tile_bits": 10, "kernel_variant": 2, "mid_low_bits": 1, "plan_search": 2})
+    cache.write_text(json.dumps({"qsim_tuning": {key: entry}}))
+    with q.State(M, "c64") as s:
+        s.write(k1)
+        t = s.autotune(tg, cm, stream=0)
+        assert (t["tile_bits"], t["kernel_variant"], t["mid_low_bits"], t["plan_search"]) == (10, 2, 1, 2)
+        s.apply(tg, cm, stream=0)
+        assert_same(s.read(), oracle.apply(M, k1, tg, cm), "apply with the cached tuning")
+    # an entry out of range is measured again
+    entry["tile_bits"] = 99
+    cache.write_text(json.dumps({"qsim_tuning": {key: entry}}))
+    with q.State(M, "c64") as s:
+        s.write(k1)
+        t = s.autotune(tg, cm, stream=0)
+        assert t["tile_bits"] in (12, 13, 14)
+        assert json.loads(cache.read_text())["qsim_tuning"][key]["tile_bits"] == t["tile_bits"]
+        s.apply(tg, cm, stream=0)
+        assert_same(s.read(), oracle.apply(M, k1, tg, cm), "apply after re-measuring")
+
+
 def test_copy_bytes(q):
     """qsim_copy_bytes (the achievable-bandwidth reference of the benchmark)
     copies every byte, for sizes that leave a partial last workgroup."""
