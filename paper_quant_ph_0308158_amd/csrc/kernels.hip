@@ -1064,18 +1064,30 @@ __global__ void __launch_bounds__(256) k_narrow(const uint64_t *__restrict__ in,
 // k2(i) = k1(x(i)) (Sec. 2(b) end, Summary of Method last bullet).  Every
 // access is non-temporal: nothing is read twice (at M = 32 114.1 against
 // 118.4 ms with ordinary accesses; the random reads fetch a whole 128-byte
-// line per row either way).
+// line per row either way).  Each thread takes two adjacent rows and the
+// launch covers the rows once: a grid-stride loop keeps the workgroups in
+// flight on regions gigabytes apart (110.0 against 114.0 ms at M = 32).
+// n is a power of two of at least 2.
 template <int ELEM>
 __global__ void __launch_bounds__(256) k_gather(const uint8_t *__restrict__ src, uint8_t *__restrict__ dst,
                                                 const uint32_t *__restrict__ x, uint64_t n) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const uint64_t j = __builtin_nontemporal_load(x + i) & (n - 1);   // n is a power of two: stays in the state
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; 2 * p < n; p += stride) {
+        const uint64_t i = 2 * p;
+        const uint64_t j0 = __builtin_nontemporal_load(x + i) & (n - 1);   // stays in the state
+        const uint64_t j1 = __builtin_nontemporal_load(x + i + 1) & (n - 1);
         if (ELEM == 8) {
-            const uint64_t v = __builtin_nontemporal_load(reinterpret_cast<const uint64_t *>(src) + j);
-            __builtin_nontemporal_store(v, reinterpret_cast<uint64_t *>(dst) + i);
+            const uint64_t *s = reinterpret_cast<const uint64_t *>(src);
+            uint64_t *d = reinterpret_cast<uint64_t *>(dst);
+            const uint64_t v0 = __builtin_nontemporal_load(s + j0), v1 = __builtin_nontemporal_load(s + j1);
+            __builtin_nontemporal_store(v0, d + i);
+            __builtin_nontemporal_store(v1, d + i + 1);
         } else {
-            st_nt(reinterpret_cast<vec16 *>(dst) + i, ld_nt(reinterpret_cast<const vec16 *>(src) + j));
+            const vec16 *s = reinterpret_cast<const vec16 *>(src);
+            vec16 *d = reinterpret_cast<vec16 *>(dst);
+            const vec16 v0 = ld_nt(s + j0), v1 = ld_nt(s + j1);
+            st_nt(d + i, v0);
+            st_nt(d + i + 1, v1);
         }
     }
 }
@@ -1341,7 +1353,9 @@ hipError_t launch_narrow(const uint64_t *in, uint32_t *out, uint64_t n, hipStrea
 }
 
 hipError_t launch_gather(uint32_t elem, const void *src, void *dst, const uint32_t *x, uint64_t n, hipStream_t st) {
-    const dim3 grid(stride_grid(n));
+    if (n < 2 || (n & (n - 1))) return hipErrorInvalidValue;
+    // one thread per pair of rows, at most 2^31 threads (2^32 rows)
+    const dim3 grid((uint32_t)std::min<uint64_t>((n / 2 + 255) / 256, 1ull << 23));
     if (elem == 8)
         hipLaunchKernelGGL(k_gather<8>, grid, dim3(256), 0, st, (const uint8_t *)src, (uint8_t *)dst, x, n);
     else
