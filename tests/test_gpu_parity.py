@@ -481,8 +481,9 @@ def test_rowmap_build_and_apply(q):
     qsim_rowmap_apply equals applying the diagram."""
     import torch
     rng = np.random.default_rng(41)
-    for M, dt in ((3, np.complex64), (12, np.complex128), (18, np.complex64), (20, np.complex128)):
-        tg, cm = W.random_steps(rng, M, 150, (0, 3))
+    for M, dt in ((1, np.complex128), (2, np.complex64), (3, np.complex64), (12, np.complex128),
+                  (18, np.complex64), (20, np.complex128)):
+        tg, cm = W.random_steps(rng, M, 150 if M > 2 else 9, (0, 3))
         x = torch.empty(1 << M, dtype=torch.int32, device="cuda")
         say("rowmap", M)
         q.rowmap_build(M, tg, cm, x)

@@ -28,7 +28,7 @@ def diagrams(draw, min_M=2, max_M=12, max_L=64):
     M = draw(st.integers(min_M, max_M))
     L = draw(st.integers(0, max_L))
     region = draw(st.sampled_from(["all", "low", "high"]))
-    lo, hi = {"all": (0, M), "low": (0, max(2, M // 2)), "high": (M // 2, M)}[region]
+    lo, hi = {"all": (0, M), "low": (0, min(M, max(2, M // 2))), "high": (M // 2, M)}[region]
     if hi - lo < 2:
         lo, hi = 0, M
     tg = np.zeros(L, dtype=np.uint32)
@@ -147,5 +147,42 @@ def test_library_matches_oracle_property(q):
             got = s.read()
         ref = oracle.apply(M, oracle.product_state(M, qq), tg, cm, kind=kd)
         assert got.tobytes() == ref.tobytes()
+
+    check()
+
+
+@pytest.mark.gpu
+def test_batch_matches_oracle_property(q):
+    """Random batches (1..10 circuits of M = 1..15, L = 0..48, each circuit's
+    steps on all, low or high bits) under random batched-mode settings, so
+    that one batch mixes per-row circuits, circuits whole in LDS, whole
+    multi-pass circuits and tile blocks: every circuit equals the oracle."""
+
+    @settings(max_examples=40, **SETTINGS)
+    @given(st.lists(diagrams(min_M=1, max_M=15, max_L=48), min_size=1, max_size=10),
+           st.sampled_from(["c64", "c128"]), st.integers(10, 13), st.sampled_from([1, 2, 4, 8, 32]),
+           st.sampled_from([1, 2, 64]), st.sampled_from([1, 2]), st.integers(0, 2**31))
+    def check(batch, code, tile_bits, tpi, ctiles, order, seed):
+        dt = np.complex64 if code == "c64" else np.complex128
+        tuning = {"tile_bits": min(tile_bits, 13 if code == "c64" else 12), "tiles_per_item": tpi,
+                  "circuit_tiles": ctiles, "order": order}
+        rng = np.random.default_rng(seed)
+        states, ins = [], []
+        try:
+            for M, tg, cm, kd in batch:
+                k1 = W.gaussian_state(rng, M, dt)
+                s = q.State(M, code)
+                s.write(k1)
+                states.append(s)
+                ins.append(k1)
+            q.batch_set_tuning(code, tuning)
+            q.apply_batch(states, [(tg, cm, kd) for _, tg, cm, kd in batch], stream=0)
+            q.batch_status()
+            for (M, tg, cm, kd), s, k1 in zip(batch, states, ins):
+                assert s.read().tobytes() == oracle.apply(M, k1, tg, cm, kind=kd).tobytes(), (M, len(tg), tuning)
+        finally:
+            q.batch_set_tuning(code, None)
+            for s in states:
+                s.close()
 
     check()
