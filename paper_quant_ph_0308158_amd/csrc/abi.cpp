@@ -24,6 +24,8 @@
 #include <memory>
 #include <thread>
 
+#include <unistd.h>
+
 #include "../../include/qsim.h"
 #include "host_threads.h"
 #include "qsim_internal.h"
@@ -2108,7 +2110,9 @@ bool read_file(const char *path, std::string &out) {
 }
 
 bool write_file(const char *path, const std::string &text) {
-    const std::string tmp = std::string(path) + ".tmp";
+    // written beside it under a name of this process, then renamed over it:
+    // readers see the old file or the new one, never a part of either
+    const std::string tmp = std::string(path) + "." + std::to_string((long)getpid()) + ".tmp";
     FILE *f = std::fopen(tmp.c_str(), "wb");
     if (!f) return false;
     const bool ok = std::fwrite(text.data(), 1, text.size(), f) == text.size();
@@ -2219,6 +2223,19 @@ int qsim_batch_autotune(qsim_state *const *states, const qsim_step *const *steps
         std::lock_guard<std::mutex> lk(w.mu);
         keep = w.tune[di];
     }
+    // an exception part-way leaves the setting the call found
+    struct RestoreOnThrow {
+        BatchWorkspace &w;
+        int di;
+        BatchTune keep;
+        int before = std::uncaught_exceptions();
+        ~RestoreOnThrow() {
+            if (std::uncaught_exceptions() > before) {
+                std::lock_guard<std::mutex> lk(w.mu);
+                w.tune[di] = keep;
+            }
+        }
+    } restore_on_throw{w, di, keep};
     // A trial's cost is the time per batch of a long run of batches: the
     // host plans the next batch while the device runs the current one, so
     // it is the larger of the kernel's device time and the host's enqueue
@@ -2354,7 +2371,20 @@ int qsim_autotune(qsim_state *s, const qsim_step *steps, uint64_t L, void *hip_s
     std::reverse(rev.begin(), rev.end());
     DeviceGuard g(s->device);
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    hipEvent_t e0 = nullptr, e1 = nullptr;
+    // the events are released however the function ends, and an exception
+    // part-way leaves the state with the tuning it came with
+    struct Scope {
+        qsim_state *s;
+        Tuning keep;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        int before = std::uncaught_exceptions();
+        ~Scope() {
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+            if (std::uncaught_exceptions() > before) s->tune = keep;
+        }
+    } scope{s, keep};
+    hipEvent_t &e0 = scope.e0, &e1 = scope.e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return device_fail(s, hipErrorOutOfMemory, "autotune events");
     // Each candidate applies the diagram (timed) and then its reverse, which
@@ -2389,8 +2419,6 @@ int qsim_autotune(qsim_state *s, const qsim_step *steps, uint64_t L, void *hip_s
         }
     }
     (void)hipStreamSynchronize(st);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     s->tune = rc ? keep : best;
     if (rc) return rc;
     if (cache_ok) {
