@@ -121,7 +121,7 @@ def test_library_matches_oracle_property(q):
     state and on a product state formed inside the first pass, against the
     oracle bit for bit."""
 
-    @settings(max_examples=80, **SETTINGS)
+    @settings(max_examples=200, **SETTINGS)
     @given(diagrams(), st.sampled_from([np.complex64, np.complex128]), st.data(),
            st.integers(1, 5), st.integers(0, 2**31))
     def check(d, dt, data, low_bits, seed):
@@ -158,7 +158,7 @@ def test_batch_matches_oracle_property(q):
     that one batch mixes per-row circuits, circuits whole in LDS, whole
     multi-pass circuits and tile blocks: every circuit equals the oracle."""
 
-    @settings(max_examples=40, **SETTINGS)
+    @settings(max_examples=100, **SETTINGS)
     @given(st.lists(diagrams(min_M=1, max_M=15, max_L=48), min_size=1, max_size=10),
            st.sampled_from(["c64", "c128"]), st.integers(10, 13), st.sampled_from([1, 2, 4, 8, 32]),
            st.sampled_from([1, 2, 64]), st.sampled_from([1, 2]), st.integers(0, 2**31))
