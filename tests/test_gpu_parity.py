@@ -673,6 +673,46 @@ def test_batch_invalid_step_runs_nothing(q):
         s.close()
 
 
+def test_m32_complex128_sampled(q):
+    """M=32 complex128 (64 GiB per buffer, byte offsets up to 2^36, 2^20
+    tiles of 2^12 entries per pass): the headline diagram, sampled rows
+    (including the first and last and those around 2^31) against the
+    oracle's source rows, then the involution."""
+    import torch
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()          # 128 GiB of buffers: return what earlier tests cached
+    M = 32
+    tg, cm = W.m32_config()
+    say("m32 c128: generate")
+    k1_dev = W.gaussian_state_torch(M, "c128", seed=3232)
+    rng = np.random.default_rng(3232)
+    rows = np.concatenate([rng.integers(0, 1 << M, size=1500, dtype=np.uint64),
+                           np.arange(32, dtype=np.uint64), (1 << M) - 1 - np.arange(32, dtype=np.uint64),
+                           (1 << 31) + np.arange(-16, 16, dtype=np.int64).astype(np.uint64)])
+    src_rows = np.array([oracle.source_index(M, tg, cm, int(i)) for i in rows], dtype=np.int64)
+    words = lambda t: t.view(torch.int64).view(-1, 2)
+    expect = words(k1_dev)[torch.from_numpy(src_rows).cuda()].cpu().numpy()
+    b1 = torch.empty_like(k1_dev)
+    s = q.State(M, "c128", buffers=(k1_dev, b1))
+    say("m32 c128: apply")
+    s.apply(tg, cm)
+    torch.cuda.synchronize()
+    cur = k1_dev if s.current_ptr() == k1_dev.data_ptr() else b1
+    got = words(cur)[torch.from_numpy(rows.astype(np.int64)).cuda()].cpu().numpy()
+    np.testing.assert_array_equal(got, expect)
+    say("m32 c128: involution")
+    s.apply(tg[::-1].copy(), cm[::-1].copy())
+    torch.cuda.synchronize()
+    cur = k1_dev if s.current_ptr() == k1_dev.data_ptr() else b1
+    s.close()
+    del b1
+    k1_again = W.gaussian_state_torch(M, "c128", seed=3232)
+    same = torch.equal(cur.view(torch.int64), k1_again.view(torch.int64))
+    del k1_again, cur, k1_dev
+    torch.cuda.empty_cache()
+    assert same
+
+
 def test_m33_sampled_beyond_2_32_rows(q):
     """M=33 complex64 (2^33 rows, 64 GiB per buffer): row addresses and
     outer tile bits above bit 32.  Sampled rows (including the first and
