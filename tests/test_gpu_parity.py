@@ -752,43 +752,47 @@ def test_m33_sampled_beyond_2_32_rows(q):
     assert same
 
 
-def test_m34_largest_state_sampled(q):
-    """M=34 complex64, the largest state one MI355X holds out of place (two
-    128 GiB buffers): sampled rows (the first and last, those around 2^32
-    and 2^33, and random ones) against the oracle's source rows; then the
-    reversed diagram, after which other sampled rows hold their original
-    values (no second copy of the state fits beside the two buffers)."""
+@pytest.mark.parametrize("M,code", [(34, "c64"), (33, "c128")])
+def test_largest_states_sampled(q, M, code):
+    """The largest states one MI355X holds out of place (two 128 GiB
+    buffers): M=34 complex64 and M=33 complex128.  Sampled rows (the first
+    and last, those around 2^32 and 2^33, and random ones) against the
+    oracle's source rows; then the reversed diagram, after which other
+    sampled rows hold their original values (no second copy of the state
+    fits beside the two buffers)."""
     import torch
     torch.cuda.synchronize()
     torch.cuda.empty_cache()          # 256 GiB of buffers: return what earlier tests cached
-    M = 34
-    tg, cm = W.m32_config(M=34, seed=34)
-    say("m34: generate")
-    k1_dev = W.gaussian_state_torch(M, "c64", seed=34)
-    rng = np.random.default_rng(3434)
+    tg, cm = W.m32_config(M=M, seed=M)
+    say(f"M={M} {code}: generate")
+    k1_dev = W.gaussian_state_torch(M, code, seed=M)
+    rng = np.random.default_rng(100 * M + len(code))
     edges = np.concatenate([np.arange(32), (1 << M) - 1 - np.arange(32),
-                            (1 << 32) + np.arange(-16, 16), (1 << 33) + np.arange(-16, 16)]).astype(np.uint64)
+                            (1 << 32) + np.arange(-16, 16), (1 << (M - 1)) + np.arange(-16, 16)]).astype(np.uint64)
     rows = np.concatenate([rng.integers(0, 1 << M, size=1500, dtype=np.uint64), edges])
     src_rows = np.array([oracle.source_index(M, tg, cm, int(i)) for i in rows], dtype=np.int64)
-    assert (src_rows >= (1 << 33)).any() and (src_rows < (1 << 32)).any()
-    words = k1_dev.view(torch.int64)
+    assert int(rows.max()) < (1 << M) and 0 <= int(src_rows.min()) and int(src_rows.max()) < (1 << M)
+    assert (src_rows >= (1 << (M - 1))).any() and (src_rows < (1 << 32)).any()
+    per = 1 if code == "c64" else 2          # 64-bit words per entry
+    words = k1_dev.view(torch.int64).view(-1, per)
     expect = words[torch.from_numpy(src_rows).cuda()].cpu().numpy()
-    back_rows = torch.from_numpy(np.concatenate([rng.integers(0, 1 << M, size=1500, dtype=np.uint64),
-                                                 edges]).astype(np.int64)).cuda()
+    back = np.concatenate([rng.integers(0, 1 << M, size=1500, dtype=np.uint64), edges])
+    assert int(back.max()) < (1 << M)
+    back_rows = torch.from_numpy(back.astype(np.int64)).cuda()
     before = words[back_rows].cpu().numpy()
     b1 = torch.empty_like(k1_dev)
-    s = q.State(M, "c64", buffers=(k1_dev, b1))
-    say("m34: apply")
+    s = q.State(M, code, buffers=(k1_dev, b1))
+    say(f"M={M} {code}: apply")
     s.apply(tg, cm)
     torch.cuda.synchronize()
     cur = k1_dev if s.current_ptr() == k1_dev.data_ptr() else b1
-    got = cur.view(torch.int64)[torch.from_numpy(rows.astype(np.int64)).cuda()].cpu().numpy()
+    got = cur.view(torch.int64).view(-1, per)[torch.from_numpy(rows.astype(np.int64)).cuda()].cpu().numpy()
     np.testing.assert_array_equal(got, expect)
-    say("m34: reversed diagram")
+    say(f"M={M} {code}: reversed diagram")
     s.apply(tg[::-1].copy(), cm[::-1].copy())
     torch.cuda.synchronize()
     cur = k1_dev if s.current_ptr() == k1_dev.data_ptr() else b1
-    after = cur.view(torch.int64)[back_rows].cpu().numpy()
+    after = cur.view(torch.int64).view(-1, per)[back_rows].cpu().numpy()
     s.close()
     del b1, cur, k1_dev, words
     torch.cuda.empty_cache()
